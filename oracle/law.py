@@ -1,0 +1,33 @@
+"""The current-voltage relation (test infrastructure only).
+
+Eq. 1: e = rho(|j|) j with rho(|j|) = (e0/jc) |j/jc|^(n-1).  In the
+dimensionless variables of Eq. 8 (e' = e/e0, j' = j/jc) this is
+    e' = |j'|^(n-1) j'.
+With a local critical-density map kappa = jc(x)/jc_ref (an extension the
+paper allows: "a different relation can also be employed"):
+    e' = (|j'|/kappa)^(n-1) j'/kappa.
+Outside the superconductor the fictitious Ohm law e = rho_out j is used
+(the iteration paragraph of Sec. 2).  The oracle evaluates the plain
+definition with a power; the GPU path uses a log form, and tests compare.
+"""
+import numpy as np
+
+
+def power_law(j, n, kappa=None):
+    """e' = (|j'|/kappa)^(n-1) j'/kappa, pointwise, e'(0) = 0."""
+    j = np.asarray(j, dtype=np.float64)
+    a = np.sqrt(j[0] ** 2 + j[1] ** 2 + j[2] ** 2)
+    if kappa is None:
+        kappa = np.ones_like(a)
+    r = a / kappa
+    with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+        rho = np.power(r, n - 1.0) / kappa
+    rho = np.where(a > 0.0, rho, 0.0)
+    return j * rho
+
+
+def constitutive(j, chi, n, rho_out, kappa=None):
+    """e = rho(|j|) j in the superconductor (chi = 1), rho_out j outside."""
+    j = np.asarray(j, dtype=np.float64)
+    inside = np.asarray(chi) != 0
+    return np.where(inside, power_law(j, n, kappa), rho_out * j)

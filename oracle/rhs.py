@@ -1,0 +1,106 @@
+"""Right-hand side of the method-of-lines system (test infrastructure only).
+
+Follows Sec. 2 of the paper, in its order and notation, in the dimensionless
+variables of Eq. 8 (mu0 = e0 = jc = 1):
+
+  j = curl h                                   (Eq. 4, smoothed spectral curl)
+  e = rho(|j|) j in Omega, rho_out j outside   (Eq. 1 and the Ohm-law start)
+  hdot_in = -curl e restricted to Omega        (Eq. 3)
+  hdot_out^0 = initial approximation in Omega_out
+  iterate i = 0, 1, ...:
+      jdot^i = curl hdot^i
+      jdot_in^i = jdot^i in Omega, 0 in Omega_out
+      hdot_out^{i+1} = hedot + Phi[jdot_in^i] restricted to Omega_out   (Eq. 5)
+  until mean over Omega_out nodes of |hdot^{i+1} - hdot^i|
+        < delta_it * max(|hedot|, 1)                     (stopping rule)
+
+Readings (listed in the design notes):
+  * the initial approximation is hdot_out from the most recent call
+    ("from the previous time step"); on the first call, when none exists,
+    it is the Ohm-law value -curl e on Omega_out;
+  * min_iter (default 1) iterations always run; max_iter (default 200)
+    stops with a not-converged flag; fixed_iter > 0 runs exactly that many;
+  * |hedot| is the Euclidean norm at the evaluation time; the mean is over
+    Omega_out nodes; an empty Omega_out counts as converged.
+"""
+import numpy as np
+
+from . import law, operators
+
+
+class RhsOptions:
+    def __init__(self, delta_it=2e-5, min_iter=1, max_iter=200, fixed_iter=0,
+                 smooth_phi=False):
+        self.delta_it = float(delta_it)
+        self.min_iter = int(min_iter)
+        self.max_iter = int(max_iter)
+        self.fixed_iter = int(fixed_iter)
+        self.smooth_phi = bool(smooth_phi)
+
+
+class Problem:
+    """Everything rhs_eval needs besides the state: grid, mask, material,
+    drive and options, plus the warm-start memory (hdot_out of the last call)."""
+
+    def __init__(self, grid, chi, n_power, rho_out, drive, opts=None, kappa=None):
+        self.grid = grid
+        self.chi = np.asarray(chi, dtype=np.uint8)
+        self.n = float(n_power)
+        self.rho_out = float(rho_out)
+        self.drive = drive
+        self.opts = opts if opts is not None else RhsOptions()
+        self.kappa = kappa
+        self.warm = None            # hdot on Omega_out from the most recent call
+        self.last_iters = 0
+        self.last_deltas = []
+        self.last_converged = True
+
+
+def rhs_eval(prob, t, h):
+    """hdot = f(t, h) for h of shape (3, Nz, Ny, Nx); updates prob.warm."""
+    g = prob.grid
+    inside = prob.chi.astype(np.float64)       # chi
+    outside = 1.0 - inside                     # 1 - chi
+    n_out = int(np.sum(prob.chi == 0))
+    o = prob.opts
+
+    j = operators.curl_s(h, g)                                   # Eq. 4
+    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out, prob.kappa)   # Eq. 1
+    hdot_in = -operators.curl_s(e, g) * inside                   # Eq. 3 on Omega
+    if prob.warm is None:
+        hdot_out = -operators.curl_s(e, g) * outside             # Ohm-law start
+    else:
+        hdot_out = prob.warm * outside
+    hdot = hdot_in + hdot_out
+
+    hedot = np.asarray(prob.drive.hedot(t), dtype=np.float64).reshape(3, 1, 1, 1)
+    tol = o.delta_it * max(float(np.sqrt(np.sum(hedot ** 2))), 1.0)
+    deltas = []
+    converged = False
+    i = 0
+    while True:
+        jdot = operators.curl_s(hdot, g)                         # jdot^i = curl hdot^i
+        jdot_in = jdot * inside                                  # zero in Omega_out
+        new = hdot_in + outside * (hedot + operators.phi(jdot_in, g, o.smooth_phi))  # Eq. 5
+        diff = new - hdot
+        mag = np.sqrt(diff[0] ** 2 + diff[1] ** 2 + diff[2] ** 2)
+        d = float(np.sum(mag * outside) / n_out) if n_out > 0 else 0.0
+        deltas.append(d)
+        hdot = new
+        i += 1
+        if o.fixed_iter > 0:
+            if i >= o.fixed_iter:
+                converged = True
+                break
+            continue
+        if i >= o.min_iter and d < tol:
+            converged = True
+            break
+        if i >= o.max_iter:
+            converged = False
+            break
+    prob.warm = hdot * outside
+    prob.last_iters = i
+    prob.last_deltas = deltas
+    prob.last_converged = converged
+    return hdot

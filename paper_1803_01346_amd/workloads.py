@@ -1,0 +1,150 @@
+"""Seeded synthetic workloads: the configurations' parameters, their shapes as
+primitive lists, and smooth random vector fields.
+
+This module holds inputs only.  It does no voxelization, no Fourier
+transform and none of the method's operators: each consumer (the HIP
+library, the CPU oracle used by tests) turns these specifications into
+masks and fields by its own code.
+
+Shapes are lists of primitives in units of the characteristic length l
+(kind "box" | "cylinder" | "sphere", op "add" | "sub", center, size, axis):
+  box       size = half-extents (ax, ay, az)
+  cylinder  size = (radius, 0, half-height), axis = 0 | 1 | 2
+  sphere    size = (radius, 0, 0)
+"""
+import math
+
+import numpy as np
+
+
+def prim(kind, op="add", center=(0.0, 0.0, 0.0), size=(0.0, 0.0, 0.0), axis=2):
+    return dict(kind=kind, op=op, center=tuple(float(v) for v in center),
+                size=tuple(float(v) for v in size), axis=int(axis))
+
+
+def shape_cube(half_side=1.0):
+    """Cube of side 2*half_side centred at the origin."""
+    return [prim("box", "add", (0, 0, 0), (half_side,) * 3)]
+
+
+def shape_cup(r_out=1.0, r_in=0.8, height=4.0, cap=0.2, axis=2):
+    """Hollow cylinder closed at one end: bottom cap of thickness `cap`,
+    open top; the hole reaches past the top face."""
+    hh = 0.5 * height
+    c = [0.0, 0.0, 0.0]
+    c[axis] = cap                         # hole spans (-hh + cap, hh + cap)
+    return [prim("cylinder", "add", (0, 0, 0), (r_out, 0.0, hh), axis),
+            prim("cylinder", "sub", tuple(c), (r_in, 0.0, hh), axis)]
+
+
+def shape_lens(radius=1.0, height=4.0 / 3.0, bore=0.2, slit=1.0 / 15.0):
+    """Cylinder (axis z) with a coaxial bore and one radial slit along +x from
+    the bore to the rim, both through the full height."""
+    hh = 0.5 * height
+    reach = 0.75 * radius                 # slit box spans x in (0, 1.5 R)
+    return [prim("cylinder", "add", (0, 0, 0), (radius, 0.0, hh), 2),
+            prim("cylinder", "sub", (0, 0, 0), (bore, 0.0, 2.0 * hh), 2),
+            prim("box", "sub", (reach, 0.0, 0.0), (reach, 0.5 * slit, 2.0 * hh))]
+
+
+def shape_cylinder(radius=1.0, height=2.0, axis=2):
+    return [prim("cylinder", "add", (0, 0, 0), (radius, 0.0, 0.5 * height), axis)]
+
+
+def shape_sphere(radius=1.0):
+    return [prim("sphere", "add", (0, 0, 0), (radius, 0.0, 0.0))]
+
+
+# --------------------------------------------------------------------------
+# Configurations.  SI material and drive; geometry in units of l.
+#   n           grid counts (Nx, Ny, Nz) of the padded FFT box
+#   half_width  box half-widths in units of l
+#   drive       kind ramp_hold | sine | pwl, direction, amplitude (T), ...
+# rho_out: 20 for the shield-like and cube cases, 100 for the slit lens
+# (the paper's own choices for its shield and lens).
+# --------------------------------------------------------------------------
+
+_S45 = math.sqrt(0.5)
+
+CONFIGS = {
+    # superconducting cube, side 1 cm, 16^3 voxels in a 32^3 box
+    "cube32": dict(n=(32, 32, 32), l_m=5e-3, half_width=(2.0, 2.0, 2.0),
+                   shapes=shape_cube(1.0), n_power=20.0, jc=1e8, e0=1e-4, rho_out=20.0,
+                   drive=dict(kind="ramp_hold", direction=(0.0, 0.0, 1.0), amp_T=0.1,
+                              t_ramp_s=1.0), t_end_s=2.0),
+    # closed-end hollow cylinder R 10/8 mm, H 40 mm, cap 2 mm, 64^3 voxels in 128^3
+    "cup128": dict(n=(128, 128, 128), l_m=10e-3, half_width=(4.0, 4.0, 4.0),
+                   shapes=shape_cup(1.0, 0.8, 4.0, 0.2), n_power=100.0, jc=1e8, e0=1e-4,
+                   rho_out=20.0,
+                   drive=dict(kind="sine", direction=(_S45, 0.0, _S45), amp_T=0.05,
+                              freq_hz=50.0), t_end_s=0.04),
+    # the same shield on a coarser 64^3 box (32^3 voxels) for quick runs
+    "cup64": dict(n=(64, 64, 64), l_m=10e-3, half_width=(4.0, 4.0, 4.0),
+                  shapes=shape_cup(1.0, 0.8, 4.0, 0.2), n_power=100.0, jc=1e8, e0=1e-4,
+                  rho_out=20.0,
+                  drive=dict(kind="sine", direction=(_S45, 0.0, _S45), amp_T=0.05,
+                             freq_hz=50.0), t_end_s=0.04),
+    # bulk lens R 15 mm, H 20 mm, bore 3 mm, slit 1 mm, 128^3 voxels in 256^3
+    "lens256": dict(n=(256, 256, 256), l_m=15e-3, half_width=(2.0, 2.0, 2.0),
+                    shapes=shape_lens(1.0, 4.0 / 3.0, 0.2, 1.0 / 15.0), n_power=50.0,
+                    jc=2e8, e0=1e-4, rho_out=100.0,
+                    drive=dict(kind="ramp_hold", direction=(0.0, 0.0, 1.0), amp_T=1.0,
+                               t_ramp_s=150.0), t_end_s=150.0),
+}
+
+
+def config(name):
+    return CONFIGS[name]
+
+
+# --------------------------------------------------------------------------
+# Smooth random fields
+# --------------------------------------------------------------------------
+
+def smooth_field(n, half_width, seed=0, n_modes=12, max_index=None, j_target=1.05):
+    """Random smooth periodic vector field on the node lattice and its exact
+    continuum curl.
+
+    dh(i) = sum_q a_q cos(2 pi (mx ix/Nx + my iy/Ny + mz iz/Nz) + p_q)
+    with integer index vectors |m_a| <= max_index (default N_a/8, so there is
+    no content near the Nyquist planes), Gaussian amplitude vectors a_q and
+    uniform phases p_q.  The continuum curl, with k_a = pi m_a / L_a, is
+    curl dh = -sum_q sin(...) (k_q x a_q); the field is scaled so that the
+    largest node value of |curl dh| equals j_target.
+    Returns (dh, curl_dh), each float64 of shape (3, Nz, Ny, Nx).
+    """
+    nx, ny, nz = (int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    if max_index is None:
+        max_index = (max(1, nx // 8), max(1, ny // 8), max(1, nz // 8))
+    elif np.isscalar(max_index):
+        max_index = (int(max_index),) * 3
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    dh = np.zeros((3, nz, ny, nx))
+    cj = np.zeros((3, nz, ny, nx))
+    for _ in range(n_modes):
+        m = [int(rng.integers(-mi, mi + 1)) for mi in max_index]
+        if m == [0, 0, 0]:
+            m[0] = 1 if max_index[0] >= 1 else 0
+        a = rng.normal(size=3)
+        p = rng.uniform(0.0, 2.0 * np.pi)
+        ph = 2.0 * np.pi * (m[0] * ix / nx + m[1] * iy / ny + m[2] * iz / nz) + p
+        c, s = np.cos(ph), np.sin(ph)
+        k = np.array([np.pi * m[0] / half_width[0], np.pi * m[1] / half_width[1],
+                      np.pi * m[2] / half_width[2]])
+        kxa = np.cross(k, a)
+        for comp in range(3):
+            dh[comp] += a[comp] * c
+            cj[comp] -= kxa[comp] * s
+    jmax = float(np.sqrt(np.max(np.sum(cj * cj, axis=0))))
+    scale = j_target / jmax if jmax > 0 else 1.0
+    return dh * scale, cj * scale
+
+
+def synthetic_state(name_or_cfg, seed=0, background=(0.0, 0.0, 0.0), n=None, **kw):
+    """h = uniform background + smooth_field(...) for a configuration."""
+    cfg = CONFIGS[name_or_cfg] if isinstance(name_or_cfg, str) else name_or_cfg
+    n = cfg["n"] if n is None else n
+    dh, _ = smooth_field(n, cfg["half_width"], seed=seed, **kw)
+    b = np.asarray(background, dtype=np.float64).reshape(3, 1, 1, 1)
+    return dh + b

@@ -1,0 +1,64 @@
+"""Pin P6: the power law of Eq. 1 in the dimensionless form of Eq. 8,
+checked against closed forms that a dropped factor or a wrong exponent
+would violate."""
+import numpy as np
+import pytest
+
+from oracle import law
+
+
+def _vec(a, d):
+    d = np.asarray(d, float) / np.linalg.norm(d)
+    return (a * d).reshape(3, 1)
+
+
+@pytest.mark.parametrize("n", [1.0, 5.0, 20.0, 30.0, 100.0])
+def test_critical_density_gives_e0(n):
+    # |j| = jc  ->  e = e0 * j/|j|   (e' = j' when |j'| = 1)
+    j = _vec(1.0, [0.3, -0.5, 0.8])
+    e = law.power_law(j, n)
+    assert np.allclose(e, j, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", [2.0, 20.0, 100.0])
+@pytest.mark.parametrize("a", [1e-6, 0.3, 0.97, 1.0, 1.05, 2.0])
+def test_magnitude_is_power_n(n, a):
+    j = _vec(a, [1.0, 2.0, -2.0])
+    e = law.power_law(j, n)
+    assert np.isclose(np.linalg.norm(e), a ** n, rtol=1e-13)
+    assert np.allclose(np.cross(e[:, 0], j[:, 0]), 0.0, atol=1e-14 * a ** n * a)  # e parallel to j
+
+
+def test_zero_current_and_ohmic_case():
+    assert np.all(law.power_law(np.zeros((3, 4)), 100.0) == 0.0)
+    assert np.all(law.power_law(np.zeros((3, 4)), 1.0) == 0.0)
+    rng = np.random.default_rng(0)
+    j = rng.normal(size=(3, 10))
+    assert np.allclose(law.power_law(j, 1.0), j, rtol=1e-15)       # n = 1: Ohm's law
+
+
+def test_kappa_scaling():
+    # (|j|/kappa)^(n-1) j / kappa: with j = kappa * u, e = |u|^(n-1) u
+    rng = np.random.default_rng(1)
+    u = rng.normal(size=(3, 20)) * 0.4
+    kap = rng.uniform(0.5, 2.0, size=20)
+    e = law.power_law(u * kap, 25.0, kappa=kap)
+    assert np.allclose(e, law.power_law(u, 25.0), rtol=1e-13)
+
+
+def test_constitutive_masks():
+    rng = np.random.default_rng(2)
+    j = rng.normal(size=(3, 2, 2, 2))
+    chi = np.array([[[1, 0], [0, 1]], [[1, 1], [0, 0]]], dtype=np.uint8)
+    e = law.constitutive(j, chi, 30.0, 20.0)
+    assert np.allclose(e[:, chi == 0], 20.0 * j[:, chi == 0])
+    assert np.allclose(e[:, chi == 1], law.power_law(j[:, chi == 1], 30.0))
+
+
+def test_odd_and_isotropic():
+    rng = np.random.default_rng(3)
+    j = rng.normal(size=(3, 50))
+    e = law.power_law(j, 30.0)
+    assert np.array_equal(law.power_law(-j, 30.0), -e)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    assert np.allclose(law.power_law(q @ j, 30.0), q @ e, rtol=1e-12, atol=1e-14 * np.abs(e).max())
