@@ -1,0 +1,312 @@
+/*
+ * scfft — right-hand side and method-of-lines integrator of the FFT-based
+ * bulk magnetization method of Prigozhin & Sokolovsky (arXiv:1803.01346,
+ * "3D simulation of superconducting magnetic shields and lenses using the
+ * Fast Fourier Transform"), for AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper Sec. 2): a superconductor Omega inside the box
+ * D = {|x|<=Lx, |y|<=Ly, |z|<=Lz}, a uniform applied field h_e(t), the power
+ * law e = rho(|j|) j (Eq. 1), the Biot-Savart law h = h_e + Phi[j] (Eq. 2),
+ * Faraday's law mu0 dh/dt = -curl e (Eq. 3), Ampere's law j = curl h (Eq. 4),
+ * the exterior fixed-point iteration (Eq. 5) and Phi evaluated in Fourier
+ * space (Eq. 7, with 1/|k|^2 replaced by 0 at k = 0).  Derivatives are
+ * spectral with Gaussian smoothing of width sigma = half the cell diagonal;
+ * the node values of h obey an ODE system integrated in time (Sec. 2,
+ * discretisation paragraph).  Internal units are those of Eq. 8.
+ *
+ * Conventions shared by every entry point
+ *   Device arrays   caller-owned device memory (e.g. torch tensors).  A
+ *                   vector field is dense, structure-of-arrays [3][Nz][Ny][Nx]
+ *                   with x fastest and components (x, y, z), in the context's
+ *                   precision: double for SCFFT_F64, float for SCFFT_F32.
+ *                   Field values are dimensionless (h' = h/(jc l), Eq. 8).
+ *                   A scalar mask is uint8 [Nz][Ny][Nx], nonzero = inside.
+ *   Nodes           cell-centred: x_i = -L + (i + 1/2) 2L/N, i = 0..N-1.
+ *   Streams         every call is ordered on the HIP stream given at create;
+ *                   calls that return host values synchronise that stream.
+ *   Workspace       device memory the caller provides (scfft_set_workspace)
+ *                   and keeps alive while the context uses it; it holds the
+ *                   spectrum, the warm start, masks, tables and ODE stages.
+ *   Errors          every call returns an scfft_status; negative values are
+ *                   errors (nothing was launched, or the context state is as
+ *                   described per call), positive values are warnings.  The
+ *                   message of the last failure is scfft_last_error(ctx).
+ *   Threading       a context is not thread-safe; use one per host thread.
+ */
+#ifndef SCFFT_H
+#define SCFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCFFT_OK = 0,
+  SCFFT_WARN_NOT_CONVERGED = 1, /* iteration (5) stopped at max_iter        */
+  SCFFT_WARN_CLAMPED = 2,       /* power-law exponent clamped (overflow)    */
+  SCFFT_ERR_ARG = -1,           /* invalid argument (NULL, range, order)    */
+  SCFFT_ERR_SHAPE = -2,         /* unsupported grid size                    */
+  SCFFT_ERR_DEVICE = -3,        /* HIP runtime error or no device           */
+  SCFFT_ERR_WORKSPACE = -4,     /* workspace missing, too small, misaligned */
+  SCFFT_ERR_NAN = -5,           /* non-finite values met by the integrator  */
+  SCFFT_ERR_STEP_UNDERFLOW = -6,/* step size fell below its floor           */
+  SCFFT_ERR_GEOMETRY = -7,      /* mask not set, or empty where needed      */
+  SCFFT_ERR_STATE = -8          /* checkpoint blob does not fit the context */
+} scfft_status;
+
+typedef enum { SCFFT_F64 = 0, SCFFT_F32 = 1 } scfft_precision;
+
+/* Grid of the padded FFT box D.  n[a] = node counts (x, y, z): each a power
+ * of two in [8, 512].  half_width_m[a] = L_a in metres.  Sec. 2. */
+typedef struct {
+  int32_t n[3];
+  double half_width_m[3];
+} scfft_grid;
+
+/* Material and scaling (Eq. 1, Eq. 8).  n_power and jc (A/m^2) of the power
+ * law, e0 (V/m; the paper's value is 1e-4), rho_out the dimensionless
+ * fictitious exterior resistivity (Sec. 2; 20 and 100 in Sec. 3), l_char_m the
+ * characteristic length l of Eq. 8 in metres. */
+typedef struct {
+  double n_power;
+  double jc;
+  double e0;
+  double rho_out;
+  double l_char_m;
+} scfft_material;
+
+/* Uniform applied field h_e(t) (Sec. 2), given as B = mu0 h in tesla.
+ *   RAMP_HOLD  B(t) = dir * amp_T * min(t / t_ramp_s, 1)
+ *   SINE       B(t) = dir * amp_T * sin(2 pi freq_hz t)
+ *   PWL        B(t) linear between the n_pts points (t_s[k], b_T[3k..3k+2]),
+ *              constant outside; points are copied at scfft_set_drive.
+ * dir need not be normalised (it is).  Kinks are integrator breakpoints. */
+enum { SCFFT_DRIVE_RAMP_HOLD = 0, SCFFT_DRIVE_SINE = 1, SCFFT_DRIVE_PWL = 2 };
+typedef struct {
+  int32_t kind;
+  int32_t n_pts;
+  double dir[3];
+  double amp_T;
+  double t_ramp_s;
+  double freq_hz;
+  const double* t_s;
+  const double* b_T;
+} scfft_drive;
+
+/* Primitive of the voxelizer (the shape of Omega, Sec. 2).  Shapes apply in
+ * order: ADD sets nodes strictly inside the primitive, SUB clears nodes inside
+ * or on it; a node within 1e-9 * (smallest cell size) of a surface counts as
+ * on it, so nodes on the boundary of Omega fall outside Omega.
+ *   BOX       center_m, size_m = half-extents
+ *   CYLINDER  center_m, axis (0, 1, 2), size_m = (radius, unused, half-height)
+ *   SPHERE    center_m, size_m[0] = radius */
+enum { SCFFT_SHAPE_BOX = 0, SCFFT_SHAPE_CYLINDER = 1, SCFFT_SHAPE_SPHERE = 2 };
+enum { SCFFT_OP_ADD = 0, SCFFT_OP_SUB = 1 };
+typedef struct {
+  int32_t kind;
+  int32_t op;
+  int32_t axis;
+  int32_t reserved;
+  double center_m[3];
+  double size_m[3];
+} scfft_shape;
+
+/* Options of the right-hand side (Sec. 2, iteration (5) and its stopping rule).
+ *   delta_it     tolerance: stop when the mean over Omega_out nodes of
+ *                |hdot^{i+1} - hdot^i| < delta_it * max(|dh_e/dt|, 1)
+ *                (paper: 2e-5)
+ *   min_iter     iterations always run (default 1)
+ *   max_iter     stop with SCFFT_WARN_NOT_CONVERGED after this many (200)
+ *   fixed_iter   if > 0, run exactly this many and skip the test
+ *   smooth_phi   if nonzero, Phi's symbol is Gaussian-smoothed too (default 0)
+ *   sigma_scale  smoothing width in units of half the cell diagonal (1) */
+typedef struct {
+  double delta_it;
+  int32_t min_iter;
+  int32_t max_iter;
+  int32_t fixed_iter;
+  int32_t smooth_phi;
+  double sigma_scale;
+} scfft_rhs_opts;
+
+typedef struct {
+  int32_t iters;        /* iterations (5) run                              */
+  int32_t converged;    /* 1 if the stopping rule (or fixed_iter) ended it */
+  double last_delta;    /* last mean |hdot^{i+1} - hdot^i| over Omega_out  */
+  int64_t clamps;       /* power-law evaluations whose exponent was clamped */
+} scfft_rhs_stats;
+
+/* Options of the Bogacki-Shampine 3(2) integrator (the paper's ode23).
+ *   rtol (2e-4), atol (1e-6, on dimensionless h); err = max_i |E_i| /
+ *   max(|y_i|, |y_new,i|, atol/rtol), accept iff err <= rtol.
+ *   dt0_s (0 = automatic), dt_max_s (0 = no cap), fixed_steps > 0 = that many
+ *   equal steps, all accepted.  breakpoints_s: extra times never stepped over.
+ *   max_steps bounds accepted + rejected steps (0 = 10^7). */
+typedef struct {
+  double rtol;
+  double atol;
+  double dt0_s;
+  double dt_max_s;
+  int32_t fixed_steps;
+  int32_t n_bp;
+  const double* breakpoints_s;
+  int64_t max_steps;
+} scfft_ode_opts;
+
+typedef struct {
+  int64_t accepted;
+  int64_t rejected;
+  int64_t rhs_calls;
+  int64_t iters_total;   /* sum of iterations (5) over all RHS calls  */
+  int64_t not_converged; /* RHS calls that hit max_iter               */
+  int64_t clamps;
+  double t_s;            /* time reached                               */
+  double dt_last_s;
+  double err_last;
+} scfft_ode_stats;
+
+/* Called after every accepted step with the time (s) and the device state;
+ * it may call readout entry points on the same context.  A nonzero return
+ * stops the integration (scfft_integrate then returns SCFFT_OK). */
+typedef int32_t (*scfft_observer)(void* user, double t_s, const void* h_dev);
+
+/* Right-hand side on host arrays, for scfft_bs23_host. */
+typedef int32_t (*scfft_host_rhs)(void* user, double t, const double* y, double* ydot);
+
+typedef struct scfft_ctx scfft_ctx;
+
+/* ---- host-only utilities (no device work) ---- */
+
+/* Fill the defaults named above. */
+void scfft_default_rhs_opts(scfft_rhs_opts* o);
+void scfft_default_ode_opts(scfft_ode_opts* o);
+
+/* Scaling of Eq. 8: t0 = mu0 jc l^2 / e0 (s) and h_scale = jc l (A/m). */
+scfft_status scfft_units(const scfft_material* m, double* t0_s, double* h_scale);
+
+/* Applied field of a drive at time t_s, dimensionless (h' and dh'/dt'). */
+scfft_status scfft_drive_eval(const scfft_drive* d, const scfft_material* m, double t_s,
+                              double he[3], double hedot[3]);
+
+/* Voxelize shapes (coordinates in metres, scaled by m->l_char_m) on the grid
+ * into a host uint8 mask [Nz][Ny][Nx] the caller owns. */
+scfft_status scfft_voxelize_host(const scfft_grid* g, const scfft_material* m,
+                                 const scfft_shape* shapes, int32_t n_shapes, uint8_t* mask);
+
+/* Bogacki-Shampine 3(2) with the step control of scfft_integrate, on host
+ * arrays y[n] (in/out) with a host right-hand side; t in the caller's units.
+ * The device integrator runs the same controller. */
+scfft_status scfft_bs23_host(int64_t n, double* y, double t0, double t1, scfft_host_rhs f,
+                             void* user, const scfft_ode_opts* o, scfft_ode_stats* st);
+
+/* ---- context ---- */
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = the null stream).  Returns SCFFT_ERR_SHAPE for unsupported n,
+ * SCFFT_ERR_DEVICE without a usable device. */
+scfft_status scfft_create(scfft_ctx** out, const scfft_grid* g, const scfft_material* m,
+                          scfft_precision prec, void* hip_stream);
+void scfft_destroy(scfft_ctx* ctx);
+
+/* Bytes of device workspace the context needs (256-byte aligned start). */
+scfft_status scfft_workspace_size(const scfft_ctx* ctx, size_t* bytes);
+/* Attach the workspace; uploads tables (synchronously); clears mask, jc map
+ * and warm start. */
+scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Voxelize Omega on the host and upload the mask (synchronous). */
+scfft_status scfft_voxelize(scfft_ctx* ctx, const scfft_shape* shapes, int32_t n_shapes);
+/* Copy a caller's device mask uint8 [Nz][Ny][Nx] into the workspace. */
+scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask);
+/* Optional local critical density kappa = jc(x)/jc [Nz][Ny][Nx] in the
+ * context precision, all > 0; NULL clears it (kappa = 1).  Copied. */
+scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa);
+scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d);
+scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o);
+/* Forget the warm start of iteration (5): the next RHS starts from Ohm's law. */
+scfft_status scfft_reset_warm(scfft_ctx* ctx);
+
+/* Virgin state of Sec. 3: h = h_e(t0) everywhere (j = 0); clears the warm start. */
+scfft_status scfft_init_state(scfft_ctx* ctx, double t0_s, void* h_dev);
+
+/* The right-hand side hdot' = f(t, h) (Sec. 2): j = curl h, e from Eq. 1 in
+ * Omega and rho_out j outside, hdot = -curl e in Omega, iteration (5) in
+ * Omega_out from the warm start (hdot_out of the previous call; Ohm's law on
+ * the first call).  h_dev and hdot_dev must not alias.  Updates the warm
+ * start.  Requires workspace and mask.  stats may be NULL. */
+scfft_status scfft_rhs_eval(scfft_ctx* ctx, double t_s, const void* h_dev, void* hdot_dev,
+                            scfft_rhs_stats* stats);
+
+/* Integrate h from t0_s to t1_s in place (method of lines, Sec. 2).  The
+ * observer (may be NULL) sees every accepted step.  On SCFFT_ERR_NAN or
+ * SCFFT_ERR_STEP_UNDERFLOW h holds the last accepted state. */
+scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_dev,
+                             const scfft_ode_opts* o, scfft_observer obs, void* user,
+                             scfft_ode_stats* stats);
+
+/* ---- operators and readouts ---- */
+
+/* out = C_s v, the smoothed spectral curl (derivatives of Eqs. 3, 4). */
+scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev);
+/* out = Phi[v], Eq. 7 with the k = 0 rule (smoothed iff smooth_phi). */
+scfft_status scfft_phi(scfft_ctx* ctx, const void* v_dev, void* out_dev);
+/* j' = C_s h (dimensionless current density, all nodes). */
+scfft_status scfft_current(scfft_ctx* ctx, const void* h_dev, void* j_dev);
+/* Magnetic moment m = 1/2 sum (r x j) dV in A m^2, r from the box centre,
+ * over all nodes (omega_only = 0) or Omega nodes only. */
+scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only, double m_Am2[3]);
+/* Mean of |B| = mu0 |h| (tesla) over the nodes of a device region mask. */
+scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const uint8_t* dev_region,
+                                     double* b_T);
+/* B = mu0 h (tesla) at npts points (metres), trilinear between nodes with
+ * periodic wrap; b_T[3*p + c]. */
+scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_m, int32_t npts,
+                           double* b_T);
+
+/* ---- per-kernel timing ---- */
+
+/* Kernel kinds of the pass schedule.  X passes (rows along x, fused pointwise
+ * work) by operation, Y passes (columns along y) by direction, Z passes
+ * (columns along z with the operator symbol) by symbol. */
+enum {
+  SCFFT_KERNEL_X_FWD = 0,    /* real field -> x spectrum                   */
+  SCFFT_KERNEL_X_LAW,        /* -> j -> e of Eq. 1 -> spectrum             */
+  SCFFT_KERNEL_X_HIN,        /* -> -curl e, warm start -> hdot, spectrum   */
+  SCFFT_KERNEL_X_MASK,       /* -> jdot masked to Omega -> spectrum        */
+  SCFFT_KERNEL_X_UPDATE,     /* -> Phi, exterior update (Eq. 5) -> spectrum */
+  SCFFT_KERNEL_X_UPDATE_LAST,/* the same without the forward transform     */
+  SCFFT_KERNEL_X_STORE,      /* -> real field                              */
+  SCFFT_KERNEL_X_MOMENT,     /* -> j -> moment partial sums                */
+  SCFFT_KERNEL_Y_FWD,
+  SCFFT_KERNEL_Y_INV,
+  SCFFT_KERNEL_Z_CURL,       /* z transform, smoothed i k x, inverse       */
+  SCFFT_KERNEL_Z_PHI,        /* z transform, i k x / |k|^2, inverse        */
+  SCFFT_KERNEL_KINDS
+};
+
+/* enable != 0: start timing every pass launch with a HIP event pair on the
+ * context stream (and reset the totals); 0: stop.  Timing adds event records
+ * between launches, so time throughput with it off. */
+scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable);
+/* Launch counts and summed kernel durations (ms) per kind since enable;
+ * synchronises with the recorded events. */
+scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KINDS],
+                                double total_ms[SCFFT_KERNEL_KINDS]);
+
+/* ---- checkpoint ---- */
+
+/* Serialise the warm start and options (pass blob = NULL to query bytes). */
+scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes);
+scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes);
+
+const char* scfft_status_string(scfft_status s);
+const char* scfft_last_error(const scfft_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCFFT_H */

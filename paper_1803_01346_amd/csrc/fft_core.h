@@ -1,0 +1,202 @@
+// Device FFT engine for gfx950: Stockham radix passes on data held in
+// registers, exchanged through LDS between passes.
+//
+// A length-N transform is owned by TPT = N / E threads; thread j of a
+// transform holds the E elements v[m] = x[j + m * TPT], m = 0..E-1, both on
+// entry and on exit (natural order, no bit reversal).  Each Stockham pass of
+// radix R (R divides E) lets thread j run E/R butterflies b = j + q * TPT,
+// whose inputs are x[b + r * N/R] = v[q + r * E/R]; outputs go to
+// (b / Ns) * Ns * R + (b % Ns) + r * Ns, where Ns is the product of earlier
+// radices.  After the last pass that position is again v[q + r * E/R], so
+// the final pass needs no exchange.
+//
+// Forward transforms use exp(-2 pi i k / N) (the paper's sign, Sec. 2 text
+// before Eq. 7); the inverse is conj(forward(conj(x))), unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace scfft {
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---- in-register DFTs of radix 2, 4, 8 (forward sign) ----
+
+template <typename T>
+__device__ __forceinline__ void dft2(C2<T>* v) {
+  C2<T> a = v[0];
+  v[0] = a + v[1];
+  v[1] = a - v[1];
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(C2<T>& a, C2<T>& b, C2<T>& c, C2<T>& d) {
+  C2<T> t0 = a + c, t1 = a - c, t2 = b + d, t3 = b - d;
+  a = t0 + t2;
+  c = t0 - t2;
+  b = {t1.x + t3.y, t1.y - t3.x};  // t1 - i t3
+  d = {t1.x - t3.y, t1.y + t3.x};  // t1 + i t3
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(C2<T>* v) { dft4(v[0], v[1], v[2], v[3]); }
+
+template <typename T>
+__device__ __forceinline__ void dft8(C2<T>* v) {
+  const T r = T(0.70710678118654752440084436210484904);
+  C2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  // twiddles w8^k o_k, w8 = exp(-i pi / 4)
+  C2<T> t1 = {(o1.x + o1.y) * r, (o1.y - o1.x) * r};
+  C2<T> t2 = {o2.y, -o2.x};
+  C2<T> t3 = {(o3.y - o3.x) * r, -(o3.y + o3.x) * r};
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + t1;
+  v[5] = e1 - t1;
+  v[2] = e2 + t2;
+  v[6] = e2 - t2;
+  v[3] = e3 + t3;
+  v[7] = e3 - t3;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftR(C2<T>* v) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 4) dft4(v);
+  else if constexpr (R == 8) dft8(v);
+  else static_assert(R == 2 || R == 4 || R == 8, "radix");
+}
+
+// ---- pass plan: radices for length N with E elements per thread ----
+
+__host__ __device__ constexpr int elems_per_thread(int n) { return n >= 8 ? 8 : n; }
+
+// radix of pass p (0-based) for length N with E per thread: E while the
+// remaining factor allows, then the remainder.
+__host__ __device__ constexpr int pass_radix(int n, int e, int p) {
+  int rem = n;
+  for (int i = 0; i < p; ++i) rem /= (rem >= e ? e : rem);
+  return rem >= e ? e : rem;
+}
+__host__ __device__ constexpr int pass_count(int n, int e) {
+  int c = 0;
+  for (int rem = n; rem > 1; rem /= (rem >= e ? e : rem)) ++c;
+  return c;
+}
+__host__ __device__ constexpr int pass_span(int n, int e, int p) {  // Ns of pass p
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= pass_radix(n, e, i);
+  return ns;
+}
+
+// One Stockham pass.  tw points at a table of exp(-2 pi i k / (N * TWS)),
+// k = 0 .. N*TWS - 1, read with stride TWS.  Lds provides store(idx, v),
+// load(idx) for this transform and sync().
+template <typename T, int N, int E, int P, class Lds>
+__device__ __forceinline__ void stockham_pass(C2<T> (&v)[E], int j, Lds& lds,
+                                              const C2<T>* __restrict__ tw, int tws) {
+  constexpr int R = pass_radix(N, E, P);
+  constexpr int NS = pass_span(N, E, P);
+  constexpr int TPT = N / E;
+  constexpr int Q = E / R;
+  constexpr bool LAST = (P + 1 == pass_count(N, E));
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = j + q * TPT;
+    C2<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[q + r * Q];
+    const int kk = b & (NS - 1);
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tw[(r * kk * (N / (NS * R))) * tws]);
+    }
+    dftR<T, R>(a);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * Q] = a[r];
+    } else {
+      const int base = (b / NS) * NS * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds.store(base + r * NS, a[r]);
+    }
+  }
+  if constexpr (!LAST) {
+    lds.sync();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = lds.load(j + m * TPT);
+    lds.sync();
+  }
+}
+
+template <typename T, int N, int E, int P, class Lds>
+__device__ __forceinline__ void fft_passes(C2<T> (&v)[E], int j, Lds& lds,
+                                           const C2<T>* __restrict__ tw, int tws) {
+  if constexpr (P < pass_count(N, E)) {
+    stockham_pass<T, N, E, P>(v, j, lds, tw, tws);
+    fft_passes<T, N, E, P + 1>(v, j, lds, tw, tws);
+  }
+}
+
+// Forward (exp(-i...)) transform of length N; all threads of the block must
+// call it together (it synchronises the block between passes).
+template <typename T, int N, int E, class Lds>
+__device__ __forceinline__ void fft_forward(C2<T> (&v)[E], int j, Lds& lds,
+                                            const C2<T>* __restrict__ tw, int tws) {
+  fft_passes<T, N, E, 0>(v, j, lds, tw, tws);
+}
+
+template <typename T, int N, int E, class Lds>
+__device__ __forceinline__ void fft_inverse(C2<T> (&v)[E], int j, Lds& lds,
+                                            const C2<T>* __restrict__ tw, int tws) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+  fft_passes<T, N, E, 0>(v, j, lds, tw, tws);
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+}
+
+// LDS layouts.  Column-major: COLS transforms side by side, element idx of
+// column c at idx * COLS + c (lanes of one row of columns are contiguous).
+template <typename T, int COLS>
+struct LdsCols {
+  C2<T>* base;
+  int col;
+  __device__ __forceinline__ void store(int idx, C2<T> v) { base[idx * COLS + col] = v; }
+  __device__ __forceinline__ C2<T> load(int idx) const { return base[idx * COLS + col]; }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// Row-major with one padding element every 8 (spreads the radix-8 strides
+// of the first pass over the banks).
+template <typename T, int N>
+struct LdsRows {
+  static constexpr int STRIDE = N + N / 8 + 1;
+  C2<T>* base;
+  int row;
+  __device__ __forceinline__ static int pad(int idx) { return idx + (idx >> 3); }
+  __device__ __forceinline__ void store(int idx, C2<T> v) { base[row * STRIDE + pad(idx)] = v; }
+  __device__ __forceinline__ C2<T> load(int idx) const { return base[row * STRIDE + pad(idx)]; }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+}  // namespace scfft

@@ -1,0 +1,110 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_core.h"
+
+namespace scfft {
+
+// Per-axis device tables (context precision T), built on the host in FP64:
+//   tw[k]   = exp(-2 pi i k / N), k = 0..N-1
+//   kodd[i] = pi m_i / L with m_i the signed DFT index, 0 at the Nyquist entry
+//   kk[i]   = (pi m_i / L)^2 with the true Nyquist wavenumber
+//   sm[i]   = exp(-sigma^2 (pi m_i / L)^2 / 2), the axis factor of S(k)
+template <typename T>
+struct AxisTab {
+  const C2<T>* tw;
+  const T* kodd;
+  const T* kk;
+  const T* sm;
+};
+
+// Spectrum and sizes seen by the pass kernels.
+//   main[c][z][y][kx], kx = 0..nx/2-1   (x-transformed columns)
+//   nyq [c][z][y]                       (the kx = nx/2 column)
+template <typename T>
+struct Plan {
+  int nx, ny, nz;
+  C2<T>* main;
+  C2<T>* nyq;
+  AxisTab<T> ax, ay, az;
+};
+
+enum XOp : int {
+  X_FWD = 0,      // real input -> spectrum
+  X_LAW,          // spectrum -> j -> e (Eq. 1, rho_out outside) -> spectrum
+  X_HIN,          // spectrum -> g = -curl e; hdot0 = chi g + (1-chi) warm -> out, spectrum
+  X_MASK,         // spectrum -> chi * v -> spectrum
+  X_UPDATE,       // spectrum -> phi; hdot = chi hdot + (1-chi)(hedot + phi) -> out, spectrum; |delta| sums
+  X_UPDATE_LAST,  // X_UPDATE without the forward transform
+  X_STORE,        // spectrum -> real output
+  X_MOMENT,       // spectrum -> j; sums of r x j over all nodes (or chi nodes)
+  X_NUM_OPS
+};
+
+enum ZSym : int { Z_CURL = 0, Z_PHI = 1, Z_PHI_SMOOTH = 2 };
+
+template <typename T>
+struct XArgs {
+  const T* in;           // X_FWD
+  T* out;                // X_HIN, X_UPDATE*: hdot;  X_STORE: output field
+  const T* warm;         // X_HIN: warm start (nullptr: Ohm-law start)
+  const uint8_t* chi;    // mask [nz][ny][nx]
+  const T* kappa;        // jc map or nullptr
+  double* partials;      // X_UPDATE*: one double per block; X_MOMENT: 3 per block
+  unsigned long long* clamps;
+  T npow, rho_out, expmax;
+  T hedot[3];
+  int omega_only;        // X_MOMENT: 1 = chi nodes only
+  double pos0[3];        // coordinate of node 0 along each axis (moment)
+  double step[3];        // node spacing (moment)
+};
+
+template <typename T>
+int xpass_blocks(const Plan<T>& p);
+template <typename T>
+hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_ypass(const Plan<T>& p, bool inverse, hipStream_t s);
+template <typename T>
+hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s);
+
+// ---- pointwise / reduction kernels (pointwise.hip) ----
+hipError_t launch_sum_partials(const double* partials, int n, int stride, int ncomp, double* out,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream_t s);
+// out = y + c1 k1 + c2 k2 + c3 k3 (terms with null k skipped)
+template <typename T>
+hipError_t launch_combo(T* out, const T* y, const T* k1, double c1, const T* k2, double c2,
+                        const T* k3, double c3, size_t n, hipStream_t s);
+// per-block max of |dt (e1 k1 + e2 k2 + e3 k3 + e4 k4)| / max(|y|, |y1|, thr); NaN -> inf
+template <typename T>
+hipError_t launch_errnorm(const T* y, const T* y1, const T* k1, const T* k2, const T* k3,
+                          const T* k4, double dt, double thr, size_t n, double* partials,
+                          int nblocks, hipStream_t s);
+// per-block max of |a_i| / max(|y_i|, thr)
+template <typename T>
+hipError_t launch_ratio_max(const T* a, const T* y, double thr, size_t n, double* partials,
+                            int nblocks, hipStream_t s);
+hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s);
+// per-block sums of |h| and count over region nodes
+template <typename T>
+hipError_t launch_region_abs(const T* h, const uint8_t* region, size_t nodes, double* partials,
+                             int nblocks, hipStream_t s);
+// trilinear probe of h at npts dimensionless points
+template <typename T>
+hipError_t launch_probe(const T* h, int nx, int ny, int nz, const double* pts, int npts,
+                        double x0, double y0, double z0, double hx, double hy, double hz,
+                        double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t nodes,
+                              hipStream_t s);
+
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace scfft

@@ -1,0 +1,523 @@
+// The three kinds of full-field passes of one spectral operator application.
+//
+// A vector field v (3 components on an Nx x Ny x Nz grid) goes through
+//   X pass   rows along x: real-to-complex transform of length Nx, done as a
+//            complex transform of length Nx/2 plus a split step, fused with
+//            all pointwise work of the method (power law, masks, exterior
+//            update, reductions) between the inverse of one operator and
+//            the forward transform of the next
+//   Y pass   columns along y of the half spectrum (per component)
+//   Z pass   columns along z, all three components at once: forward
+//            transform, the operator's symbol (smoothed curl or Phi of
+//            Eq. 7, both cross products with i k), inverse transform
+// The spectrum of each component is stored as main[z][y][kx], kx < Nx/2,
+// plus the Nyquist column nyq[z][y] (kx = Nx/2), so every row of the main
+// part is a power of two long and column tiles stay aligned.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace scfft {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Y pass
+// ---------------------------------------------------------------------------
+template <typename T, int NY, bool INV>
+__global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
+                                                       C2<T>* __restrict__ nyq, int M,
+                                                       int ncols_main, int ncols_nyq,
+                                                       int nblk_main, const C2<T>* __restrict__ tw) {
+  constexpr int E = elems_per_thread(NY);
+  constexpr int TPT = NY / E;
+  constexpr int COLS = kBlock / TPT;
+  __shared__ C2<T> smem[NY * COLS];
+  const int tid = threadIdx.x;
+  const int col = tid % COLS;
+  const int j = tid / COLS;
+  const bool is_nyq = (int)blockIdx.x >= nblk_main;
+  const int q = (is_nyq ? (int)blockIdx.x - nblk_main : (int)blockIdx.x) * COLS + col;
+  const bool valid = q < (is_nyq ? ncols_nyq : ncols_main);
+  C2<T>* p;
+  size_t es;
+  if (!is_nyq) {
+    const int blk = q / M, kx = q % M;
+    p = main + (size_t)blk * NY * M + kx;
+    es = (size_t)M;
+  } else {
+    p = nyq + (size_t)q * NY;
+    es = 1;
+  }
+  C2<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = valid ? p[(size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
+  LdsCols<T, COLS> lds{smem, col};
+  if constexpr (INV)
+    fft_inverse<T, NY, E>(v, j, lds, tw, 1);
+  else
+    fft_forward<T, NY, E>(v, j, lds, tw, 1);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) p[(size_t)(j + m * TPT) * es] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z pass: forward z transform of the three components, symbol, inverse.
+// ---------------------------------------------------------------------------
+template <typename T, int NZ, int SYM>
+__global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
+                                                       C2<T>* __restrict__ nyq, int ny, int M,
+                                                       int nblk_main, AxisTab<T> tx, AxisTab<T> ty,
+                                                       AxisTab<T> tz, T coef) {
+  constexpr int E = elems_per_thread(NZ);
+  constexpr int TPT = NZ / E;
+  constexpr int COLS = kBlock / TPT;
+  __shared__ C2<T> smem[NZ * COLS];
+  const int tid = threadIdx.x;
+  const int col = tid % COLS;
+  const int j = tid / COLS;
+  const bool is_nyq = (int)blockIdx.x >= nblk_main;
+  const int q = (is_nyq ? (int)blockIdx.x - nblk_main : (int)blockIdx.x) * COLS + col;
+  C2<T>* p;
+  size_t es, cs;
+  int kx, ky;
+  bool valid;
+  if (!is_nyq) {
+    valid = q < ny * M;
+    p = main + q;
+    es = (size_t)ny * M;
+    cs = (size_t)NZ * ny * M;
+    kx = q % M;
+    ky = q / M;
+  } else {
+    valid = q < ny;
+    p = nyq + q;
+    es = (size_t)ny;
+    cs = (size_t)NZ * ny;
+    kx = M;
+    ky = q;
+  }
+  if (!valid) {
+    kx = 0;
+    ky = 0;
+  }
+  C2<T> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      v[c][m] = valid ? p[c * cs + (size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
+  LdsCols<T, COLS> lds{smem, col};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
+
+  const T kxo = tx.kodd[kx], kyo = ty.kodd[ky];
+  T fxy;
+  if constexpr (SYM == Z_CURL) {
+    fxy = coef * tx.sm[kx] * ty.sm[ky];
+  } else {
+    fxy = tx.kk[kx] + ty.kk[ky];
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kz = j + m * TPT;
+    const T kzo = tz.kodd[kz];
+    T f;
+    if constexpr (SYM == Z_CURL) {
+      f = fxy * tz.sm[kz];
+    } else {
+      const T k2 = fxy + tz.kk[kz];
+      f = k2 > T(0) ? coef / k2 : T(0);
+      if constexpr (SYM == Z_PHI_SMOOTH) f = f * tx.sm[kx] * ty.sm[ky] * tz.sm[kz];
+    }
+    const C2<T> a = v[0][m], b = v[1][m], d = v[2][m];
+    // k x v, then multiply by i f:  i (u + i w) f = (-w f, u f)
+    const C2<T> cx = {kyo * d.x - kzo * b.x, kyo * d.y - kzo * b.y};
+    const C2<T> cy = {kzo * a.x - kxo * d.x, kzo * a.y - kxo * d.y};
+    const C2<T> cz = {kxo * b.x - kyo * a.x, kxo * b.y - kyo * a.y};
+    v[0][m] = {-cx.y * f, cx.x * f};
+    v[1][m] = {-cy.y * f, cy.x * f};
+    v[2][m] = {-cz.y * f, cz.x * f};
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fft_inverse<T, NZ, E>(v[c], j, lds, tz.tw, 1);
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) p[c * cs + (size_t)(j + m * TPT) * es] = v[c][m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X pass
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dev_exp(T x);
+template <>
+__device__ __forceinline__ double dev_exp<double>(double x) { return exp(x); }
+template <>
+__device__ __forceinline__ float dev_exp<float>(float x) { return expf(x); }
+template <typename T>
+__device__ __forceinline__ T dev_log(T x);
+template <>
+__device__ __forceinline__ double dev_log<double>(double x) { return log(x); }
+template <>
+__device__ __forceinline__ float dev_log<float>(float x) { return logf(x); }
+
+// e = (|j|/kappa)^(n-1) j / kappa evaluated as j exp((n-1) (ln|j| - ln kappa) - ln kappa)
+template <typename T>
+__device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T expmax,
+                                          unsigned& clamps) {
+  const T s = a * a + b * b + c * c;
+  if (s > T(0)) {
+    T ex = (npow - T(1)) * (T(0.5) * dev_log<T>(s) - lnk) - lnk;
+    if (ex > expmax) {
+      ex = expmax;
+      ++clamps;
+    }
+    const T f = dev_exp<T>(ex);
+    a *= f;
+    b *= f;
+    c *= f;
+  } else {
+    a = T(0);
+    b = T(0);
+    c = T(0);
+  }
+}
+
+template <typename T, int NX, int OP>
+__global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
+  constexpr int M = NX / 2;
+  constexpr int E = elems_per_thread(M);
+  constexpr int TPT = M / E;
+  constexpr int ROWS = kBlock / TPT;
+  constexpr bool HAS_INV = OP != X_FWD;
+  constexpr bool HAS_FWD = OP == X_FWD || OP == X_LAW || OP == X_HIN || OP == X_MASK ||
+                           OP == X_UPDATE;
+  constexpr bool REDUCE = OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MOMENT;
+  using L = LdsRows<T, M>;
+  __shared__ C2<T> smem[ROWS * L::STRIDE];
+  __shared__ double red[REDUCE ? 3 * kBlock : 1];
+
+  const int tid = threadIdx.x;
+  const int rl = tid / TPT;
+  const int j = tid % TPT;
+  const int nrows = P.ny * P.nz;
+  const int r = blockIdx.x * ROWS + rl;
+  const bool valid = r < nrows;
+  const int rr = valid ? r : 0;
+  const size_t csm = (size_t)nrows * M;        // component stride, main spectrum
+  const size_t csn = (size_t)nrows;            // component stride, Nyquist column
+  const size_t csr = (size_t)nrows * NX;       // component stride, real field
+  const C2<T>* __restrict__ tw = P.ax.tw;      // exp(-2 pi i k / NX)
+  L lds{smem, rl};
+
+  T a[3][2 * E];
+  unsigned clamps = 0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+
+  if constexpr (HAS_INV) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C2<T> X[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        X[m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
+        lds.store(j + m * TPT, X[m]);
+      }
+      if (j == 0) lds.store(M, valid ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)});
+      __syncthreads();
+      C2<T> Z[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = j + m * TPT;
+        const C2<T> pc = cconj(lds.load(M - k));                // conj X[M-k]
+        const C2<T> ev = X[m] + pc;                              // X[k] + X[k+M]
+        const C2<T> od = cmul(X[m] - pc, cconj(tw[k]));          // (X[k] - X[k+M]) w^-k
+        Z[m] = {ev.x - od.y, ev.y + od.x};                       // ev + i od
+      }
+      __syncthreads();
+      fft_inverse<T, M, E>(Z, j, lds, tw, 2);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        a[c][2 * m] = Z[m].x;
+        a[c][2 * m + 1] = Z[m].y;
+      }
+    }
+  }
+
+  // ---- pointwise work on the nodes x = 2n, 2n+1, n = j + m TPT ----
+  const int y = rr % P.ny;
+  const int z = rr / P.ny;
+  const size_t rowbase = (size_t)rr * NX;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = 2 * (j + m * TPT) + h;
+      const size_t idx = rowbase + x;
+      const int e = 2 * m + h;
+      if constexpr (OP == X_FWD) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[c][e] = valid ? A.in[c * csr + idx] : T(0);
+      } else if constexpr (OP == X_LAW) {
+        const bool in = valid && A.chi[idx] != 0;
+        if (in) {
+          const T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
+          power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c][e] *= A.rho_out;
+        }
+      } else if constexpr (OP == X_HIN) {
+        const bool in = valid && A.chi[idx] != 0;
+        if (!in && A.warm) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c][e] = valid ? A.warm[c * csr + idx] : T(0);
+        }
+        if (valid) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+        }
+      } else if constexpr (OP == X_MASK) {
+        const bool in = valid && A.chi[idx] != 0;
+        if (!in) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c][e] = T(0);
+        }
+      } else if constexpr (OP == X_UPDATE || OP == X_UPDATE_LAST) {
+        const bool in = valid && A.chi[idx] != 0;
+        T d2 = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T old = valid ? A.out[c * csr + idx] : T(0);
+          const T nw = in ? old : A.hedot[c] + a[c][e];
+          const T dd = nw - old;
+          d2 += dd * dd;
+          a[c][e] = nw;
+        }
+        if (valid && !in) {
+          acc0 += sqrt((double)d2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+        }
+      } else if constexpr (OP == X_STORE) {
+        if (valid) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+        }
+      } else if constexpr (OP == X_MOMENT) {
+        const bool use = valid && (!A.omega_only || A.chi[idx] != 0);
+        if (use) {
+          const double px = A.pos0[0] + A.step[0] * x;
+          const double py = A.pos0[1] + A.step[1] * y;
+          const double pz = A.pos0[2] + A.step[2] * z;
+          const double jx = a[0][e], jy = a[1][e], jz = a[2][e];
+          acc0 += py * jz - pz * jy;
+          acc1 += pz * jx - px * jz;
+          acc2 += px * jy - py * jx;
+        }
+      }
+    }
+  }
+
+  if constexpr (REDUCE) {
+    red[tid] = acc0;
+    red[kBlock + tid] = acc1;
+    red[2 * kBlock + tid] = acc2;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        red[tid] += red[tid + s];
+        red[kBlock + tid] += red[kBlock + tid + s];
+        red[2 * kBlock + tid] += red[2 * kBlock + tid + s];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      if constexpr (OP == X_MOMENT) {
+        A.partials[3 * blockIdx.x + 0] = red[0];
+        A.partials[3 * blockIdx.x + 1] = red[kBlock];
+        A.partials[3 * blockIdx.x + 2] = red[2 * kBlock];
+      } else {
+        A.partials[blockIdx.x] = red[0];
+      }
+    }
+  }
+  if constexpr (OP == X_LAW) {
+    if (clamps) atomicAdd(A.clamps, (unsigned long long)clamps);
+  }
+
+  if constexpr (HAS_FWD) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C2<T> Z[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) Z[m] = {a[c][2 * m], a[c][2 * m + 1]};
+      fft_forward<T, M, E>(Z, j, lds, tw, 2);
+#pragma unroll
+      for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Z[m]);
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = j + m * TPT;
+        const C2<T> pc = cconj(lds.load((M - k) & (M - 1)));   // conj Z[M-k], Z[M] = Z[0]
+        const C2<T> s = Z[m] + pc, d = Z[m] - pc;
+        const C2<T> ev = {T(0.5) * s.x, T(0.5) * s.y};         // E[k]
+        const C2<T> od = {T(0.5) * d.y, T(-0.5) * d.x};        // O[k] = d / (2i)
+        const C2<T> X = ev + cmul(tw[k], od);
+        if (valid) P.main[c * csm + (size_t)rr * M + k] = X;
+      }
+      if (j == 0 && valid) P.nyq[c * csn + rr] = C2<T>{Z[0].x - Z[0].y, T(0)};
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int N>
+constexpr int tpt_of() {
+  return N / elems_per_thread(N);
+}
+
+template <typename T, int NX>
+static int xblocks_n(const Plan<T>& p) {
+  constexpr int ROWS = kBlock / tpt_of<NX / 2>();
+  return (p.ny * p.nz + ROWS - 1) / ROWS;
+}
+
+template <typename T>
+int xpass_blocks(const Plan<T>& p) {
+  switch (p.nx) {
+    case 8: return xblocks_n<T, 8>(p);
+    case 16: return xblocks_n<T, 16>(p);
+    case 32: return xblocks_n<T, 32>(p);
+    case 64: return xblocks_n<T, 64>(p);
+    case 128: return xblocks_n<T, 128>(p);
+    case 256: return xblocks_n<T, 256>(p);
+    case 512: return xblocks_n<T, 512>(p);
+  }
+  return -1;
+}
+
+template <typename T, int NX>
+static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s) {
+  const dim3 grid(xblocks_n<T, NX>(p)), block(kBlock);
+  switch (op) {
+    case X_FWD: hipLaunchKernelGGL((xpass_kernel<T, NX, X_FWD>), grid, block, 0, s, p, a); break;
+    case X_LAW: hipLaunchKernelGGL((xpass_kernel<T, NX, X_LAW>), grid, block, 0, s, p, a); break;
+    case X_HIN: hipLaunchKernelGGL((xpass_kernel<T, NX, X_HIN>), grid, block, 0, s, p, a); break;
+    case X_MASK: hipLaunchKernelGGL((xpass_kernel<T, NX, X_MASK>), grid, block, 0, s, p, a); break;
+    case X_UPDATE:
+      hipLaunchKernelGGL((xpass_kernel<T, NX, X_UPDATE>), grid, block, 0, s, p, a);
+      break;
+    case X_UPDATE_LAST:
+      hipLaunchKernelGGL((xpass_kernel<T, NX, X_UPDATE_LAST>), grid, block, 0, s, p, a);
+      break;
+    case X_STORE: hipLaunchKernelGGL((xpass_kernel<T, NX, X_STORE>), grid, block, 0, s, p, a); break;
+    case X_MOMENT:
+      hipLaunchKernelGGL((xpass_kernel<T, NX, X_MOMENT>), grid, block, 0, s, p, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s) {
+  switch (p.nx) {
+    case 8: return xlaunch_n<T, 8>(p, op, a, s);
+    case 16: return xlaunch_n<T, 16>(p, op, a, s);
+    case 32: return xlaunch_n<T, 32>(p, op, a, s);
+    case 64: return xlaunch_n<T, 64>(p, op, a, s);
+    case 128: return xlaunch_n<T, 128>(p, op, a, s);
+    case 256: return xlaunch_n<T, 256>(p, op, a, s);
+    case 512: return xlaunch_n<T, 512>(p, op, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int NY>
+static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s) {
+  constexpr int COLS = kBlock / tpt_of<NY>();
+  const int M = p.nx / 2;
+  const int ncm = 3 * p.nz * M, ncn = 3 * p.nz;
+  const int nbm = (ncm + COLS - 1) / COLS, nbn = (ncn + COLS - 1) / COLS;
+  const dim3 grid(nbm + nbn), block(kBlock);
+  if (inv)
+    hipLaunchKernelGGL((ypass_kernel<T, NY, true>), grid, block, 0, s, p.main, p.nyq, M, ncm, ncn,
+                       nbm, p.ay.tw);
+  else
+    hipLaunchKernelGGL((ypass_kernel<T, NY, false>), grid, block, 0, s, p.main, p.nyq, M, ncm, ncn,
+                       nbm, p.ay.tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s) {
+  switch (p.ny) {
+    case 8: return ylaunch_n<T, 8>(p, inv, s);
+    case 16: return ylaunch_n<T, 16>(p, inv, s);
+    case 32: return ylaunch_n<T, 32>(p, inv, s);
+    case 64: return ylaunch_n<T, 64>(p, inv, s);
+    case 128: return ylaunch_n<T, 128>(p, inv, s);
+    case 256: return ylaunch_n<T, 256>(p, inv, s);
+    case 512: return ylaunch_n<T, 512>(p, inv, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int NZ>
+static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s) {
+  constexpr int COLS = kBlock / tpt_of<NZ>();
+  const int M = p.nx / 2;
+  const int nbm = (p.ny * M + COLS - 1) / COLS, nbn = (p.ny + COLS - 1) / COLS;
+  const dim3 grid(nbm + nbn), block(kBlock);
+  switch (sym) {
+    case Z_CURL:
+      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_CURL>), grid, block, 0, s, p.main, p.nyq, p.ny, M,
+                         nbm, p.ax, p.ay, p.az, coef);
+      break;
+    case Z_PHI:
+      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_PHI>), grid, block, 0, s, p.main, p.nyq, p.ny, M,
+                         nbm, p.ax, p.ay, p.az, coef);
+      break;
+    case Z_PHI_SMOOTH:
+      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_PHI_SMOOTH>), grid, block, 0, s, p.main, p.nyq,
+                         p.ny, M, nbm, p.ax, p.ay, p.az, coef);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s) {
+  switch (p.nz) {
+    case 8: return zlaunch_n<T, 8>(p, sym, coef, s);
+    case 16: return zlaunch_n<T, 16>(p, sym, coef, s);
+    case 32: return zlaunch_n<T, 32>(p, sym, coef, s);
+    case 64: return zlaunch_n<T, 64>(p, sym, coef, s);
+    case 128: return zlaunch_n<T, 128>(p, sym, coef, s);
+    case 256: return zlaunch_n<T, 256>(p, sym, coef, s);
+    case 512: return zlaunch_n<T, 512>(p, sym, coef, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template int xpass_blocks<double>(const Plan<double>&);
+template int xpass_blocks<float>(const Plan<float>&);
+template hipError_t launch_xpass<double>(const Plan<double>&, int, const XArgs<double>&, hipStream_t);
+template hipError_t launch_xpass<float>(const Plan<float>&, int, const XArgs<float>&, hipStream_t);
+template hipError_t launch_ypass<double>(const Plan<double>&, bool, hipStream_t);
+template hipError_t launch_ypass<float>(const Plan<float>&, bool, hipStream_t);
+template hipError_t launch_zpass<double>(const Plan<double>&, int, double, hipStream_t);
+template hipError_t launch_zpass<float>(const Plan<float>&, int, float, hipStream_t);
+
+}  // namespace scfft

@@ -1,0 +1,287 @@
+// Streaming kernels outside the transform passes: the integrator's stage
+// combinations and error norm, FP64 reductions, readouts.
+//
+// Reductions are two-stage and deterministic: a fixed grid writes one
+// partial per block (fixed tree inside the block), and a single block sums
+// or maximises the partials in a fixed order.  No floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace scfft {
+
+constexpr int kRB = 256;  // threads per block of these kernels
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kRB / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kRB / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// out[c] = sum_b partials[b * stride + c], c < ncomp, one block.
+__global__ __launch_bounds__(kRB) void sum_partials_kernel(const double* __restrict__ p, int n,
+                                                           int stride, int ncomp,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kRB];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRB) acc += p[(size_t)i * stride + c];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[c] = r;
+  }
+}
+
+hipError_t launch_sum_partials(const double* partials, int n, int stride, int ncomp, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, stride, ncomp,
+                     out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restrict__ p, int n,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kRB];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kRB) acc = fmax(acc, p[i]);
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void fill_uniform_kernel(T* __restrict__ h, size_t nodes, T a,
+                                                           T b, T c) {
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < nodes; i += (size_t)gridDim.x * kRB) {
+    h[i] = a;
+    h[nodes + i] = b;
+    h[2 * nodes + i] = c;
+  }
+}
+
+template <typename T>
+hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream_t s) {
+  const int nb = (int)((nodes + kRB - 1) / kRB < 4096 ? (nodes + kRB - 1) / kRB : 4096);
+  hipLaunchKernelGGL((fill_uniform_kernel<T>), dim3(nb), dim3(kRB), 0, s, h, nodes, (T)he[0],
+                     (T)he[1], (T)he[2]);
+  return hipGetLastError();
+}
+
+// out = y + c1 k1 + c2 k2 + c3 k3; coefficients in T (FP32 path: the stage
+// combination is bulk arithmetic), terms with a null pointer are skipped.
+template <typename T>
+__global__ __launch_bounds__(kRB) void combo_kernel(T* __restrict__ out, const T* __restrict__ y,
+                                                    const T* __restrict__ k1, T c1,
+                                                    const T* __restrict__ k2, T c2,
+                                                    const T* __restrict__ k3, T c3, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
+    T v = y[i];
+    if (k1) v += c1 * k1[i];
+    if (k2) v += c2 * k2[i];
+    if (k3) v += c3 * k3[i];
+    out[i] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_combo(T* out, const T* y, const T* k1, double c1, const T* k2, double c2,
+                        const T* k3, double c3, size_t n, hipStream_t s) {
+  const size_t want = (n + kRB - 1) / kRB;
+  const int nb = (int)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL((combo_kernel<T>), dim3(nb), dim3(kRB), 0, s, out, y, k1, (T)c1, k2, (T)c2,
+                     k3, (T)c3, n);
+  return hipGetLastError();
+}
+
+// Error norm of the Bogacki-Shampine pair, FP64 regardless of T.
+template <typename T>
+__global__ __launch_bounds__(kRB) void errnorm_kernel(const T* __restrict__ y,
+                                                      const T* __restrict__ y1,
+                                                      const T* __restrict__ k1,
+                                                      const T* __restrict__ k2,
+                                                      const T* __restrict__ k3,
+                                                      const T* __restrict__ k4, double dt,
+                                                      double thr, size_t n,
+                                                      double* __restrict__ partials) {
+  __shared__ double sh[kRB];
+  const double e1 = -5.0 / 72.0, e2 = 1.0 / 12.0, e3 = 1.0 / 9.0, e4 = -1.0 / 8.0;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
+    const double E = dt * (e1 * (double)k1[i] + e2 * (double)k2[i] + e3 * (double)k3[i] +
+                           e4 * (double)k4[i]);
+    const double sc = fmax(fmax(fabs((double)y[i]), fabs((double)y1[i])), thr);
+    double r = fabs(E) / sc;
+    if (!(r == r) || isinf(r)) r = INFINITY;  // NaN or inf forces rejection
+    acc = fmax(acc, r);
+  }
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+template <typename T>
+hipError_t launch_errnorm(const T* y, const T* y1, const T* k1, const T* k2, const T* k3,
+                          const T* k4, double dt, double thr, size_t n, double* partials,
+                          int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((errnorm_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, y, y1, k1, k2, k3, k4,
+                     dt, thr, n, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void ratio_max_kernel(const T* __restrict__ a,
+                                                        const T* __restrict__ y, double thr,
+                                                        size_t n, double* __restrict__ partials) {
+  __shared__ double sh[kRB];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
+    double r = fabs((double)a[i]) / fmax(fabs((double)y[i]), thr);
+    if (!(r == r)) r = INFINITY;
+    acc = fmax(acc, r);
+  }
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+template <typename T>
+hipError_t launch_ratio_max(const T* a, const T* y, double thr, size_t n, double* partials,
+                            int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((ratio_max_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, a, y, thr, n, partials);
+  return hipGetLastError();
+}
+
+// partials[2b] = sum |h| over region nodes, partials[2b+1] = count.
+template <typename T>
+__global__ __launch_bounds__(kRB) void region_abs_kernel(const T* __restrict__ h,
+                                                         const uint8_t* __restrict__ region,
+                                                         size_t nodes, double* __restrict__ partials) {
+  __shared__ double sh[kRB];
+  double acc = 0.0, cnt = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < nodes; i += (size_t)gridDim.x * kRB) {
+    if (region[i]) {
+      const double a = h[i], b = h[nodes + i], c = h[2 * nodes + i];
+      acc += sqrt(a * a + b * b + c * c);
+      cnt += 1.0;
+    }
+  }
+  const double s = block_sum(acc, sh);
+  const double k = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = k;
+  }
+}
+
+template <typename T>
+hipError_t launch_region_abs(const T* h, const uint8_t* region, size_t nodes, double* partials,
+                             int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((region_abs_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, h, region, nodes,
+                     partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void probe_kernel(const T* __restrict__ h, int nx, int ny, int nz,
+                                                    const double* __restrict__ pts, int npts,
+                                                    double x0, double y0, double z0, double hx,
+                                                    double hy, double hz, double* __restrict__ out) {
+  const int p = blockIdx.x * kRB + threadIdx.x;
+  if (p >= npts) return;
+  const double s[3] = {(pts[3 * p] - x0) / hx, (pts[3 * p + 1] - y0) / hy, (pts[3 * p + 2] - z0) / hz};
+  const int nn[3] = {nx, ny, nz};
+  int i0[3];
+  double f[3];
+  for (int a = 0; a < 3; ++a) {
+    const double fl = floor(s[a]);
+    f[a] = s[a] - fl;
+    long long i = (long long)fl % nn[a];
+    if (i < 0) i += nn[a];
+    i0[a] = (int)i;
+  }
+  const size_t nodes = (size_t)nx * ny * nz;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+        const int ix = (i0[0] + dx) % nx, iy = (i0[1] + dy) % ny, iz = (i0[2] + dz) % nz;
+        const size_t idx = ((size_t)iz * ny + iy) * nx + ix;
+        for (int c = 0; c < 3; ++c) acc[c] += w * (double)h[c * nodes + idx];
+      }
+  for (int c = 0; c < 3; ++c) out[3 * p + c] = acc[c];
+}
+
+template <typename T>
+hipError_t launch_probe(const T* h, int nx, int ny, int nz, const double* pts, int npts, double x0,
+                        double y0, double z0, double hx, double hy, double hz, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((probe_kernel<T>), dim3((npts + kRB - 1) / kRB), dim3(kRB), 0, s, h, nx, ny,
+                     nz, pts, npts, x0, y0, z0, hx, hy, hz, out);
+  return hipGetLastError();
+}
+
+// dst = src on nodes outside Omega, 0 inside (warm start of iteration (5)).
+template <typename T>
+__global__ __launch_bounds__(kRB) void masked_copy_kernel(T* __restrict__ dst,
+                                                          const T* __restrict__ src,
+                                                          const uint8_t* __restrict__ chi,
+                                                          size_t nodes) {
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < nodes; i += (size_t)gridDim.x * kRB) {
+    const bool in = chi[i] != 0;
+    for (int c = 0; c < 3; ++c) dst[c * nodes + i] = in ? T(0) : src[c * nodes + i];
+  }
+}
+
+template <typename T>
+hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t nodes,
+                              hipStream_t s) {
+  const size_t want = (nodes + kRB - 1) / kRB;
+  const int nb = (int)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL((masked_copy_kernel<T>), dim3(nb), dim3(kRB), 0, s, dst, src, chi, nodes);
+  return hipGetLastError();
+}
+
+#define SCFFT_INST(T)                                                                          \
+  template hipError_t launch_fill_uniform<T>(T*, size_t, const double[3], hipStream_t);        \
+  template hipError_t launch_combo<T>(T*, const T*, const T*, double, const T*, double,        \
+                                      const T*, double, size_t, hipStream_t);                  \
+  template hipError_t launch_errnorm<T>(const T*, const T*, const T*, const T*, const T*,      \
+                                        const T*, double, double, size_t, double*, int,        \
+                                        hipStream_t);                                           \
+  template hipError_t launch_region_abs<T>(const T*, const uint8_t*, size_t, double*, int,     \
+                                           hipStream_t);                                        \
+  template hipError_t launch_probe<T>(const T*, int, int, int, const double*, int, double,     \
+                                      double, double, double, double, double, double*,         \
+                                      hipStream_t);                                             \
+  template hipError_t launch_masked_copy<T>(T*, const T*, const uint8_t*, size_t, hipStream_t); \
+  template hipError_t launch_ratio_max<T>(const T*, const T*, double, size_t, double*, int,     \
+                                          hipStream_t);
+SCFFT_INST(double)
+SCFFT_INST(float)
+#undef SCFFT_INST
+
+}  // namespace scfft

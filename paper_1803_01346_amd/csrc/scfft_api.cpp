@@ -1,0 +1,1012 @@
+// C-ABI layer of libscfft: argument checking, the workspace, the pass
+// schedule of the right-hand side, the device integrator and the readouts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scfft.h"
+#include "bs23.h"
+#include "host_model.h"
+#include "internal.h"
+
+using namespace scfft;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxDeltaSlots = 256;
+constexpr int kProbeChunk = 4096;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+struct scfft_ctx {
+  scfft_grid grid;
+  scfft_material mat;
+  scfft_precision prec;
+  hipStream_t stream;
+  int device;
+  int n[3];
+  size_t nodes;
+  double L[3];     // dimensionless half widths
+  double h[3];     // dimensionless cell sizes
+  Units u;
+  Drive drive;
+  bool has_drive = false;
+  scfft_rhs_opts opts;
+  double sigma;
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_main, off_nyq, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
+      off_clamp, off_ode, off_probe, total;
+  size_t wsize;  // element size
+  bool has_mask = false, has_kappa = false, has_warm = false;
+  int64_t n_in = 0, n_out = 0;
+  std::string err;
+  int64_t clamp_seen = 0;
+
+  // optional per-kernel timing with HIP events on the context stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;          // pairs: 2i (start), 2i+1 (stop)
+  std::vector<int> ev_kind;                 // kind of pending pair i
+  size_t ev_used = 0;
+  int64_t prof_launches[SCFFT_KERNEL_KINDS] = {};
+  double prof_ms[SCFFT_KERNEL_KINDS] = {};
+};
+
+namespace {
+
+scfft_status fail(scfft_ctx* c, scfft_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, SCFFT_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_));          \
+  } while (0)
+
+void layout(scfft_ctx* c) {
+  const size_t nodes = c->nodes;
+  const size_t w = c->wsize;
+  const size_t M = (size_t)c->n[0] / 2;
+  size_t o = 0;
+  c->off_main = o;  o = align_up(o + 3 * (size_t)c->n[2] * c->n[1] * M * 2 * w);
+  c->off_nyq = o;   o = align_up(o + 3 * (size_t)c->n[2] * c->n[1] * 2 * w);
+  c->off_warm = o;  o = align_up(o + 3 * nodes * w);
+  c->off_chi = o;   o = align_up(o + nodes);
+  c->off_kappa = o; o = align_up(o + nodes * w);
+  c->off_tab = o;
+  for (int a = 0; a < 3; ++a) o = align_up(o + (size_t)c->n[a] * (2 + 3) * w);
+  // partials: enough for the X pass (3 per block) and the streaming reductions
+  const size_t xb = (size_t)c->n[1] * c->n[2];  // rows: an upper bound of X-pass blocks
+  c->off_part = o;  o = align_up(o + std::max<size_t>(3 * xb, 2 * kReduceBlocks) * sizeof(double));
+  c->off_scal = o;  o = align_up(o + 16 * sizeof(double));
+  c->off_delta = o; o = align_up(o + kMaxDeltaSlots * sizeof(double));
+  c->off_clamp = o; o = align_up(o + sizeof(unsigned long long));
+  c->off_ode = o;   o = align_up(o + 5 * 3 * nodes * w);
+  c->off_probe = o; o = align_up(o + (size_t)kProbeChunk * 6 * sizeof(double));
+  c->total = o;
+}
+
+template <typename T>
+T* wsp(scfft_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
+
+template <typename T>
+Plan<T> make_plan(scfft_ctx* c) {
+  Plan<T> p;
+  p.nx = c->n[0];
+  p.ny = c->n[1];
+  p.nz = c->n[2];
+  p.main = wsp<C2<T>>(c, c->off_main);
+  p.nyq = wsp<C2<T>>(c, c->off_nyq);
+  size_t o = c->off_tab;
+  AxisTab<T>* tabs[3] = {&p.ax, &p.ay, &p.az};
+  for (int a = 0; a < 3; ++a) {
+    const size_t N = c->n[a];
+    tabs[a]->tw = wsp<C2<T>>(c, o);
+    tabs[a]->kodd = wsp<T>(c, o + N * 2 * sizeof(T));
+    tabs[a]->kk = wsp<T>(c, o + N * 3 * sizeof(T));
+    tabs[a]->sm = wsp<T>(c, o + N * 4 * sizeof(T));
+    o = align_up(o + N * 5 * sizeof(T));
+  }
+  return p;
+}
+
+// Axis tables in FP64 on the host (Sec. 2: wavenumbers on the box, Gaussian
+// smoothing with sigma = half the cell diagonal), converted to T.
+template <typename T>
+std::vector<char> build_tables(const scfft_ctx* c) {
+  std::vector<char> buf(c->off_part - c->off_tab, 0);
+  size_t o = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int N = c->n[a];
+    T* tw = reinterpret_cast<T*>(buf.data() + o);
+    T* kodd = tw + 2 * N;
+    T* kk = tw + 3 * N;
+    T* sm = tw + 4 * N;
+    for (int i = 0; i < N; ++i) {
+      const double ang = -2.0 * M_PI * (double)i / (double)N;
+      tw[2 * i] = (T)std::cos(ang);
+      tw[2 * i + 1] = (T)std::sin(ang);
+      const int m = i < N / 2 ? i : i - N;
+      const double k = M_PI * (double)m / c->L[a];
+      kodd[i] = (T)(i == N / 2 ? 0.0 : k);
+      kk[i] = (T)(k * k);
+      sm[i] = (T)std::exp(-0.5 * c->sigma * c->sigma * k * k);
+    }
+    o = align_up(o + (size_t)N * 5 * sizeof(T));
+  }
+  return buf;
+}
+
+bool ready(scfft_ctx* c, bool need_mask, scfft_status* st) {
+  if (!c->ws) {
+    *st = fail(c, SCFFT_ERR_WORKSPACE, "no workspace attached");
+    return false;
+  }
+  if (need_mask && !c->has_mask) {
+    *st = fail(c, SCFFT_ERR_GEOMETRY, "no mask: call scfft_voxelize or scfft_set_mask");
+    return false;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// the right-hand side: pass schedule
+// ---------------------------------------------------------------------------
+template <typename T>
+XArgs<T> base_args(scfft_ctx* c) {
+  XArgs<T> a;
+  std::memset(&a, 0, sizeof a);
+  a.chi = wsp<uint8_t>(c, c->off_chi);
+  a.kappa = c->has_kappa ? wsp<T>(c, c->off_kappa) : nullptr;
+  a.partials = wsp<double>(c, c->off_part);
+  a.clamps = wsp<unsigned long long>(c, c->off_clamp);
+  a.npow = (T)c->mat.n_power;
+  a.rho_out = (T)c->mat.rho_out;
+  a.expmax = sizeof(T) == 4 ? (T)80.0 : (T)700.0;
+  for (int d = 0; d < 3; ++d) {
+    a.pos0[d] = -c->L[d] + 0.5 * c->h[d];
+    a.step[d] = c->h[d];
+  }
+  return a;
+}
+
+// ---- per-kernel event timing (scfft_profile) ----
+hipError_t prof_harvest(scfft_ctx* c) {
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    hipError_t e = hipEventSynchronize(c->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    c->prof_ms[c->ev_kind[i]] += ms;
+    c->prof_launches[c->ev_kind[i]] += 1;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+hipError_t prof_begin(scfft_ctx* c, int kind) {
+  if (!c->prof) return hipSuccess;
+  if (2 * (c->ev_used + 1) > c->ev_pool.size()) {
+    hipError_t e = prof_harvest(c);  // waits for the pending launches
+    if (e != hipSuccess) return e;
+  }
+  c->ev_kind[c->ev_used] = kind;
+  return hipEventRecord(c->ev_pool[2 * c->ev_used], c->stream);
+}
+
+hipError_t prof_end(scfft_ctx* c, hipError_t launch_err) {
+  if (!c->prof || launch_err != hipSuccess) return launch_err;
+  hipError_t e = hipEventRecord(c->ev_pool[2 * c->ev_used + 1], c->stream);
+  ++c->ev_used;
+  return e;
+}
+
+template <typename T>
+hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
+  hipError_t e = prof_begin(c, SCFFT_KERNEL_X_FWD + op);
+  if (e != hipSuccess) return e;
+  return prof_end(c, launch_xpass<T>(p, op, a, c->stream));
+}
+
+template <typename T>
+hipError_t run_y(scfft_ctx* c, const Plan<T>& p, bool inv) {
+  hipError_t e = prof_begin(c, inv ? SCFFT_KERNEL_Y_INV : SCFFT_KERNEL_Y_FWD);
+  if (e != hipSuccess) return e;
+  return prof_end(c, launch_ypass<T>(p, inv, c->stream));
+}
+
+template <typename T>
+hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
+  hipError_t e = prof_begin(c, sym == Z_CURL ? SCFFT_KERNEL_Z_CURL : SCFFT_KERNEL_Z_PHI);
+  if (e != hipSuccess) return e;
+  return prof_end(c, launch_zpass<T>(p, sym, (T)coef, c->stream));
+}
+
+// Y forward, Z (symbol), Y inverse: the middle of one operator application.
+template <typename T>
+hipError_t spectral_middle(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
+  hipError_t e;
+  if ((e = run_y<T>(c, p, false)) != hipSuccess) return e;
+  if ((e = run_z<T>(c, p, sym, coef)) != hipSuccess) return e;
+  return run_y<T>(c, p, true);
+}
+
+template <typename T>
+scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_stats* stats) {
+  const Plan<T> p = make_plan<T>(c);
+  const hipStream_t s = c->stream;
+  const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
+  const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
+  double he[3], hedot[3];
+  c->drive.eval(t, he, hedot);
+  const double hedot_abs = std::sqrt(hedot[0] * hedot[0] + hedot[1] * hedot[1] + hedot[2] * hedot[2]);
+  const double tol = c->opts.delta_it * std::max(hedot_abs, 1.0);
+  const int xb = xpass_blocks<T>(p);
+
+  XArgs<T> a = base_args<T>(c);
+  for (int d = 0; d < 3; ++d) a.hedot[d] = (T)hedot[d];
+
+  // j = C_s h  (Eq. 4)
+  a.in = h;
+  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+  // e (Eq. 1; rho_out j outside), then -C_s e (Eq. 3)
+  HIPCHK(c, run_x<T>(c, p, X_LAW, a));
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, -norm));
+  // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out
+  a.out = hdot;
+  a.warm = c->has_warm ? wsp<T>(c, c->off_warm) : nullptr;
+  HIPCHK(c, run_x<T>(c, p, X_HIN, a));
+
+  // iteration (5)
+  const int fixed = c->opts.fixed_iter;
+  const int max_it = fixed > 0 ? fixed : c->opts.max_iter;
+  double* deltas = wsp<double>(c, c->off_delta);
+  int it = 0;
+  bool converged = false;
+  double last = 0.0;
+  for (;;) {
+    HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));      // jdot^i = C_s hdot^i
+    HIPCHK(c, run_x<T>(c, p, X_MASK, a));             // jdot_in^i
+    HIPCHK(c, spectral_middle<T>(c, p, phi_sym, norm));      // Phi[jdot_in^i]  (Eq. 7)
+    const bool last_known = it + 1 >= max_it;
+    HIPCHK(c, run_x<T>(c, p, last_known ? X_UPDATE_LAST : X_UPDATE, a));  // Eq. 5
+    HIPCHK(c, launch_sum_partials(a.partials, xb, 1, 1, deltas + (it % kMaxDeltaSlots), s));
+    ++it;
+    if (fixed > 0) {
+      if (it >= fixed) {
+        converged = true;
+        break;
+      }
+      continue;
+    }
+    double sum = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&sum, deltas + ((it - 1) % kMaxDeltaSlots), sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    last = c->n_out > 0 ? sum / (double)c->n_out : 0.0;
+    if (it >= c->opts.min_iter && last < tol) {
+      converged = true;
+      break;
+    }
+    if (it >= max_it) break;
+    if (last_known) break;
+  }
+  // warm start of the next call: hdot on Omega_out (only those nodes are read)
+  HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
+                           hipMemcpyDeviceToDevice, s));
+  c->has_warm = true;
+
+  scfft_status st = converged ? SCFFT_OK : SCFFT_WARN_NOT_CONVERGED;
+  if (stats || fixed <= 0) {
+    unsigned long long cl = 0;
+    HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
+                             hipMemcpyDeviceToHost, s));
+    if (fixed > 0) {
+      double sum = 0.0;
+      HIPCHK(c, hipMemcpyAsync(&sum, deltas + ((it - 1) % kMaxDeltaSlots), sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      last = c->n_out > 0 ? sum / (double)c->n_out : 0.0;
+    } else {
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+    const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
+    c->clamp_seen = (int64_t)cl;
+    if (stats) {
+      stats->iters = it;
+      stats->converged = converged ? 1 : 0;
+      stats->last_delta = last;
+      stats->clamps = new_clamps;
+    }
+    if (st == SCFFT_OK && new_clamps > 0) st = SCFFT_WARN_CLAMPED;
+  }
+  return st;
+}
+
+template <typename T>
+scfft_status apply_operator(scfft_ctx* c, const T* v, T* out, int sym, double sign) {
+  const Plan<T> p = make_plan<T>(c);
+  const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
+  XArgs<T> a = base_args<T>(c);
+  a.in = v;
+  a.out = out;
+  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+  HIPCHK(c, spectral_middle<T>(c, p, sym, sign * norm));
+  HIPCHK(c, run_x<T>(c, p, X_STORE, a));
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status moment_impl(scfft_ctx* c, const T* h, int omega_only, double m[3]) {
+  const Plan<T> p = make_plan<T>(c);
+  const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
+  XArgs<T> a = base_args<T>(c);
+  a.in = h;
+  a.omega_only = omega_only ? 1 : 0;
+  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+  HIPCHK(c, run_x<T>(c, p, X_MOMENT, a));
+  double* out = wsp<double>(c, c->off_scal);
+  HIPCHK(c, launch_sum_partials(a.partials, xpass_blocks<T>(p), 3, 3, out, c->stream));
+  double r[3];
+  HIPCHK(c, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double dv = c->h[0] * c->h[1] * c->h[2];
+  const double scale = c->u.jc * std::pow(c->u.l, 4.0);  // m' -> A m^2
+  for (int d = 0; d < 3; ++d) m[d] = 0.5 * r[d] * dv * scale;
+  return SCFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device integrator ops
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DeviceOps {
+  scfft_ctx* c;
+  T* buf[6];
+  scfft_observer obs;
+  void* user;
+  scfft_ode_stats* st;
+  scfft_status last_warn = SCFFT_OK;
+
+  int rhs(double t, Buf src, Buf dst) {
+    scfft_rhs_stats rs;
+    scfft_status s = rhs_impl<T>(c, t, buf[src], buf[dst], c->opts.fixed_iter > 0 ? nullptr : &rs);
+    if (s < 0) return s;
+    if (c->opts.fixed_iter > 0) {
+      st->iters_total += c->opts.fixed_iter;
+    } else {
+      st->iters_total += rs.iters;
+      if (!rs.converged) st->not_converged += 1;
+      st->clamps += rs.clamps;
+    }
+    if (s > 0) last_warn = s;
+    return 0;
+  }
+  int combo(Buf out, Buf y, Buf a, double ca, Buf b, double cb, Buf cc_, double cc) {
+    hipError_t e = launch_combo<T>(buf[out], buf[y], a >= 0 ? buf[a] : nullptr, ca,
+                                   b >= 0 ? buf[b] : nullptr, cb, cc_ >= 0 ? buf[cc_] : nullptr, cc,
+                                   3 * c->nodes, c->stream);
+    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "combo: %s", hipGetErrorString(e));
+  }
+  int errnorm(Buf y, Buf y1, double dt, double thr, double* err) {
+    double* part = wsp<double>(c, c->off_part);
+    double* out = wsp<double>(c, c->off_scal);
+    hipError_t e = launch_errnorm<T>(buf[y], buf[y1], buf[B_K1], buf[B_K2], buf[B_K3], buf[B_K4],
+                                     dt, thr, 3 * c->nodes, part, kReduceBlocks, c->stream);
+    if (e == hipSuccess) e = launch_max_partials(part, kReduceBlocks, out, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(err, out, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "errnorm: %s", hipGetErrorString(e));
+  }
+  int rate(double thr, double* r) {
+    double* part = wsp<double>(c, c->off_part);
+    double* out = wsp<double>(c, c->off_scal);
+    hipError_t e = launch_ratio_max<T>(buf[B_K1], buf[B_Y], thr, 3 * c->nodes, part,
+                                       kReduceBlocks, c->stream);
+    if (e == hipSuccess) e = launch_max_partials(part, kReduceBlocks, out, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, out, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "rate: %s", hipGetErrorString(e));
+  }
+  int accept() {
+    hipError_t e = hipMemcpyAsync(buf[B_Y], buf[B_Y1], 3 * c->nodes * sizeof(T),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    std::swap(buf[B_K1], buf[B_K4]);
+    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "accept: %s", hipGetErrorString(e));
+  }
+  int observe(double t, int* stop) {
+    *stop = 0;
+    if (obs) *stop = obs(user, t * c->u.t0, buf[B_Y]);
+    return 0;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host test integrator ops
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HostOps {
+  int64_t n;
+  std::vector<double> b[6];
+  double* y;
+  scfft_host_rhs f;
+  void* user;
+  double* bp(Buf k) { return k == B_Y ? y : b[k].data(); }
+  int rhs(double t, Buf src, Buf dst) {
+    return f(user, t, bp(src), bp(dst)) == 0 ? 0 : SCFFT_ERR_ARG;
+  }
+  int combo(Buf out, Buf yy, Buf a, double ca, Buf bb, double cb, Buf cc_, double cc) {
+    double *o = bp(out), *py = bp(yy);
+    double* pa = a >= 0 ? bp(a) : nullptr;
+    double* pb = bb >= 0 ? bp(bb) : nullptr;
+    double* pc = cc_ >= 0 ? bp(cc_) : nullptr;
+    for (int64_t i = 0; i < n; ++i) {
+      double v = py[i];
+      if (pa) v += ca * pa[i];
+      if (pb) v += cb * pb[i];
+      if (pc) v += cc * pc[i];
+      o[i] = v;
+    }
+    return 0;
+  }
+  int errnorm(Buf yy, Buf y1, double dt, double thr, double* err) {
+    const double e1 = -5.0 / 72.0, e2 = 1.0 / 12.0, e3 = 1.0 / 9.0, e4 = -1.0 / 8.0;
+    double m = 0.0;
+    double *k1 = bp(B_K1), *k2 = bp(B_K2), *k3 = bp(B_K3), *k4 = bp(B_K4), *p = bp(yy), *q = bp(y1);
+    for (int64_t i = 0; i < n; ++i) {
+      const double E = dt * (e1 * k1[i] + e2 * k2[i] + e3 * k3[i] + e4 * k4[i]);
+      double r = std::fabs(E) / std::max(std::max(std::fabs(p[i]), std::fabs(q[i])), thr);
+      if (!std::isfinite(r)) r = INFINITY;
+      m = std::max(m, r);
+    }
+    *err = m;
+    return 0;
+  }
+  int rate(double thr, double* r) {
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs(b[B_K1][i]) / std::max(std::fabs(y[i]), thr));
+    *r = m;
+    return 0;
+  }
+  int accept() {
+    std::copy(b[B_Y1].begin(), b[B_Y1].end(), y);
+    std::swap(b[B_K1], b[B_K4]);
+    return 0;
+  }
+  int observe(double, int* stop) {
+    *stop = 0;
+    return 0;
+  }
+};
+
+bool valid_ode_opts(const scfft_ode_opts* o) {
+  return o && o->rtol > 0.0 && o->atol > 0.0 && o->dt0_s >= 0.0 && o->dt_max_s >= 0.0 &&
+         o->fixed_steps >= 0 && o->n_bp >= 0 && (o->n_bp == 0 || o->breakpoints_s) &&
+         o->max_steps >= 0;
+}
+
+template <typename T>
+scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scfft_ode_opts* o,
+                            scfft_observer obs, void* user, scfft_ode_stats* st) {
+  DeviceOps<T> ops;
+  ops.c = c;
+  ops.buf[B_Y] = h;
+  for (int k = 1; k < 6; ++k) ops.buf[k] = wsp<T>(c, c->off_ode + (size_t)(k - 1) * 3 * c->nodes * sizeof(T));
+  ops.obs = obs;
+  ops.user = user;
+  ops.st = st;
+  scfft_ode_opts od = *o;  // convert times to t' = t / t0
+  od.dt0_s = o->dt0_s / c->u.t0;
+  od.dt_max_s = o->dt_max_s / c->u.t0;
+  std::vector<double> stops = c->drive.kinks();
+  for (int i = 0; i < o->n_bp; ++i) stops.push_back(o->breakpoints_s[i] / c->u.t0);
+  scfft_status s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
+  st->t_s *= c->u.t0;
+  st->dt_last_s *= c->u.t0;
+  if (s == SCFFT_OK && st->not_converged > 0) s = SCFFT_WARN_NOT_CONVERGED;
+  return s;
+}
+
+template <typename T>
+scfft_status region_impl(scfft_ctx* c, const T* h, const uint8_t* region, double* b) {
+  double* part = wsp<double>(c, c->off_part);
+  double* out = wsp<double>(c, c->off_scal);
+  HIPCHK(c, launch_region_abs<T>(h, region, c->nodes, part, kReduceBlocks, c->stream));
+  HIPCHK(c, launch_sum_partials(part, kReduceBlocks, 2, 2, out, c->stream));
+  double r[2];
+  HIPCHK(c, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *b = r[1] > 0 ? r[0] / r[1] * c->u.h_scale * kMu0 : 0.0;
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status probe_impl(scfft_ctx* c, const T* h, const double* xyz, int npts, double* b) {
+  double* dpts = wsp<double>(c, c->off_probe);
+  double* dout = dpts + 3 * kProbeChunk;
+  std::vector<double> pts;
+  for (int p0 = 0; p0 < npts; p0 += kProbeChunk) {
+    const int np = std::min(kProbeChunk, npts - p0);
+    pts.assign(xyz + 3 * (size_t)p0, xyz + 3 * (size_t)(p0 + np));
+    for (double& v : pts) v /= c->u.l;
+    HIPCHK(c, hipMemcpyAsync(dpts, pts.data(), pts.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_probe<T>(h, c->n[0], c->n[1], c->n[2], dpts, np, -c->L[0] + 0.5 * c->h[0],
+                              -c->L[1] + 0.5 * c->h[1], -c->L[2] + 0.5 * c->h[2], c->h[0], c->h[1],
+                              c->h[2], dout, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + 3 * (size_t)p0, dout, 3 * (size_t)np * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  const double s = c->u.h_scale * kMu0;
+  for (int i = 0; i < 3 * npts; ++i) b[i] *= s;
+  return SCFFT_OK;
+}
+
+scfft_status set_mask_host(scfft_ctx* c, const std::vector<uint8_t>& m) {
+  HIPCHK(c, hipMemcpyAsync(wsp<uint8_t>(c, c->off_chi), m.data(), c->nodes, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int64_t in = 0;
+  for (uint8_t v : m) in += v != 0;
+  c->n_in = in;
+  c->n_out = (int64_t)c->nodes - in;
+  c->has_mask = true;
+  c->has_warm = false;
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status upload_tables(scfft_ctx* c) {
+  std::vector<char> t = build_tables<T>(c);
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_tab, t.data(), t.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_clamp, 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->clamp_seen = 0;
+  return SCFFT_OK;
+}
+
+struct StateHeader {
+  uint64_t magic;
+  int32_t version, prec, n[3], has_warm;
+  scfft_rhs_opts opts;
+  uint64_t warm_bytes;
+};
+const uint64_t kStateMagic = 0x5343464654535431ull;  // "SCFFTST1"
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void scfft_default_rhs_opts(scfft_rhs_opts* o) {
+  if (!o) return;
+  o->delta_it = 2e-5;
+  o->min_iter = 1;
+  o->max_iter = 200;
+  o->fixed_iter = 0;
+  o->smooth_phi = 0;
+  o->sigma_scale = 1.0;
+}
+
+void scfft_default_ode_opts(scfft_ode_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->rtol = 2e-4;
+  o->atol = 1e-6;
+}
+
+scfft_status scfft_units(const scfft_material* m, double* t0_s, double* h_scale) {
+  const char* why = nullptr;
+  if (!m || !t0_s || !h_scale || !validate_material(*m, &why)) return SCFFT_ERR_ARG;
+  Units u = make_units(*m);
+  *t0_s = u.t0;
+  *h_scale = u.h_scale;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_drive_eval(const scfft_drive* d, const scfft_material* m, double t_s,
+                              double he[3], double hedot[3]) {
+  const char* why = nullptr;
+  if (!d || !m || !he || !hedot || !validate_material(*m, &why)) return SCFFT_ERR_ARG;
+  Units u = make_units(*m);
+  Drive dr;
+  if (!dr.set(*d, u, &why)) return SCFFT_ERR_ARG;
+  dr.eval(t_s / u.t0, he, hedot);
+  return SCFFT_OK;
+}
+
+scfft_status scfft_voxelize_host(const scfft_grid* g, const scfft_material* m,
+                                 const scfft_shape* shapes, int32_t n_shapes, uint8_t* mask) {
+  const char* why = nullptr;
+  if (!g || !m || !mask || !validate_material(*m, &why) || !validate_shapes(shapes, n_shapes, &why))
+    return SCFFT_ERR_ARG;
+  double hw[3];
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] < 2 || g->n[a] > 4096 || !(g->half_width_m[a] > 0.0)) return SCFFT_ERR_SHAPE;
+    hw[a] = g->half_width_m[a] / m->l_char_m;
+  }
+  voxelize(g->n, hw, m->l_char_m, shapes, n_shapes, mask);
+  return SCFFT_OK;
+}
+
+scfft_status scfft_bs23_host(int64_t n, double* y, double t0, double t1, scfft_host_rhs f,
+                             void* user, const scfft_ode_opts* o, scfft_ode_stats* st) {
+  if (n <= 0 || !y || !f || !valid_ode_opts(o) || !st || !(t1 > t0)) return SCFFT_ERR_ARG;
+  std::memset(st, 0, sizeof *st);
+  HostOps ops;
+  ops.n = n;
+  for (auto& v : ops.b) v.assign((size_t)n, 0.0);
+  ops.y = y;
+  ops.f = f;
+  ops.user = user;
+  std::vector<double> stops(o->breakpoints_s, o->breakpoints_s + o->n_bp);
+  return bs23_run(ops, t0, t1, *o, stops, *st);
+}
+
+scfft_status scfft_create(scfft_ctx** out, const scfft_grid* g, const scfft_material* m,
+                          scfft_precision prec, void* hip_stream) {
+  if (!out || !g || !m) return SCFFT_ERR_ARG;
+  *out = nullptr;
+  const char* why = nullptr;
+  if (!validate_material(*m, &why)) return SCFFT_ERR_ARG;
+  if (prec != SCFFT_F64 && prec != SCFFT_F32) return SCFFT_ERR_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (!pow2_in_range(g->n[a])) return SCFFT_ERR_SHAPE;
+    if (!(g->half_width_m[a] > 0.0) || !std::isfinite(g->half_width_m[a])) return SCFFT_ERR_ARG;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return SCFFT_ERR_DEVICE;
+  scfft_ctx* c = new scfft_ctx();
+  c->grid = *g;
+  c->mat = *m;
+  c->prec = prec;
+  c->stream = (hipStream_t)hip_stream;
+  c->device = dev;
+  c->nodes = 1;
+  for (int a = 0; a < 3; ++a) {
+    c->n[a] = g->n[a];
+    c->nodes *= (size_t)g->n[a];
+    c->L[a] = g->half_width_m[a] / m->l_char_m;
+    c->h[a] = 2.0 * c->L[a] / g->n[a];
+  }
+  c->u = make_units(*m);
+  scfft_default_rhs_opts(&c->opts);
+  c->sigma = 0.5 * std::sqrt(c->h[0] * c->h[0] + c->h[1] * c->h[1] + c->h[2] * c->h[2]);
+  c->wsize = prec == SCFFT_F64 ? sizeof(double) : sizeof(float);
+  layout(c);
+  *out = c;
+  return SCFFT_OK;
+}
+
+void scfft_destroy(scfft_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+scfft_status scfft_workspace_size(const scfft_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return SCFFT_ERR_ARG;
+  *bytes = ctx->total;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (!dev_ptr) return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace pointer is NULL");
+  if (bytes < ctx->total)
+    return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, ctx->total);
+  if (((uintptr_t)dev_ptr) % kAlign)
+    return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+  ctx->ws = (char*)dev_ptr;
+  ctx->ws_bytes = bytes;
+  ctx->has_mask = ctx->has_kappa = ctx->has_warm = false;
+  // the sigma of the context may have been rescaled by options; rebuild tables
+  return ctx->prec == SCFFT_F64 ? upload_tables<double>(ctx) : upload_tables<float>(ctx);
+}
+
+scfft_status scfft_voxelize(scfft_ctx* ctx, const scfft_shape* shapes, int32_t n_shapes) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  const char* why = nullptr;
+  if (!validate_shapes(shapes, n_shapes, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
+  std::vector<uint8_t> m(ctx->nodes);
+  voxelize(ctx->n, ctx->L, ctx->mat.l_char_m, shapes, n_shapes, m.data());
+  return set_mask_host(ctx, m);
+}
+
+scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!dev_mask) return fail(ctx, SCFFT_ERR_ARG, "mask pointer is NULL");
+  std::vector<uint8_t> m(ctx->nodes);
+  HIPCHK(ctx, hipMemcpyAsync(m.data(), dev_mask, ctx->nodes, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return set_mask_host(ctx, m);
+}
+
+scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!dev_kappa) {
+    ctx->has_kappa = false;
+    return SCFFT_OK;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->off_kappa, dev_kappa, ctx->nodes * ctx->wsize,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->has_kappa = true;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
+  if (!ctx || !d) return SCFFT_ERR_ARG;
+  const char* why = nullptr;
+  Drive dr;
+  if (!dr.set(*d, ctx->u, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
+  ctx->drive = dr;
+  ctx->has_drive = true;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
+  if (!ctx || !o) return SCFFT_ERR_ARG;
+  if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
+      !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter)
+    return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");
+  const bool resigma = o->sigma_scale != ctx->opts.sigma_scale;
+  ctx->opts = *o;
+  if (resigma) {
+    ctx->sigma = o->sigma_scale * 0.5 *
+                 std::sqrt(ctx->h[0] * ctx->h[0] + ctx->h[1] * ctx->h[1] + ctx->h[2] * ctx->h[2]);
+    if (ctx->ws) return ctx->prec == SCFFT_F64 ? upload_tables<double>(ctx) : upload_tables<float>(ctx);
+  }
+  return SCFFT_OK;
+}
+
+scfft_status scfft_reset_warm(scfft_ctx* ctx) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  ctx->has_warm = false;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_init_state(scfft_ctx* ctx, double t0_s, void* h_dev) {
+  if (!ctx || !h_dev) return SCFFT_ERR_ARG;
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  double he[3], hd[3];
+  ctx->drive.eval(t0_s / ctx->u.t0, he, hd);
+  hipError_t e = ctx->prec == SCFFT_F64
+                     ? launch_fill_uniform<double>((double*)h_dev, ctx->nodes, he, ctx->stream)
+                     : launch_fill_uniform<float>((float*)h_dev, ctx->nodes, he, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, SCFFT_ERR_DEVICE, "init_state: %s", hipGetErrorString(e));
+  ctx->has_warm = false;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_rhs_eval(scfft_ctx* ctx, double t_s, const void* h_dev, void* hdot_dev,
+                            scfft_rhs_stats* stats) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!h_dev || !hdot_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  if (h_dev == hdot_dev) return fail(ctx, SCFFT_ERR_ARG, "h and hdot must not alias");
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  const double t = t_s / ctx->u.t0;
+  return ctx->prec == SCFFT_F64
+             ? rhs_impl<double>(ctx, t, (const double*)h_dev, (double*)hdot_dev, stats)
+             : rhs_impl<float>(ctx, t, (const float*)h_dev, (float*)hdot_dev, stats);
+}
+
+scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_dev,
+                             const scfft_ode_opts* o, scfft_observer obs, void* user,
+                             scfft_ode_stats* stats) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!h_dev || !valid_ode_opts(o) || !(t1_s > t0_s))
+    return fail(ctx, SCFFT_ERR_ARG, "invalid integrate arguments");
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  scfft_ode_stats local;
+  scfft_ode_stats* s = stats ? stats : &local;
+  std::memset(s, 0, sizeof *s);
+  return ctx->prec == SCFFT_F64
+             ? integrate_impl<double>(ctx, t0_s, t1_s, (double*)h_dev, o, obs, user, s)
+             : integrate_impl<float>(ctx, t0_s, t1_s, (float*)h_dev, o, obs, user, s);
+}
+
+scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!v_dev || !out_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  return ctx->prec == SCFFT_F64
+             ? apply_operator<double>(ctx, (const double*)v_dev, (double*)out_dev, Z_CURL, 1.0)
+             : apply_operator<float>(ctx, (const float*)v_dev, (float*)out_dev, Z_CURL, 1.0);
+}
+
+scfft_status scfft_phi(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!v_dev || !out_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  const int sym = ctx->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
+  return ctx->prec == SCFFT_F64
+             ? apply_operator<double>(ctx, (const double*)v_dev, (double*)out_dev, sym, 1.0)
+             : apply_operator<float>(ctx, (const float*)v_dev, (float*)out_dev, sym, 1.0);
+}
+
+scfft_status scfft_current(scfft_ctx* ctx, const void* h_dev, void* j_dev) {
+  return scfft_curl(ctx, h_dev, j_dev);
+}
+
+scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only, double m_Am2[3]) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, omega_only != 0, &st)) return st;
+  if (!h_dev || !m_Am2) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  return ctx->prec == SCFFT_F64 ? moment_impl<double>(ctx, (const double*)h_dev, omega_only, m_Am2)
+                                : moment_impl<float>(ctx, (const float*)h_dev, omega_only, m_Am2);
+}
+
+scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const uint8_t* dev_region,
+                                     double* b_T) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!h_dev || !dev_region || !b_T) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  return ctx->prec == SCFFT_F64 ? region_impl<double>(ctx, (const double*)h_dev, dev_region, b_T)
+                                : region_impl<float>(ctx, (const float*)h_dev, dev_region, b_T);
+}
+
+scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_m, int32_t npts,
+                           double* b_T) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  if (!h_dev || npts < 0 || (npts > 0 && (!xyz_m || !b_T)))
+    return fail(ctx, SCFFT_ERR_ARG, "invalid probe arguments");
+  for (int i = 0; i < 3 * npts; ++i)
+    if (!std::isfinite(xyz_m[i])) return fail(ctx, SCFFT_ERR_ARG, "non-finite probe point");
+  if (npts == 0) return SCFFT_OK;
+  return ctx->prec == SCFFT_F64 ? probe_impl<double>(ctx, (const double*)h_dev, xyz_m, npts, b_T)
+                                : probe_impl<float>(ctx, (const float*)h_dev, xyz_m, npts, b_T);
+}
+
+scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes) {
+  if (!ctx || !bytes) return SCFFT_ERR_ARG;
+  const size_t wb = ctx->has_warm ? 3 * ctx->nodes * ctx->wsize : 0;
+  const size_t need = sizeof(StateHeader) + wb;
+  if (!blob) {
+    *bytes = need;
+    return SCFFT_OK;
+  }
+  if (*bytes < need) return fail(ctx, SCFFT_ERR_ARG, "state blob needs %zu bytes", need);
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  hd.magic = kStateMagic;
+  hd.version = 1;
+  hd.prec = ctx->prec;
+  for (int a = 0; a < 3; ++a) hd.n[a] = ctx->n[a];
+  hd.has_warm = ctx->has_warm ? 1 : 0;
+  hd.opts = ctx->opts;
+  hd.warm_bytes = wb;
+  std::memcpy(blob, &hd, sizeof hd);
+  if (wb) {
+    HIPCHK(ctx, hipMemcpyAsync((char*)blob + sizeof hd, ctx->ws + ctx->off_warm, wb,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  *bytes = need;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes) {
+  if (!ctx || !blob) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, false, &st)) return st;
+  StateHeader hd;
+  if (bytes < sizeof hd) return fail(ctx, SCFFT_ERR_STATE, "state blob too short");
+  std::memcpy(&hd, blob, sizeof hd);
+  if (hd.magic != kStateMagic || hd.version != 1)
+    return fail(ctx, SCFFT_ERR_STATE, "not an scfft state blob");
+  if (hd.prec != ctx->prec || hd.n[0] != ctx->n[0] || hd.n[1] != ctx->n[1] || hd.n[2] != ctx->n[2])
+    return fail(ctx, SCFFT_ERR_STATE, "state blob is for another grid or precision");
+  const size_t wb = hd.has_warm ? 3 * ctx->nodes * ctx->wsize : 0;
+  if (hd.warm_bytes != wb || bytes < sizeof hd + wb)
+    return fail(ctx, SCFFT_ERR_STATE, "state blob size mismatch");
+  scfft_status s = scfft_set_rhs_opts(ctx, &hd.opts);
+  if (s != SCFFT_OK) return s;
+  if (wb) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->off_warm, (const char*)blob + sizeof hd, wb,
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  ctx->has_warm = hd.has_warm != 0;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (enable) {
+    if (ctx->ev_pool.empty()) {
+      const size_t pairs = 4096;
+      ctx->ev_pool.resize(2 * pairs);
+      ctx->ev_kind.resize(pairs);
+      for (auto& e : ctx->ev_pool) HIPCHK(ctx, hipEventCreate(&e));
+    }
+    for (int k = 0; k < SCFFT_KERNEL_KINDS; ++k) {
+      ctx->prof_launches[k] = 0;
+      ctx->prof_ms[k] = 0.0;
+    }
+    ctx->ev_used = 0;
+    ctx->prof = true;
+  } else {
+    HIPCHK(ctx, prof_harvest(ctx));
+    ctx->prof = false;
+  }
+  return SCFFT_OK;
+}
+
+scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KINDS],
+                                double total_ms[SCFFT_KERNEL_KINDS]) {
+  if (!ctx || !launches || !total_ms) return SCFFT_ERR_ARG;
+  HIPCHK(ctx, prof_harvest(ctx));
+  for (int k = 0; k < SCFFT_KERNEL_KINDS; ++k) {
+    launches[k] = ctx->prof_launches[k];
+    total_ms[k] = ctx->prof_ms[k];
+  }
+  return SCFFT_OK;
+}
+
+const char* scfft_status_string(scfft_status s) {
+  switch (s) {
+    case SCFFT_OK: return "ok";
+    case SCFFT_WARN_NOT_CONVERGED: return "warning: exterior iteration did not converge";
+    case SCFFT_WARN_CLAMPED: return "warning: power-law exponent clamped";
+    case SCFFT_ERR_ARG: return "invalid argument";
+    case SCFFT_ERR_SHAPE: return "unsupported grid size";
+    case SCFFT_ERR_DEVICE: return "device error";
+    case SCFFT_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case SCFFT_ERR_NAN: return "non-finite values";
+    case SCFFT_ERR_STEP_UNDERFLOW: return "step size underflow";
+    case SCFFT_ERR_GEOMETRY: return "geometry / mask missing";
+    case SCFFT_ERR_STATE: return "state blob does not fit";
+  }
+  return "unknown status";
+}
+
+const char* scfft_last_error(const scfft_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"

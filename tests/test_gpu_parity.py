@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  FP64 path: operators <= 1e-12, right-hand side and
+trajectories <= 1e-10 (relative to the largest reference value); FP32 path
+<= 1e-4 relative L2."""
+import numpy as np
+import pytest
+
+from gpu_case import oracle_problem, rel_l2, rel_max, sim, small_cfg, state, to_dev
+from oracle import operators, readouts, rhs as orhs
+from paper_1803_01346_amd import scfft, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CUBE32 = workloads.config("cube32")
+NONCUBIC = small_cfg((16, 32, 64), (1.5, 2.0, 3.0), workloads.shape_cup(1.0, 0.6, 3.0, 0.4, axis=1))
+TINY = small_cfg((8, 8, 8), (1.0, 1.0, 1.0), workloads.shape_cube(0.5))
+FLAT = small_cfg((64, 16, 8), (4.0, 1.0, 1.0), workloads.shape_cylinder(0.6, 1.2, axis=0))
+CUP64 = workloads.config("cup64")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    scfft.load()
+
+
+@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, FLAT, CUBE32, CUP64], ids=["8", "16x32x64", "64x16x8", "32", "64"])
+def test_curl_and_phi_fp64(cfg):
+    s = sim(cfg)
+    g, _ = oracle_problem(cfg)
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=s.field_shape)               # full-band input, Nyquist included
+    dv = to_dev(torch, v, torch.float64)
+    out = s.empty_field()
+    scfft.scfft_curl(s.ctx, dv, out)
+    torch.cuda.synchronize()
+    want = operators.curl_s(v, g.grid)
+    assert rel_max(_np(out), want) < 1e-12
+    scfft.scfft_phi(s.ctx, dv, out)
+    torch.cuda.synchronize()
+    want = operators.phi(v, g.grid)
+    assert rel_max(_np(out), want) < 1e-12
+
+
+def test_curl_and_phi_fp64_128():
+    cfg = workloads.config("cup128")
+    s = sim(cfg)
+    g, _ = oracle_problem(cfg)
+    v = state(cfg, seed=3)
+    dv = to_dev(torch, v, torch.float64)
+    out = s.empty_field()
+    scfft.scfft_curl(s.ctx, dv, out)
+    torch.cuda.synchronize()
+    assert rel_max(_np(out), operators.curl_s(v, g.grid)) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, CUBE32, CUP64], ids=["8", "16x32x64", "32", "64"])
+def test_rhs_fixed_iter_fp64(cfg):
+    s = sim(cfg, fixed_iter=3)
+    prob, u = oracle_problem(cfg, fixed_iter=3)
+    h = state(cfg, seed=2)
+    dh = to_dev(torch, h, torch.float64)
+    for t_s in (0.25, 0.3):                            # second call uses the warm start
+        out, st = s.rhs_eval(t_s, dh)
+        torch.cuda.synchronize()
+        want = orhs.rhs_eval(prob, t_s / u.t0, h)
+        assert rel_max(_np(out), want) < 1e-10, t_s
+
+
+@pytest.mark.parametrize("cfg", [NONCUBIC, CUBE32], ids=["16x32x64", "32"])
+def test_rhs_adaptive_fp64(cfg):
+    s = sim(cfg, delta_it=2e-5)
+    prob, u = oracle_problem(cfg, delta_it=2e-5)
+    h = state(cfg, seed=4)
+    dh = to_dev(torch, h, torch.float64)
+    for t_s in (0.2, 0.21, 0.22):
+        stats = scfft.RhsStats()
+        out, rc = s.rhs_eval(t_s, dh, stats=stats)
+        want = orhs.rhs_eval(prob, t_s / u.t0, h)
+        assert stats.iters == prob.last_iters
+        assert abs(stats.last_delta - prob.last_deltas[-1]) <= 1e-9 * prob.last_deltas[-1]
+        assert rel_max(_np(out), want) < 1e-10
+
+
+def test_rhs_fp32_within_1e4():
+    cfg = CUP64
+    s = sim(cfg, precision=scfft.F32, fixed_iter=3)
+    prob, u = oracle_problem(cfg, fixed_iter=3)
+    h = state(cfg, seed=5)
+    out, _ = s.rhs_eval(0.004, to_dev(torch, h, torch.float32))
+    torch.cuda.synchronize()
+    want = orhs.rhs_eval(prob, 0.004 / u.t0, h)
+    assert rel_l2(_np(out), want) < 1e-4
+
+
+def test_rhs_is_odd_bitwise_on_gpu():
+    cfg = CUP64
+    s1 = sim(cfg, fixed_iter=3)
+    cfg2 = dict(cfg, drive=dict(cfg["drive"], direction=tuple(-v for v in cfg["drive"]["direction"])))
+    s2 = sim(cfg2, fixed_iter=3)
+    h = to_dev(torch, state(cfg, seed=6), torch.float64)
+    a, _ = s1.rhs_eval(0.003, h)
+    b, _ = s2.rhs_eval(0.003, -h)
+    torch.cuda.synchronize()
+    assert torch.equal(b, -a)
+
+
+def test_readouts_fp64():
+    cfg = CUBE32
+    s = sim(cfg)
+    prob, u = oracle_problem(cfg)
+    # a localized field (Gaussian window) so the moment is far above round-off
+    x, y, z = prob.grid.mesh_nodes()
+    h = state(cfg, seed=7) * np.exp(-(x * x + y * y + z * z) / 0.8)
+    dh = to_dev(torch, h, torch.float64)
+    for omega_only in (0, 1):
+        m = scfft.scfft_moment(s.ctx, dh, omega_only)
+        mo = readouts.moment(prob.grid, prob.chi, h, omega_only=bool(omega_only))
+        mo_si = u.moment_dimless_to_Am2(mo)
+        assert np.allclose(m, mo_si, rtol=1e-10, atol=1e-12 * np.max(np.abs(mo_si)))
+    region = to_dev(torch, prob.chi, torch.uint8)
+    b = scfft.scfft_region_mean_abs_b(s.ctx, dh, region)
+    bo = u.field_dimless_to_T(readouts.region_mean_abs(h, prob.chi))
+    assert abs(b - bo) <= 1e-12 * bo
+    pts = np.array([[0.0, 0.0, 0.0], [1e-3, -2e-3, 3e-3], [0.009, 0.0, -0.0095]])
+    pb = scfft.scfft_probe_b(s.ctx, dh, pts)
+    po = u.field_dimless_to_T(readouts.probe(prob.grid, h, pts / cfg["l_m"]))
+    assert np.allclose(pb, po, rtol=1e-12, atol=1e-15)
+
+
+def test_init_state_and_virgin_rhs():
+    cfg = CUBE32
+    s = sim(cfg, fixed_iter=4)
+    prob, u = oracle_problem(cfg, fixed_iter=4)
+    h = s.empty_field()
+    scfft.scfft_init_state(s.ctx, 0.5, h)
+    he = prob.drive.he(0.5 / u.t0)
+    assert np.allclose(_np(h), np.broadcast_to(he.reshape(3, 1, 1, 1), h.shape), rtol=1e-15)
+    out, _ = s.rhs_eval(0.5, h)
+    want = orhs.rhs_eval(prob, 0.5 / u.t0, _np(h))
+    assert rel_max(_np(out), want) < 1e-10
+
+
+def test_integrate_fixed_steps_fp64():
+    cfg = dict(CUBE32, n_power=20.0)
+    s = sim(cfg, fixed_iter=2)
+    prob, u = oracle_problem(cfg, fixed_iter=2)
+    h = s.empty_field()
+    scfft.scfft_init_state(s.ctx, 0.0, h)
+    o = scfft.default_ode_opts(fixed_steps=6)
+    st = scfft.OdeStats()
+    ms = []
+    scfft.scfft_integrate(s.ctx, 0.0, 0.02, h, o, observer=lambda u_, t, p: ms.append(t) or 0, stats=st)
+    torch.cuda.synchronize()
+    from oracle import ode
+    f = lambda t, y: orhs.rhs_eval(prob, t, y)
+    y, so = ode.integrate(f, 0.0, 0.02 / u.t0, np.zeros((3,) + prob.grid.shape), fixed_steps=6)
+    assert st.accepted == 6 and st.rhs_calls == so.rhs_calls and len(ms) == 6
+    assert rel_max(_np(h), y) < 1e-10
+
+
+def test_integrate_adaptive_fp64_agrees_with_oracle():
+    cfg = small_cfg((16, 16, 16), (2.0, 2.0, 2.0), workloads.shape_cube(1.0), n_power=20.0,
+                    drive=dict(kind="ramp_hold", direction=(0, 0, 1), amp_T=0.1, t_ramp_s=1.0))
+    s = sim(cfg)
+    prob, u = oracle_problem(cfg)
+    h = s.empty_field()
+    scfft.scfft_init_state(s.ctx, 0.0, h)
+    o = scfft.default_ode_opts()
+    st = scfft.OdeStats()
+    scfft.scfft_integrate(s.ctx, 0.0, 1.5, h, o, stats=st)
+    from oracle import ode
+    f = lambda t, y: orhs.rhs_eval(prob, t, y)
+    y, so = ode.integrate(f, 0.0, 1.5 / u.t0, np.zeros((3,) + prob.grid.shape),
+                          breakpoints=prob.drive.breakpoints())
+    assert abs(st.accepted - so.accepted) <= 2
+    assert rel_max(_np(h), y) < 1e-6
