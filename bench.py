@@ -113,6 +113,18 @@ def cpu_baseline(cfg, h_np):
                        "8 of a 3-iteration call" % dt)
 
 
+def copy_calibration(nbytes=256 << 20, reps=5):
+    """A plain device-to-device copy of known size: reads and writes nbytes per
+    launch.  Used to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,7 +133,13 @@ def main():
     ap.add_argument("--config", default="cup128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-events", action="store_true", help="skip the per-kernel event timing run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method here runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); rerun with --gpus 1",
@@ -151,24 +169,25 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     print("bench: %d steps, %d RHS calls in %.3f s" % (args.steps, st.rhs_calls, elapsed),
           file=sys.stderr, flush=True)
+    n = tuple(cfg["n"])
 
     # per-kernel durations with HIP events on the library's stream, same steps
-    scfft.scfft_profile(sim.ctx, 1)
-    run_steps(sim, h, T_STAR, args.steps)
-    prof = scfft.scfft_profile_read(sim.ctx)
-    scfft.scfft_profile(sim.ctx, 0)
-    n = tuple(cfg["n"])
-    per_kind = {}
-    for kind, (la, ms) in prof.items():
-        if la:
-            avg_s = ms / la * 1e-3
-            b = algorithmic_bytes(kind, n, 8, frac_out)
-            per_kind[kind] = dict(launches=la, avg_us=round(avg_s * 1e6, 2),
-                                  GBs=round(b / avg_s / 1e9, 1), total_ms=round(ms, 3))
-    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
-    dom_avg = per_kind[dom]["avg_us"] * 1e-6
-    dom_bytes = algorithmic_bytes(dom, n, 8, frac_out)
-    achieved = dom_bytes / dom_avg / 1e9
+    per_kind, dom, dom_bytes, achieved = {}, None, None, None
+    if not args.no_events:
+        scfft.scfft_profile(sim.ctx, 1)
+        run_steps(sim, h, T_STAR, args.steps)
+        prof = scfft.scfft_profile_read(sim.ctx)
+        scfft.scfft_profile(sim.ctx, 0)
+        for kind, (la, ms) in prof.items():
+            if la:
+                avg_s = ms / la * 1e-3
+                b = algorithmic_bytes(kind, n, 8, frac_out)
+                per_kind[kind] = dict(launches=la, avg_us=round(avg_s * 1e6, 2),
+                                      GBs=round(b / avg_s / 1e9, 1), total_ms=round(ms, 3))
+        dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
+        dom_avg = per_kind[dom]["avg_us"] * 1e-6
+        dom_bytes = algorithmic_bytes(dom, n, 8, frac_out)
+        achieved = dom_bytes / dom_avg / 1e9
 
     # right-hand side alone (no integrator work)
     rhs_ps, hd64 = time_rhs_only(sim, h, 50)
@@ -218,10 +237,10 @@ def main():
                    "grid": list(n), "exterior_iters": FIXED_ITER, "rhs_per_step": 3},
         "rhs_only": round(rhs_ps, 2),
         "fp32": fp32,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": dom_bytes,
-                     "avg_launch_us": per_kind[dom]["avg_us"]},
+        "roofline": None if dom is None else {
+            "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": dom_bytes, "avg_launch_us": per_kind[dom]["avg_us"]},
         "kernels": per_kind,
         "cpu_baseline": cpu,
     }

@@ -88,7 +88,7 @@ __device__ __forceinline__ void dftR(C2<T>* v) {
 
 // ---- pass plan: radices for length N with E elements per thread ----
 
-__host__ __device__ constexpr int elems_per_thread(int n) { return n >= 8 ? 8 : n; }
+__host__ __device__ constexpr int elems_per_thread(int n, int emax = 8) { return n >= emax ? emax : n; }
 
 // radix of pass p (0-based) for length N with E per thread: E while the
 // remaining factor allows, then the remainder.
@@ -186,17 +186,35 @@ struct LdsCols {
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
-// Row-major with one padding element every 8 (spreads the radix-8 strides
-// of the first pass over the banks).
-template <typename T, int N>
+// Barrier among the lanes of one wavefront: orders this wave's LDS stores
+// before its later LDS loads (a wave's LDS operations execute in order; the
+// fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row-major with one padding element every E (spreads the radix-E strides
+// of the first pass over the banks).  Holds indices 0..N inclusive.  When the
+// N/E threads of a row lie in one wavefront (N/E <= 64, rows aligned to
+// waves) the exchange needs only a wavefront barrier.
+template <typename T, int N, int E>
 struct LdsRows {
-  static constexpr int STRIDE = N + N / 8 + 1;
+  static constexpr int SHIFT = E >= 8 ? 3 : (E >= 4 ? 2 : 1);
+  static constexpr int STRIDE = N + (N >> SHIFT) + 1;
   C2<T>* base;
   int row;
-  __device__ __forceinline__ static int pad(int idx) { return idx + (idx >> 3); }
+  static constexpr bool IN_WAVE = (N / E) <= 64;
+  __device__ __forceinline__ static int pad(int idx) { return idx + (idx >> SHIFT); }
   __device__ __forceinline__ void store(int idx, C2<T> v) { base[row * STRIDE + pad(idx)] = v; }
   __device__ __forceinline__ C2<T> load(int idx) const { return base[row * STRIDE + pad(idx)]; }
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void sync() {
+    if constexpr (IN_WAVE)
+      wave_sync();
+    else
+      __syncthreads();
+  }
 };
 
 }  // namespace scfft

@@ -21,6 +21,33 @@ namespace scfft {
 
 constexpr int kBlock = 256;
 
+// Elements per thread of each pass kind (register footprint vs. number of
+// LDS exchanges); the FP64 X and Z passes hold three components at once.
+#ifndef SCFFT_EX_F64
+#define SCFFT_EX_F64 4
+#endif
+#ifndef SCFFT_EX_F32
+#define SCFFT_EX_F32 4
+#endif
+#ifndef SCFFT_EY_F64
+#define SCFFT_EY_F64 8
+#endif
+#ifndef SCFFT_EY_F32
+#define SCFFT_EY_F32 8
+#endif
+#ifndef SCFFT_EZ_F64
+#define SCFFT_EZ_F64 4
+#endif
+#ifndef SCFFT_EZ_F32
+#define SCFFT_EZ_F32 8
+#endif
+template <typename T>
+constexpr int ex_max() { return sizeof(T) == 8 ? SCFFT_EX_F64 : SCFFT_EX_F32; }
+template <typename T>
+constexpr int ey_max() { return sizeof(T) == 8 ? SCFFT_EY_F64 : SCFFT_EY_F32; }
+template <typename T>
+constexpr int ez_max() { return sizeof(T) == 8 ? SCFFT_EZ_F64 : SCFFT_EZ_F32; }
+
 // ---------------------------------------------------------------------------
 // Y pass
 // ---------------------------------------------------------------------------
@@ -29,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
                                                        C2<T>* __restrict__ nyq, int M,
                                                        int ncols_main, int ncols_nyq,
                                                        int nblk_main, const C2<T>* __restrict__ tw) {
-  constexpr int E = elems_per_thread(NY);
+  constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
   constexpr int COLS = kBlock / TPT;
   __shared__ C2<T> smem[NY * COLS];
@@ -71,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
                                                        C2<T>* __restrict__ nyq, int ny, int M,
                                                        int nblk_main, AxisTab<T> tx, AxisTab<T> ty,
                                                        AxisTab<T> tz, T coef) {
-  constexpr int E = elems_per_thread(NZ);
+  constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = kBlock / TPT;
   __shared__ C2<T> smem[NZ * COLS];
@@ -192,14 +219,14 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
 template <typename T, int NX, int OP>
 __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   constexpr int M = NX / 2;
-  constexpr int E = elems_per_thread(M);
+  constexpr int E = elems_per_thread(M, ex_max<T>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
   constexpr bool HAS_INV = OP != X_FWD;
   constexpr bool HAS_FWD = OP == X_FWD || OP == X_LAW || OP == X_HIN || OP == X_MASK ||
                            OP == X_UPDATE;
   constexpr bool REDUCE = OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MOMENT;
-  using L = LdsRows<T, M>;
+  using L = LdsRows<T, M, E>;
   __shared__ C2<T> smem[ROWS * L::STRIDE];
   __shared__ double red[REDUCE ? 3 * kBlock : 1];
 
@@ -219,28 +246,59 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   T a[3][2 * E];
   unsigned clamps = 0;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  const int y = rr % P.ny;
+  const int z = rr / P.ny;
+  const size_t rowbase = (size_t)rr * NX;
+
+  // ---- all global loads first, so their latencies overlap ----
+  constexpr bool NEED_CHI = OP == X_LAW || OP == X_HIN || OP == X_MASK || OP == X_UPDATE ||
+                            OP == X_UPDATE_LAST || OP == X_MOMENT;
+  constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST;
+  C2<T> Xs[HAS_INV ? 3 : 1][E];
+  C2<T> Xn[3];
+  if constexpr (HAS_INV) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        Xs[c][m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
+      Xn[c] = (valid && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
+    }
+  }
+  uint8_t ch[2 * E];
+  if constexpr (NEED_CHI) {
+#pragma unroll
+    for (int e = 0; e < 2 * E; ++e) ch[e] = valid ? A.chi[rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : 0;
+  }
+  // X_FWD: the real input; X_HIN: the warm start; X_UPDATE*: hdot^i
+  const T* auxp = OP == X_FWD ? A.in : (OP == X_HIN ? A.warm : A.out);
+  T aux[(NEED_AUX || OP == X_FWD) ? 3 : 1][2 * E];
+  if constexpr (NEED_AUX || OP == X_FWD) {
+    const bool have = valid && auxp != nullptr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < 2 * E; ++e)
+        aux[c][e] = have ? auxp[c * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
+  }
 
   if constexpr (HAS_INV) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      C2<T> X[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        X[m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-        lds.store(j + m * TPT, X[m]);
-      }
-      if (j == 0) lds.store(M, valid ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)});
-      __syncthreads();
+      for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Xs[c][m]);
+      if (j == 0) lds.store(M, Xn[c]);
+      lds.sync();
       C2<T> Z[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int k = j + m * TPT;
         const C2<T> pc = cconj(lds.load(M - k));                // conj X[M-k]
-        const C2<T> ev = X[m] + pc;                              // X[k] + X[k+M]
-        const C2<T> od = cmul(X[m] - pc, cconj(tw[k]));          // (X[k] - X[k+M]) w^-k
+        const C2<T> ev = Xs[c][m] + pc;                          // X[k] + X[k+M]
+        const C2<T> od = cmul(Xs[c][m] - pc, cconj(tw[k]));      // (X[k] - X[k+M]) w^-k
         Z[m] = {ev.x - od.y, ev.y + od.x};                       // ev + i od
       }
-      __syncthreads();
+      lds.sync();
       fft_inverse<T, M, E>(Z, j, lds, tw, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -251,9 +309,6 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   }
 
   // ---- pointwise work on the nodes x = 2n, 2n+1, n = j + m TPT ----
-  const int y = rr % P.ny;
-  const int z = rr / P.ny;
-  const size_t rowbase = (size_t)rr * NX;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
 #pragma unroll
@@ -261,11 +316,11 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       const int x = 2 * (j + m * TPT) + h;
       const size_t idx = rowbase + x;
       const int e = 2 * m + h;
+      const bool in = ch[NEED_CHI ? e : 0] != 0;
       if constexpr (OP == X_FWD) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a[c][e] = valid ? A.in[c * csr + idx] : T(0);
+        for (int c = 0; c < 3; ++c) a[c][e] = aux[c][e];
       } else if constexpr (OP == X_LAW) {
-        const bool in = valid && A.chi[idx] != 0;
         if (in) {
           const T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
           power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
@@ -274,27 +329,24 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           for (int c = 0; c < 3; ++c) a[c][e] *= A.rho_out;
         }
       } else if constexpr (OP == X_HIN) {
-        const bool in = valid && A.chi[idx] != 0;
         if (!in && A.warm) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) a[c][e] = valid ? A.warm[c * csr + idx] : T(0);
+          for (int c = 0; c < 3; ++c) a[c][e] = aux[c][e];
         }
         if (valid) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
         }
       } else if constexpr (OP == X_MASK) {
-        const bool in = valid && A.chi[idx] != 0;
         if (!in) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) a[c][e] = T(0);
         }
       } else if constexpr (OP == X_UPDATE || OP == X_UPDATE_LAST) {
-        const bool in = valid && A.chi[idx] != 0;
         T d2 = T(0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T old = valid ? A.out[c * csr + idx] : T(0);
+          const T old = aux[c][e];
           const T nw = in ? old : A.hedot[c] + a[c][e];
           const T dd = nw - old;
           d2 += dd * dd;
@@ -311,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
         }
       } else if constexpr (OP == X_MOMENT) {
-        const bool use = valid && (!A.omega_only || A.chi[idx] != 0);
+        const bool use = valid && (!A.omega_only || in);
         if (use) {
           const double px = A.pos0[0] + A.step[0] * x;
           const double py = A.pos0[1] + A.step[1] * y;
@@ -361,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       fft_forward<T, M, E>(Z, j, lds, tw, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Z[m]);
-      __syncthreads();
+      lds.sync();
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int k = j + m * TPT;
@@ -373,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
         if (valid) P.main[c * csm + (size_t)rr * M + k] = X;
       }
       if (j == 0 && valid) P.nyq[c * csn + rr] = C2<T>{Z[0].x - Z[0].y, T(0)};
-      __syncthreads();
+      lds.sync();
     }
   }
 }
@@ -381,14 +433,14 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int EMAX>
 constexpr int tpt_of() {
-  return N / elems_per_thread(N);
+  return N / elems_per_thread(N, EMAX);
 }
 
 template <typename T, int NX>
 static int xblocks_n(const Plan<T>& p) {
-  constexpr int ROWS = kBlock / tpt_of<NX / 2>();
+  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T>()>();
   return (p.ny * p.nz + ROWS - 1) / ROWS;
 }
 
@@ -445,7 +497,7 @@ hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t
 
 template <typename T, int NY>
 static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s) {
-  constexpr int COLS = kBlock / tpt_of<NY>();
+  constexpr int COLS = kBlock / tpt_of<NY, ey_max<T>()>();
   const int M = p.nx / 2;
   const int ncm = 3 * p.nz * M, ncn = 3 * p.nz;
   const int nbm = (ncm + COLS - 1) / COLS, nbn = (ncn + COLS - 1) / COLS;
@@ -475,7 +527,7 @@ hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s) {
 
 template <typename T, int NZ>
 static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s) {
-  constexpr int COLS = kBlock / tpt_of<NZ>();
+  constexpr int COLS = kBlock / tpt_of<NZ, ez_max<T>()>();
   const int M = p.nx / 2;
   const int nbm = (p.ny * M + COLS - 1) / COLS, nbn = (p.ny + COLS - 1) / COLS;
   const dim3 grid(nbm + nbn), block(kBlock);

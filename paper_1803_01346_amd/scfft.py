@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libscfft.so")
+# SCFFT_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SCFFT_LIBRARY") or os.path.join(_HERE, "libscfft.so")
 
 OK = 0
 WARN_NOT_CONVERGED = 1
