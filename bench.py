@@ -50,6 +50,28 @@ def algorithmic_bytes(kind, n, w, frac_out):
     return table[kind]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs_passes_cup128_f64_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1803_01346_amd", "csrc", f) for f in ("fft_core.h", "passes.hip")]
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of `kind` from the committed counter summary, or
+    None if the kernels changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+    if ("source_hash %s" % h) not in text:
+        return None
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kind:
+            return int(parts[2])
+    return None
+
+
 def make_sim(cfg, precision, fixed_iter):
     from paper_1803_01346_amd import scfft
     return scfft.Simulation(cfg, precision=precision,
@@ -239,7 +261,8 @@ def main():
         "fp32": fp32,
         "roofline": None if dom is None else {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom),
             "bytes_per_launch": dom_bytes, "avg_launch_us": per_kind[dom]["avg_us"]},
         "kernels": per_kind,
         "cpu_baseline": cpu,

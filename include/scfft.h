@@ -287,9 +287,9 @@ enum {
   SCFFT_KERNEL_KINDS
 };
 
-/* enable != 0: start timing every pass launch with a HIP event pair on the
- * context stream (and reset the totals); 0: stop.  Timing adds event records
- * between launches, so time throughput with it off. */
+/* enable != 0: start timing every pass launch (and reset the totals); 0: stop.
+ * Each pass dispatch carries its own start/stop HIP event pair on the context
+ * stream, so the durations are those of the kernel bodies. */
 scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable);
 /* Launch counts and summed kernel durations (ms) per kind since enable;
  * synchronises with the recorded events. */

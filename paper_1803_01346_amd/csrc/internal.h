@@ -64,14 +64,21 @@ struct XArgs {
   double step[3];        // node spacing (moment)
 };
 
+// Optional start/stop events attached to a kernel's own dispatch (timing of
+// the kernel body, as a kernel trace reports it); both null = plain launch.
+struct KTime {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
 template <typename T>
 int xpass_blocks(const Plan<T>& p);
 template <typename T>
-hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s);
+hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t = {});
 template <typename T>
-hipError_t launch_ypass(const Plan<T>& p, bool inverse, hipStream_t s);
+hipError_t launch_ypass(const Plan<T>& p, bool inverse, hipStream_t s, KTime t = {});
 template <typename T>
-hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s);
+hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t = {});
 
 // ---- pointwise / reduction kernels (pointwise.hip) ----
 hipError_t launch_sum_partials(const double* partials, int n, int stride, int ncomp, double* out,

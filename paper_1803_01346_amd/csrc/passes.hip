@@ -13,6 +13,7 @@
 // The spectrum of each component is stored as main[z][y][kx], kx < Nx/2,
 // plus the Nyquist column nyq[z][y] (kx = Nx/2), so every row of the main
 // part is a power of two long and column tiles stay aligned.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -20,6 +21,15 @@
 namespace scfft {
 
 constexpr int kBlock = 256;
+
+// launch, with the events of t (if any) attached to the dispatch itself
+template <typename F, typename... Args>
+static void launch(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime t, Args... args) {
+  if (t.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, t.stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // Elements per thread of each pass kind (register footprint vs. number of
 // LDS exchanges); the FP64 X and Z passes hold three components at once.
@@ -459,22 +469,22 @@ int xpass_blocks(const Plan<T>& p) {
 }
 
 template <typename T, int NX>
-static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s) {
+static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
   const dim3 grid(xblocks_n<T, NX>(p)), block(kBlock);
   switch (op) {
-    case X_FWD: hipLaunchKernelGGL((xpass_kernel<T, NX, X_FWD>), grid, block, 0, s, p, a); break;
-    case X_LAW: hipLaunchKernelGGL((xpass_kernel<T, NX, X_LAW>), grid, block, 0, s, p, a); break;
-    case X_HIN: hipLaunchKernelGGL((xpass_kernel<T, NX, X_HIN>), grid, block, 0, s, p, a); break;
-    case X_MASK: hipLaunchKernelGGL((xpass_kernel<T, NX, X_MASK>), grid, block, 0, s, p, a); break;
+    case X_FWD: launch(xpass_kernel<T, NX, X_FWD>, grid, block, s, t, p, a); break;
+    case X_LAW: launch(xpass_kernel<T, NX, X_LAW>, grid, block, s, t, p, a); break;
+    case X_HIN: launch(xpass_kernel<T, NX, X_HIN>, grid, block, s, t, p, a); break;
+    case X_MASK: launch(xpass_kernel<T, NX, X_MASK>, grid, block, s, t, p, a); break;
     case X_UPDATE:
-      hipLaunchKernelGGL((xpass_kernel<T, NX, X_UPDATE>), grid, block, 0, s, p, a);
+      launch(xpass_kernel<T, NX, X_UPDATE>, grid, block, s, t, p, a);
       break;
     case X_UPDATE_LAST:
-      hipLaunchKernelGGL((xpass_kernel<T, NX, X_UPDATE_LAST>), grid, block, 0, s, p, a);
+      launch(xpass_kernel<T, NX, X_UPDATE_LAST>, grid, block, s, t, p, a);
       break;
-    case X_STORE: hipLaunchKernelGGL((xpass_kernel<T, NX, X_STORE>), grid, block, 0, s, p, a); break;
+    case X_STORE: launch(xpass_kernel<T, NX, X_STORE>, grid, block, s, t, p, a); break;
     case X_MOMENT:
-      hipLaunchKernelGGL((xpass_kernel<T, NX, X_MOMENT>), grid, block, 0, s, p, a);
+      launch(xpass_kernel<T, NX, X_MOMENT>, grid, block, s, t, p, a);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -482,67 +492,65 @@ static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStre
 }
 
 template <typename T>
-hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s) {
+hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
   switch (p.nx) {
-    case 8: return xlaunch_n<T, 8>(p, op, a, s);
-    case 16: return xlaunch_n<T, 16>(p, op, a, s);
-    case 32: return xlaunch_n<T, 32>(p, op, a, s);
-    case 64: return xlaunch_n<T, 64>(p, op, a, s);
-    case 128: return xlaunch_n<T, 128>(p, op, a, s);
-    case 256: return xlaunch_n<T, 256>(p, op, a, s);
-    case 512: return xlaunch_n<T, 512>(p, op, a, s);
+    case 8: return xlaunch_n<T, 8>(p, op, a, s, t);
+    case 16: return xlaunch_n<T, 16>(p, op, a, s, t);
+    case 32: return xlaunch_n<T, 32>(p, op, a, s, t);
+    case 64: return xlaunch_n<T, 64>(p, op, a, s, t);
+    case 128: return xlaunch_n<T, 128>(p, op, a, s, t);
+    case 256: return xlaunch_n<T, 256>(p, op, a, s, t);
+    case 512: return xlaunch_n<T, 512>(p, op, a, s, t);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, int NY>
-static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s) {
+static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
   constexpr int COLS = kBlock / tpt_of<NY, ey_max<T>()>();
   const int M = p.nx / 2;
   const int ncm = 3 * p.nz * M, ncn = 3 * p.nz;
   const int nbm = (ncm + COLS - 1) / COLS, nbn = (ncn + COLS - 1) / COLS;
   const dim3 grid(nbm + nbn), block(kBlock);
   if (inv)
-    hipLaunchKernelGGL((ypass_kernel<T, NY, true>), grid, block, 0, s, p.main, p.nyq, M, ncm, ncn,
-                       nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, p.nyq, M, ncm, ncn, nbm, p.ay.tw);
   else
-    hipLaunchKernelGGL((ypass_kernel<T, NY, false>), grid, block, 0, s, p.main, p.nyq, M, ncm, ncn,
-                       nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, p.nyq, M, ncm, ncn, nbm, p.ay.tw);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s) {
+hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
   switch (p.ny) {
-    case 8: return ylaunch_n<T, 8>(p, inv, s);
-    case 16: return ylaunch_n<T, 16>(p, inv, s);
-    case 32: return ylaunch_n<T, 32>(p, inv, s);
-    case 64: return ylaunch_n<T, 64>(p, inv, s);
-    case 128: return ylaunch_n<T, 128>(p, inv, s);
-    case 256: return ylaunch_n<T, 256>(p, inv, s);
-    case 512: return ylaunch_n<T, 512>(p, inv, s);
+    case 8: return ylaunch_n<T, 8>(p, inv, s, t);
+    case 16: return ylaunch_n<T, 16>(p, inv, s, t);
+    case 32: return ylaunch_n<T, 32>(p, inv, s, t);
+    case 64: return ylaunch_n<T, 64>(p, inv, s, t);
+    case 128: return ylaunch_n<T, 128>(p, inv, s, t);
+    case 256: return ylaunch_n<T, 256>(p, inv, s, t);
+    case 512: return ylaunch_n<T, 512>(p, inv, s, t);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, int NZ>
-static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s) {
+static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
   constexpr int COLS = kBlock / tpt_of<NZ, ez_max<T>()>();
   const int M = p.nx / 2;
   const int nbm = (p.ny * M + COLS - 1) / COLS, nbn = (p.ny + COLS - 1) / COLS;
   const dim3 grid(nbm + nbn), block(kBlock);
   switch (sym) {
     case Z_CURL:
-      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_CURL>), grid, block, 0, s, p.main, p.nyq, p.ny, M,
-                         nbm, p.ax, p.ay, p.az, coef);
+      launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
+             p.az, coef);
       break;
     case Z_PHI:
-      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_PHI>), grid, block, 0, s, p.main, p.nyq, p.ny, M,
-                         nbm, p.ax, p.ay, p.az, coef);
+      launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
+             p.az, coef);
       break;
     case Z_PHI_SMOOTH:
-      hipLaunchKernelGGL((zpass_kernel<T, NZ, Z_PHI_SMOOTH>), grid, block, 0, s, p.main, p.nyq,
-                         p.ny, M, nbm, p.ax, p.ay, p.az, coef);
+      launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax,
+             p.ay, p.az, coef);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -550,26 +558,28 @@ static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s) {
+hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
   switch (p.nz) {
-    case 8: return zlaunch_n<T, 8>(p, sym, coef, s);
-    case 16: return zlaunch_n<T, 16>(p, sym, coef, s);
-    case 32: return zlaunch_n<T, 32>(p, sym, coef, s);
-    case 64: return zlaunch_n<T, 64>(p, sym, coef, s);
-    case 128: return zlaunch_n<T, 128>(p, sym, coef, s);
-    case 256: return zlaunch_n<T, 256>(p, sym, coef, s);
-    case 512: return zlaunch_n<T, 512>(p, sym, coef, s);
+    case 8: return zlaunch_n<T, 8>(p, sym, coef, s, t);
+    case 16: return zlaunch_n<T, 16>(p, sym, coef, s, t);
+    case 32: return zlaunch_n<T, 32>(p, sym, coef, s, t);
+    case 64: return zlaunch_n<T, 64>(p, sym, coef, s, t);
+    case 128: return zlaunch_n<T, 128>(p, sym, coef, s, t);
+    case 256: return zlaunch_n<T, 256>(p, sym, coef, s, t);
+    case 512: return zlaunch_n<T, 512>(p, sym, coef, s, t);
   }
   return hipErrorInvalidValue;
 }
 
 template int xpass_blocks<double>(const Plan<double>&);
 template int xpass_blocks<float>(const Plan<float>&);
-template hipError_t launch_xpass<double>(const Plan<double>&, int, const XArgs<double>&, hipStream_t);
-template hipError_t launch_xpass<float>(const Plan<float>&, int, const XArgs<float>&, hipStream_t);
-template hipError_t launch_ypass<double>(const Plan<double>&, bool, hipStream_t);
-template hipError_t launch_ypass<float>(const Plan<float>&, bool, hipStream_t);
-template hipError_t launch_zpass<double>(const Plan<double>&, int, double, hipStream_t);
-template hipError_t launch_zpass<float>(const Plan<float>&, int, float, hipStream_t);
+template hipError_t launch_xpass<double>(const Plan<double>&, int, const XArgs<double>&, hipStream_t,
+                                         KTime);
+template hipError_t launch_xpass<float>(const Plan<float>&, int, const XArgs<float>&, hipStream_t,
+                                        KTime);
+template hipError_t launch_ypass<double>(const Plan<double>&, bool, hipStream_t, KTime);
+template hipError_t launch_ypass<float>(const Plan<float>&, bool, hipStream_t, KTime);
+template hipError_t launch_zpass<double>(const Plan<double>&, int, double, hipStream_t, KTime);
+template hipError_t launch_zpass<float>(const Plan<float>&, int, float, hipStream_t, KTime);
 
 }  // namespace scfft

@@ -208,42 +208,48 @@ hipError_t prof_harvest(scfft_ctx* c) {
   return hipSuccess;
 }
 
-hipError_t prof_begin(scfft_ctx* c, int kind) {
+// Event pair for the next launch of `kind` (none when timing is off).
+hipError_t prof_slot(scfft_ctx* c, int kind, KTime* t) {
+  *t = KTime{};
   if (!c->prof) return hipSuccess;
   if (2 * (c->ev_used + 1) > c->ev_pool.size()) {
     hipError_t e = prof_harvest(c);  // waits for the pending launches
     if (e != hipSuccess) return e;
   }
   c->ev_kind[c->ev_used] = kind;
-  return hipEventRecord(c->ev_pool[2 * c->ev_used], c->stream);
+  t->start = c->ev_pool[2 * c->ev_used];
+  t->stop = c->ev_pool[2 * c->ev_used + 1];
+  ++c->ev_used;
+  return hipSuccess;
 }
 
-hipError_t prof_end(scfft_ctx* c, hipError_t launch_err) {
-  if (!c->prof || launch_err != hipSuccess) return launch_err;
-  hipError_t e = hipEventRecord(c->ev_pool[2 * c->ev_used + 1], c->stream);
-  ++c->ev_used;
-  return e;
+hipError_t prof_done(scfft_ctx* c, hipError_t launch_err, const KTime& t) {
+  if (launch_err != hipSuccess && t.start) --c->ev_used;  // that pair was never recorded
+  return launch_err;
 }
 
 template <typename T>
 hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
-  hipError_t e = prof_begin(c, SCFFT_KERNEL_X_FWD + op);
+  KTime t;
+  hipError_t e = prof_slot(c, SCFFT_KERNEL_X_FWD + op, &t);
   if (e != hipSuccess) return e;
-  return prof_end(c, launch_xpass<T>(p, op, a, c->stream));
+  return prof_done(c, launch_xpass<T>(p, op, a, c->stream, t), t);
 }
 
 template <typename T>
 hipError_t run_y(scfft_ctx* c, const Plan<T>& p, bool inv) {
-  hipError_t e = prof_begin(c, inv ? SCFFT_KERNEL_Y_INV : SCFFT_KERNEL_Y_FWD);
+  KTime t;
+  hipError_t e = prof_slot(c, inv ? SCFFT_KERNEL_Y_INV : SCFFT_KERNEL_Y_FWD, &t);
   if (e != hipSuccess) return e;
-  return prof_end(c, launch_ypass<T>(p, inv, c->stream));
+  return prof_done(c, launch_ypass<T>(p, inv, c->stream, t), t);
 }
 
 template <typename T>
 hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
-  hipError_t e = prof_begin(c, sym == Z_CURL ? SCFFT_KERNEL_Z_CURL : SCFFT_KERNEL_Z_PHI);
+  KTime t;
+  hipError_t e = prof_slot(c, sym == Z_CURL ? SCFFT_KERNEL_Z_CURL : SCFFT_KERNEL_Z_PHI, &t);
   if (e != hipSuccess) return e;
-  return prof_end(c, launch_zpass<T>(p, sym, (T)coef, c->stream));
+  return prof_done(c, launch_zpass<T>(p, sym, (T)coef, c->stream, t), t);
 }
 
 // Y forward, Z (symbol), Y inverse: the middle of one operator application.
