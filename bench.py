@@ -28,26 +28,38 @@ T_STAR = 0.005            # s: quarter period of the 50 Hz drive (peak field)
 DT_STEP = 1e-8            # s: fixed step of the timed integration
 
 
-def algorithmic_bytes(kind, n, w, frac_out):
+def algorithmic_bytes(kind, n, w, frac_out, track=False):
     """Bytes a kernel launch must move at minimum (one read of its inputs,
-    one write of its outputs), for an n = (nx, ny, nz) grid and word size w."""
+    one write of its outputs), for an n = (nx, ny, nz) grid and word size w.
+    track=False is the fixed-iteration mode the benchmark runs: exterior
+    updates then read hdot only on Omega and the last one writes hdot and the
+    next warm start on Omega_out; track=True keeps every iterate (adaptive)."""
     nx, ny, nz = n
     nodes = nx * ny * nz
     S = 3 * nz * ny * (nx // 2 + 1) * 2 * w        # half spectrum, 3 components
     F = 3 * nodes * w                              # real 3-vector field
     Mk = nodes                                     # uint8 mask
+    fo, fi = frac_out, 1.0 - frac_out
+    if track:
+        hin = S + Mk + F * fo + F + S              # warm read (out), hdot write (all)
+        upd = S + Mk + 2 * F * fo + S              # hdot read/write on Omega_out
+        last = S + Mk + 2 * F * fo
+    else:
+        hin = S + Mk + F * fo + F * fi + S         # warm read (out), hdot write (Omega)
+        upd = S + Mk + F * fi + S                  # hdot_in read (Omega)
+        last = S + Mk + 2 * F * fo                 # hdot and warm writes (out)
     table = {
         "X_FWD": F + S,
         "X_LAW": S + Mk + S,
-        "X_HIN": S + Mk + F + F + S,               # warm read, hdot write
+        "X_HIN": hin,
         "X_MASK": S + Mk + S,
-        "X_UPDATE": S + Mk + 2 * F * frac_out + S,  # hdot read/write on Omega_out
-        "X_UPDATE_LAST": S + Mk + 2 * F * frac_out,
+        "X_UPDATE": upd,
+        "X_UPDATE_LAST": last,
         "X_STORE": S + F,
         "X_MOMENT": S,
         "Y_FWD": 2 * S, "Y_INV": 2 * S, "Z_CURL": 2 * S, "Z_PHI": 2 * S,
     }
-    return table[kind]
+    return int(table[kind])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs_passes_cup128_f64_hbm_traffic.md")

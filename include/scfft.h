@@ -135,7 +135,8 @@ typedef struct {
 typedef struct {
   int32_t iters;        /* iterations (5) run                              */
   int32_t converged;    /* 1 if the stopping rule (or fixed_iter) ended it */
-  double last_delta;    /* last mean |hdot^{i+1} - hdot^i| over Omega_out  */
+  double last_delta;    /* last mean |hdot^{i+1} - hdot^i| over Omega_out
+                           (-1 with fixed_iter: not tracked)              */
   int64_t clamps;       /* power-law evaluations whose exponent was clamped */
 } scfft_rhs_stats;
 

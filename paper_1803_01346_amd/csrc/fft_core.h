@@ -195,20 +195,30 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Row-major with one padding element every E (spreads the radix-E strides
-// of the first pass over the banks).  Holds indices 0..N inclusive.  When the
+// Row-major, rows of STRIDE elements holding indices 0..N inclusive, with
+// an XOR swizzle inside each block of 8 elements: bits 0..2 of the index are
+// XORed with parities of bits 3..6 (masks 3, 5, 3), chosen by a search over
+// all such linear swizzles for the fewest bank conflicts of the split and
+// Stockham exchanges of one row (32 four-byte banks, 16-byte elements, eight
+// lanes per cycle).  Contiguous accesses stay permutations; the strided
+// stores of the radix-4 passes spread over the banks.  When several rows
+// share a lane group (N/E < 16) the row index joins the high bits.  When the
 // N/E threads of a row lie in one wavefront (N/E <= 64, rows aligned to
 // waves) the exchange needs only a wavefront barrier.
 template <typename T, int N, int E>
 struct LdsRows {
-  static constexpr int SHIFT = E >= 8 ? 3 : (E >= 4 ? 2 : 1);
-  static constexpr int STRIDE = N + (N >> SHIFT) + 1;
+  static constexpr int STRIDE = ((N + 1 + 15) / 16) * 16;
+  static constexpr bool ROWMIX = (N / E) < 16;
+  static constexpr bool IN_WAVE = (N / E) <= 64;
   C2<T>* base;
   int row;
-  static constexpr bool IN_WAVE = (N / E) <= 64;
-  __device__ __forceinline__ static int pad(int idx) { return idx + (idx >> SHIFT); }
-  __device__ __forceinline__ void store(int idx, C2<T> v) { base[row * STRIDE + pad(idx)] = v; }
-  __device__ __forceinline__ C2<T> load(int idx) const { return base[row * STRIDE + pad(idx)]; }
+  __device__ __forceinline__ static int parity(int v) { return __builtin_popcount(v) & 1; }
+  __device__ __forceinline__ int swz(int idx) const {
+    const int h = ((idx >> 3) + (ROWMIX ? 2 * row : 0)) & 15;
+    return idx ^ (parity(h & 3) | (parity(h & 5) << 1) | (parity(h & 3) << 2));
+  }
+  __device__ __forceinline__ void store(int idx, C2<T> v) { base[row * STRIDE + swz(idx)] = v; }
+  __device__ __forceinline__ C2<T> load(int idx) const { return base[row * STRIDE + swz(idx)]; }
   __device__ __forceinline__ void sync() {
     if constexpr (IN_WAVE)
       wave_sync();

@@ -60,6 +60,10 @@ struct XArgs {
   T npow, rho_out, expmax;
   T hedot[3];
   int omega_only;        // X_MOMENT: 1 = chi nodes only
+  int track;             // X_HIN, X_UPDATE*: 1 = keep every iterate in `out` and sum
+                         // |delta| (adaptive stopping); 0 = fixed iteration count:
+                         // only the nodes a later pass reads are touched
+  T* warm_out;           // X_UPDATE_LAST with track = 0: also store hdot on Omega_out here
   double pos0[3];        // coordinate of node 0 along each axis (moment)
   double step[3];        // node spacing (moment)
 };

@@ -280,16 +280,22 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
     for (int e = 0; e < 2 * E; ++e) ch[e] = valid ? A.chi[rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : 0;
   }
-  // X_FWD: the real input; X_HIN: the warm start; X_UPDATE*: hdot^i
+  // X_FWD: the real input (all nodes); X_HIN: the warm start (Omega_out);
+  // X_UPDATE*: hdot^i (all nodes when tracking iterates, else Omega only:
+  // with a fixed iteration count only hdot_in is read back)
   const T* auxp = OP == X_FWD ? A.in : (OP == X_HIN ? A.warm : A.out);
   T aux[(NEED_AUX || OP == X_FWD) ? 3 : 1][2 * E];
   if constexpr (NEED_AUX || OP == X_FWD) {
-    const bool have = valid && auxp != nullptr;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int e = 0; e < 2 * E; ++e) {
+      bool need = valid && auxp != nullptr;
+      if constexpr (OP == X_HIN) need = need && ch[e] == 0;
+      if constexpr (OP == X_UPDATE) need = need && (A.track || ch[e] != 0);
+      if constexpr (OP == X_UPDATE_LAST) need = need && A.track;
 #pragma unroll
-      for (int e = 0; e < 2 * E; ++e)
-        aux[c][e] = have ? auxp[c * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
+      for (int c = 0; c < 3; ++c)
+        aux[c][e] = need ? auxp[c * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
+    }
   }
 
   if constexpr (HAS_INV) {
@@ -343,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) a[c][e] = aux[c][e];
         }
-        if (valid) {
+        if (valid && (A.track || in)) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
         }
@@ -363,9 +369,18 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           a[c][e] = nw;
         }
         if (valid && !in) {
-          acc0 += sqrt((double)d2);
+          if (A.track) {
+            acc0 += sqrt((double)d2);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+            for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+          } else if constexpr (OP == X_UPDATE_LAST) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+            if (A.warm_out) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) A.warm_out[c * csr + idx] = a[c][e];
+            }
+          }
         }
       } else if constexpr (OP == X_STORE) {
         if (valid) {
@@ -387,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
     }
   }
 
-  if constexpr (REDUCE) {
+  if (REDUCE && (OP == X_MOMENT || A.track)) {  // uniform across the block
     red[tid] = acc0;
     red[kBlock + tid] = acc1;
     red[2 * kBlock + tid] = acc2;

@@ -284,12 +284,13 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   HIPCHK(c, run_x<T>(c, p, X_LAW, a));
   HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, -norm));
   // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out
+  const int fixed = c->opts.fixed_iter;
   a.out = hdot;
   a.warm = c->has_warm ? wsp<T>(c, c->off_warm) : nullptr;
+  a.track = fixed > 0 ? 0 : 1;
   HIPCHK(c, run_x<T>(c, p, X_HIN, a));
 
   // iteration (5)
-  const int fixed = c->opts.fixed_iter;
   const int max_it = fixed > 0 ? fixed : c->opts.max_iter;
   double* deltas = wsp<double>(c, c->off_delta);
   int it = 0;
@@ -300,8 +301,11 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
     HIPCHK(c, run_x<T>(c, p, X_MASK, a));             // jdot_in^i
     HIPCHK(c, spectral_middle<T>(c, p, phi_sym, norm));      // Phi[jdot_in^i]  (Eq. 7)
     const bool last_known = it + 1 >= max_it;
+    // with a fixed count the last update also stores the next warm start
+    a.warm_out = (last_known && fixed > 0) ? wsp<T>(c, c->off_warm) : nullptr;
     HIPCHK(c, run_x<T>(c, p, last_known ? X_UPDATE_LAST : X_UPDATE, a));  // Eq. 5
-    HIPCHK(c, launch_sum_partials(a.partials, xb, 1, 1, deltas + (it % kMaxDeltaSlots), s));
+    if (fixed <= 0)
+      HIPCHK(c, launch_sum_partials(a.partials, xb, 1, 1, deltas + (it % kMaxDeltaSlots), s));
     ++it;
     if (fixed > 0) {
       if (it >= fixed) {
@@ -322,9 +326,11 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
     if (it >= max_it) break;
     if (last_known) break;
   }
-  // warm start of the next call: hdot on Omega_out (only those nodes are read)
-  HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
-                           hipMemcpyDeviceToDevice, s));
+  // warm start of the next call: hdot on Omega_out (only those nodes are read);
+  // with a fixed count the last update already stored it
+  if (fixed <= 0)
+    HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
+                             hipMemcpyDeviceToDevice, s));
   c->has_warm = true;
 
   scfft_status st = converged ? SCFFT_OK : SCFFT_WARN_NOT_CONVERGED;
@@ -332,15 +338,8 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
     unsigned long long cl = 0;
     HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
                              hipMemcpyDeviceToHost, s));
-    if (fixed > 0) {
-      double sum = 0.0;
-      HIPCHK(c, hipMemcpyAsync(&sum, deltas + ((it - 1) % kMaxDeltaSlots), sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      last = c->n_out > 0 ? sum / (double)c->n_out : 0.0;
-    } else {
-      HIPCHK(c, hipStreamSynchronize(s));
-    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (fixed > 0) last = -1.0;  // not tracked with a fixed iteration count
     const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
     c->clamp_seen = (int64_t)cl;
     if (stats) {
