@@ -144,7 +144,7 @@ __device__ __forceinline__ void stockham_pass(C2<T> (&v)[E], int j, Lds& lds,
     lds.sync();
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = lds.load(j + m * TPT);
-    lds.sync();
+    lds.after_load();
   }
 }
 
@@ -177,6 +177,9 @@ __device__ __forceinline__ void fft_inverse(C2<T> (&v)[E], int j, Lds& lds,
 
 // LDS layouts.  Column-major: COLS transforms side by side, element idx of
 // column c at idx * COLS + c (lanes of one row of columns are contiguous).
+//
+// Each layout provides sync() (between the stores of a pass and the loads of
+// the next) and after_load() (before the next pass may store again).
 template <typename T, int COLS>
 struct LdsCols {
   C2<T>* base;
@@ -184,6 +187,23 @@ struct LdsCols {
   __device__ __forceinline__ void store(int idx, C2<T> v) { base[idx * COLS + col] = v; }
   __device__ __forceinline__ C2<T> load(int idx) const { return base[idx * COLS + col]; }
   __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void after_load() { __syncthreads(); }
+};
+
+// Column-major with two buffers of N * COLS elements used alternately:
+// consecutive exchanges never touch the same buffer, so one block barrier
+// per exchange suffices (the barrier of exchange p+1 also orders the loads
+// of exchange p before the stores of exchange p+2).  The parity carries
+// over from one transform to the next.
+template <typename T, int N, int COLS>
+struct LdsColsPP {
+  C2<T>* base;
+  int col;
+  int off = 0;
+  __device__ __forceinline__ void store(int idx, C2<T> v) { base[off + idx * COLS + col] = v; }
+  __device__ __forceinline__ C2<T> load(int idx) const { return base[off + idx * COLS + col]; }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ void after_load() { off = off ? 0 : N * COLS; }
 };
 
 // Barrier among the lanes of one wavefront: orders this wave's LDS stores
@@ -225,6 +245,7 @@ struct LdsRows {
     else
       __syncthreads();
   }
+  __device__ __forceinline__ void after_load() { sync(); }
 };
 
 }  // namespace scfft

@@ -16,6 +16,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace scfft {
@@ -58,6 +60,19 @@ constexpr int ey_max() { return sizeof(T) == 8 ? SCFFT_EY_F64 : SCFFT_EY_F32; }
 template <typename T>
 constexpr int ez_max() { return sizeof(T) == 8 ? SCFFT_EZ_F64 : SCFFT_EZ_F32; }
 
+// Column passes exchange through two alternating LDS buffers (one barrier
+// per exchange) where that does not cost occupancy: the Z pass (three
+// transforms per column, 4 elements per thread in FP64); the Y pass keeps a
+// single buffer (its 8-element FP64 tile would double to 64 KB).
+#ifndef SCFFT_PP_Y
+#define SCFFT_PP_Y 0
+#endif
+#ifndef SCFFT_PP_Z
+#define SCFFT_PP_Z 1
+#endif
+template <bool PP, typename T, int N, int COLS>
+using ColLds = typename std::conditional<PP, LdsColsPP<T, N, COLS>, LdsCols<T, COLS>>::type;
+
 // ---------------------------------------------------------------------------
 // Y pass
 // ---------------------------------------------------------------------------
@@ -69,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
   constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
   constexpr int COLS = kBlock / TPT;
-  __shared__ C2<T> smem[NY * COLS];
+  __shared__ C2<T> smem[(SCFFT_PP_Y ? 2 : 1) * NY * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -89,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
   C2<T> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? p[(size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
-  LdsCols<T, COLS> lds{smem, col};
+  ColLds<SCFFT_PP_Y, T, NY, COLS> lds{smem, col};
   if constexpr (INV)
     fft_inverse<T, NY, E>(v, j, lds, tw, 1);
   else
@@ -111,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = kBlock / TPT;
-  __shared__ C2<T> smem[NZ * COLS];
+  __shared__ C2<T> smem[(SCFFT_PP_Z ? 2 : 1) * NZ * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -146,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
 #pragma unroll
     for (int m = 0; m < E; ++m)
       v[c][m] = valid ? p[c * cs + (size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
-  LdsCols<T, COLS> lds{smem, col};
+  ColLds<SCFFT_PP_Z, T, NZ, COLS> lds{smem, col};
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
 
