@@ -122,7 +122,12 @@ typedef struct {
  *   max_iter     stop with SCFFT_WARN_NOT_CONVERGED after this many (200)
  *   fixed_iter   if > 0, run exactly this many and skip the test
  *   smooth_phi   if nonzero, Phi's symbol is Gaussian-smoothed too (default 0)
- *   sigma_scale  smoothing width in units of half the cell diagonal (1) */
+ *   sigma_scale  smoothing width in units of half the cell diagonal (1)
+ *   fuse_xy      per-component steps (warm start, masks, exterior update with
+ *                fixed_iter) as one fused xy-plane pass instead of y inverse,
+ *                x pass, y forward, where the plane fits on chip (Nx = Ny <=
+ *                128): 0 never, 1 (default) where measured faster (FP32),
+ *                2 always.  Results agree to rounding. */
 typedef struct {
   double delta_it;
   int32_t min_iter;
@@ -130,6 +135,8 @@ typedef struct {
   int32_t fixed_iter;
   int32_t smooth_phi;
   double sigma_scale;
+  int32_t fuse_xy;
+  int32_t reserved;
 } scfft_rhs_opts;
 
 typedef struct {
@@ -285,6 +292,12 @@ enum {
   SCFFT_KERNEL_Y_INV,
   SCFFT_KERNEL_Z_CURL,       /* z transform, smoothed i k x, inverse       */
   SCFFT_KERNEL_Z_PHI,        /* z transform, i k x / |k|^2, inverse        */
+  SCFFT_KERNEL_XY_FWD,       /* fused xy-plane passes (one component, one  */
+  SCFFT_KERNEL_XY_HIN,       /* z plane in LDS): y inverse, x inverse,     */
+  SCFFT_KERNEL_XY_MASK,      /* pointwise step, x forward, y forward       */
+  SCFFT_KERNEL_XY_UPDATE,
+  SCFFT_KERNEL_XY_UPDATE_LAST,
+  SCFFT_KERNEL_XY_STORE,
   SCFFT_KERNEL_KINDS
 };
 

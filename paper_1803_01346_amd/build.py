@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libscfft.so")
 
-SOURCES = ["passes.hip", "pointwise.hip", "scfft_api.cpp", "host_model.cpp"]
+SOURCES = ["passes.hip", "xyplane.hip", "pointwise.hip", "scfft_api.cpp", "host_model.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SCFFT_OFFLOAD_ARCH", "gfx950")

@@ -48,6 +48,19 @@ enum XOp : int {
 
 enum ZSym : int { Z_CURL = 0, Z_PHI = 1, Z_PHI_SMOOTH = 2 };
 
+// Fused xy-plane passes (one component, one z plane, plane held in LDS):
+// Y inverse, X inverse, per-component pointwise step, X forward, Y forward.
+enum XYOp : int {
+  XY_FWD = 0,      // real input -> x, y forward
+  XY_HIN,          // -curl e on Omega, warm start on Omega_out -> out (Omega), forward
+  XY_MASK,         // chi * v, forward
+  XY_UPDATE,       // exterior update of Eq. 5 with a fixed iteration count, forward
+  XY_UPDATE_LAST,  // the same, storing hdot and the next warm start on Omega_out
+  XY_STORE,        // real output
+  XY_NUM_OPS
+};
+constexpr size_t kXYMaxLds = 160 * 1024;
+
 template <typename T>
 struct XArgs {
   const T* in;           // X_FWD
@@ -83,6 +96,10 @@ template <typename T>
 hipError_t launch_ypass(const Plan<T>& p, bool inverse, hipStream_t s, KTime t = {});
 template <typename T>
 hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t = {});
+template <typename T>
+bool xypass_supported(const Plan<T>& p);
+template <typename T>
+hipError_t launch_xypass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t = {});
 
 // ---- pointwise / reduction kernels (pointwise.hip) ----
 hipError_t launch_sum_partials(const double* partials, int n, int stride, int ncomp, double* out,

@@ -53,8 +53,18 @@ static void launch(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime t, Args
 #ifndef SCFFT_EZ_F32
 #define SCFFT_EZ_F32 8
 #endif
-template <typename T>
-constexpr int ex_max() { return sizeof(T) == 8 ? SCFFT_EX_F64 : SCFFT_EX_F32; }
+#ifndef SCFFT_EX1_F64
+#define SCFFT_EX1_F64 8
+#endif
+#ifndef SCFFT_EX1_F32
+#define SCFFT_EX1_F32 8
+#endif
+// X passes: NC = 3 components per thread, or 1 (fewer registers: longer lines)
+template <typename T, int NC = 3>
+constexpr int ex_max() {
+  return NC == 1 ? (sizeof(T) == 8 ? SCFFT_EX1_F64 : SCFFT_EX1_F32)
+                 : (sizeof(T) == 8 ? SCFFT_EX_F64 : SCFFT_EX_F32);
+}
 template <typename T>
 constexpr int ey_max() { return sizeof(T) == 8 ? SCFFT_EY_F64 : SCFFT_EY_F32; }
 template <typename T>
@@ -241,10 +251,15 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
   }
 }
 
-template <typename T, int NX, int OP>
+// NC = 3: all three components per row (the power law, the moment, the
+// exterior update with convergence sums); NC = 1: one component per block
+// (blockIdx.y), for the steps that act on each component alone.
+template <typename T, int NX, int OP, int NC>
 __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
+  static_assert(NC == 3 || NC == 1, "components per block");
+  static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT), "needs all components");
   constexpr int M = NX / 2;
-  constexpr int E = elems_per_thread(M, ex_max<T>());
+  constexpr int E = elems_per_thread(M, ex_max<T, NC>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
   constexpr bool HAS_INV = OP != X_FWD;
@@ -266,9 +281,10 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   const size_t csn = (size_t)nrows;            // component stride, Nyquist column
   const size_t csr = (size_t)nrows * NX;       // component stride, real field
   const C2<T>* __restrict__ tw = P.ax.tw;      // exp(-2 pi i k / NX)
+  const int c0 = NC == 3 ? 0 : (int)blockIdx.y;  // first component of this block
   L lds{smem, rl};
 
-  T a[3][2 * E];
+  T a[NC][2 * E];
   unsigned clamps = 0;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
   const int y = rr % P.ny;
@@ -279,15 +295,16 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   constexpr bool NEED_CHI = OP == X_LAW || OP == X_HIN || OP == X_MASK || OP == X_UPDATE ||
                             OP == X_UPDATE_LAST || OP == X_MOMENT;
   constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST;
-  C2<T> Xs[HAS_INV ? 3 : 1][E];
-  C2<T> Xn[3];
+  C2<T> Xs[HAS_INV ? NC : 1][E];
+  C2<T> Xn[NC];
   if constexpr (HAS_INV) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int cc = 0; cc < NC; ++cc) {
+      const int c = c0 + cc;
 #pragma unroll
       for (int m = 0; m < E; ++m)
-        Xs[c][m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-      Xn[c] = (valid && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
+        Xs[cc][m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
+      Xn[cc] = (valid && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
     }
   }
   uint8_t ch[2 * E];
@@ -299,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   // X_UPDATE*: hdot^i (all nodes when tracking iterates, else Omega only:
   // with a fixed iteration count only hdot_in is read back)
   const T* auxp = OP == X_FWD ? A.in : (OP == X_HIN ? A.warm : A.out);
-  T aux[(NEED_AUX || OP == X_FWD) ? 3 : 1][2 * E];
+  T aux[(NEED_AUX || OP == X_FWD) ? NC : 1][2 * E];
   if constexpr (NEED_AUX || OP == X_FWD) {
 #pragma unroll
     for (int e = 0; e < 2 * E; ++e) {
@@ -308,14 +325,14 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       if constexpr (OP == X_UPDATE) need = need && (A.track || ch[e] != 0);
       if constexpr (OP == X_UPDATE_LAST) need = need && A.track;
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        aux[c][e] = need ? auxp[c * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
+      for (int cc = 0; cc < NC; ++cc)
+        aux[cc][e] = need ? auxp[(c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
     }
   }
 
   if constexpr (HAS_INV) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
       for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Xs[c][m]);
       if (j == 0) lds.store(M, Xn[c]);
@@ -350,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       const bool in = ch[NEED_CHI ? e : 0] != 0;
       if constexpr (OP == X_FWD) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a[c][e] = aux[c][e];
+        for (int cc = 0; cc < NC; ++cc) a[cc][e] = aux[cc][e];
       } else if constexpr (OP == X_LAW) {
         if (in) {
           const T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
@@ -362,45 +379,45 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       } else if constexpr (OP == X_HIN) {
         if (!in && A.warm) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) a[c][e] = aux[c][e];
+          for (int cc = 0; cc < NC; ++cc) a[cc][e] = aux[cc][e];
         }
         if (valid && (A.track || in)) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+          for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
         }
       } else if constexpr (OP == X_MASK) {
         if (!in) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) a[c][e] = T(0);
+          for (int cc = 0; cc < NC; ++cc) a[cc][e] = T(0);
         }
       } else if constexpr (OP == X_UPDATE || OP == X_UPDATE_LAST) {
         T d2 = T(0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T old = aux[c][e];
-          const T nw = in ? old : A.hedot[c] + a[c][e];
+        for (int cc = 0; cc < NC; ++cc) {
+          const T old = aux[cc][e];
+          const T nw = in ? old : A.hedot[c0 + cc] + a[cc][e];
           const T dd = nw - old;
           d2 += dd * dd;
-          a[c][e] = nw;
+          a[cc][e] = nw;
         }
         if (valid && !in) {
           if (A.track) {
             acc0 += sqrt((double)d2);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+            for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
           } else if constexpr (OP == X_UPDATE_LAST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+            for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
             if (A.warm_out) {
 #pragma unroll
-              for (int c = 0; c < 3; ++c) A.warm_out[c * csr + idx] = a[c][e];
+              for (int cc = 0; cc < NC; ++cc) A.warm_out[(c0 + cc) * csr + idx] = a[cc][e];
             }
           }
         }
       } else if constexpr (OP == X_STORE) {
         if (valid) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) A.out[c * csr + idx] = a[c][e];
+          for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
         }
       } else if constexpr (OP == X_MOMENT) {
         const bool use = valid && (!A.omega_only || in);
@@ -446,10 +463,11 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 
   if constexpr (HAS_FWD) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int cc = 0; cc < NC; ++cc) {
+      const int c = c0 + cc;
       C2<T> Z[E];
 #pragma unroll
-      for (int m = 0; m < E; ++m) Z[m] = {a[c][2 * m], a[c][2 * m + 1]};
+      for (int m = 0; m < E; ++m) Z[m] = {a[cc][2 * m], a[cc][2 * m + 1]};
       fft_forward<T, M, E>(Z, j, lds, tw, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Z[m]);
@@ -478,9 +496,9 @@ constexpr int tpt_of() {
   return N / elems_per_thread(N, EMAX);
 }
 
-template <typename T, int NX>
+template <typename T, int NX, int NC = 3>
 static int xblocks_n(const Plan<T>& p) {
-  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T>()>();
+  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T, NC>()>();
   return (p.ny * p.nz + ROWS - 1) / ROWS;
 }
 
@@ -498,27 +516,41 @@ int xpass_blocks(const Plan<T>& p) {
   return -1;
 }
 
-template <typename T, int NX>
-static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
-  const dim3 grid(xblocks_n<T, NX>(p)), block(kBlock);
+template <typename T, int NX, int NC>
+static hipError_t xlaunch_nc(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
+  const dim3 grid(xblocks_n<T, NX, NC>(p), NC == 3 ? 1 : 3), block(kBlock);
   switch (op) {
-    case X_FWD: launch(xpass_kernel<T, NX, X_FWD>, grid, block, s, t, p, a); break;
-    case X_LAW: launch(xpass_kernel<T, NX, X_LAW>, grid, block, s, t, p, a); break;
-    case X_HIN: launch(xpass_kernel<T, NX, X_HIN>, grid, block, s, t, p, a); break;
-    case X_MASK: launch(xpass_kernel<T, NX, X_MASK>, grid, block, s, t, p, a); break;
-    case X_UPDATE:
-      launch(xpass_kernel<T, NX, X_UPDATE>, grid, block, s, t, p, a);
-      break;
+    case X_FWD: launch(xpass_kernel<T, NX, X_FWD, NC>, grid, block, s, t, p, a); break;
+    case X_HIN: launch(xpass_kernel<T, NX, X_HIN, NC>, grid, block, s, t, p, a); break;
+    case X_MASK: launch(xpass_kernel<T, NX, X_MASK, NC>, grid, block, s, t, p, a); break;
+    case X_UPDATE: launch(xpass_kernel<T, NX, X_UPDATE, NC>, grid, block, s, t, p, a); break;
     case X_UPDATE_LAST:
-      launch(xpass_kernel<T, NX, X_UPDATE_LAST>, grid, block, s, t, p, a);
+      launch(xpass_kernel<T, NX, X_UPDATE_LAST, NC>, grid, block, s, t, p, a);
       break;
-    case X_STORE: launch(xpass_kernel<T, NX, X_STORE>, grid, block, s, t, p, a); break;
-    case X_MOMENT:
-      launch(xpass_kernel<T, NX, X_MOMENT>, grid, block, s, t, p, a);
-      break;
-    default: return hipErrorInvalidValue;
+    case X_STORE: launch(xpass_kernel<T, NX, X_STORE, NC>, grid, block, s, t, p, a); break;
+    default:
+      if constexpr (NC == 3) {
+        if (op == X_LAW) {
+          launch(xpass_kernel<T, NX, X_LAW, 3>, grid, block, s, t, p, a);
+          break;
+        }
+        if (op == X_MOMENT) {
+          launch(xpass_kernel<T, NX, X_MOMENT, 3>, grid, block, s, t, p, a);
+          break;
+        }
+      }
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Steps acting on one component at a time run one component per block
+// (a third of the registers, more rows in flight).
+template <typename T, int NX>
+static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
+  const bool per_component = op == X_FWD || op == X_HIN || op == X_MASK || op == X_STORE ||
+                             ((op == X_UPDATE || op == X_UPDATE_LAST) && !a.track);
+  return per_component ? xlaunch_nc<T, NX, 1>(p, op, a, s, t) : xlaunch_nc<T, NX, 3>(p, op, a, s, t);
 }
 
 template <typename T>

@@ -252,6 +252,14 @@ hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
   return prof_done(c, launch_zpass<T>(p, sym, (T)coef, c->stream, t), t);
 }
 
+template <typename T>
+hipError_t run_xy(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
+  KTime t;
+  hipError_t e = prof_slot(c, SCFFT_KERNEL_XY_FWD + op, &t);
+  if (e != hipSuccess) return e;
+  return prof_done(c, launch_xypass<T>(p, op, a, c->stream, t), t);
+}
+
 // Y forward, Z (symbol), Y inverse: the middle of one operator application.
 template <typename T>
 hipError_t spectral_middle(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
@@ -259,6 +267,62 @@ hipError_t spectral_middle(scfft_ctx* c, const Plan<T>& p, int sym, double coef)
   if ((e = run_y<T>(c, p, false)) != hipSuccess) return e;
   if ((e = run_z<T>(c, p, sym, coef)) != hipSuccess) return e;
   return run_y<T>(c, p, true);
+}
+
+// fuse_xy: 0 never, 1 where the fused plane pass measured faster (FP32; in
+// FP64 one 133 KB plane per CU leaves too few waves), 2 always (if it fits).
+template <typename T>
+bool use_xy(const scfft_ctx* c, const Plan<T>& p) {
+  if (!xypass_supported<T>(p)) return false;
+  return c->opts.fuse_xy >= 2 || (c->opts.fuse_xy == 1 && sizeof(T) == 4);
+}
+
+// Fixed iteration count with fused xy-plane passes: the per-component steps
+// (warm start, masks, exterior update) each take one pass over the spectrum
+// instead of three; only the power law, which needs |j| over the three
+// components, keeps the Y inverse / X / Y forward sequence.
+template <typename T>
+scfft_status rhs_fused(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, const T* h, T* hdot,
+                       scfft_rhs_stats* stats) {
+  const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
+  const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
+  const int fixed = c->opts.fixed_iter;
+  T* warm = wsp<T>(c, c->off_warm);
+  a.in = h;
+  a.out = hdot;
+  a.track = 0;
+  HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));                     // F(h) in x, y
+  HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));                   // j = C_s h (Eq. 4)
+  HIPCHK(c, run_y<T>(c, p, true));
+  HIPCHK(c, run_x<T>(c, p, X_LAW, a));                       // e (Eq. 1)
+  HIPCHK(c, run_y<T>(c, p, false));
+  HIPCHK(c, run_z<T>(c, p, Z_CURL, -norm));                  // -C_s e (Eq. 3)
+  a.warm = c->has_warm ? warm : nullptr;
+  HIPCHK(c, run_xy<T>(c, p, XY_HIN, a));                     // hdot^0
+  for (int it = 0; it < fixed; ++it) {                       // iteration (5)
+    HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));                 // jdot^i
+    HIPCHK(c, run_xy<T>(c, p, XY_MASK, a));                  // jdot_in^i
+    HIPCHK(c, run_z<T>(c, p, phi_sym, norm));                // Phi[jdot_in^i] (Eq. 7)
+    const bool last = it + 1 == fixed;
+    a.warm_out = last ? warm : nullptr;
+    HIPCHK(c, run_xy<T>(c, p, last ? XY_UPDATE_LAST : XY_UPDATE, a));
+  }
+  c->has_warm = true;
+  scfft_status st = SCFFT_OK;
+  if (stats) {
+    unsigned long long cl = 0;
+    HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
+    c->clamp_seen = (int64_t)cl;
+    stats->iters = fixed;
+    stats->converged = 1;
+    stats->last_delta = -1.0;
+    stats->clamps = new_clamps;
+    if (new_clamps > 0) st = SCFFT_WARN_CLAMPED;
+  }
+  return st;
 }
 
 template <typename T>
@@ -275,6 +339,8 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
 
   XArgs<T> a = base_args<T>(c);
   for (int d = 0; d < 3; ++d) a.hedot[d] = (T)hedot[d];
+
+  if (c->opts.fixed_iter > 0 && use_xy<T>(c, p)) return rhs_fused<T>(c, p, a, h, hdot, stats);
 
   // j = C_s h  (Eq. 4)
   a.in = h;
@@ -360,6 +426,12 @@ scfft_status apply_operator(scfft_ctx* c, const T* v, T* out, int sym, double si
   XArgs<T> a = base_args<T>(c);
   a.in = v;
   a.out = out;
+  if (use_xy<T>(c, p)) {
+    HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));
+    HIPCHK(c, run_z<T>(c, p, sym, sign * norm));
+    HIPCHK(c, run_xy<T>(c, p, XY_STORE, a));
+    return SCFFT_OK;
+  }
   HIPCHK(c, run_x<T>(c, p, X_FWD, a));
   HIPCHK(c, spectral_middle<T>(c, p, sym, sign * norm));
   HIPCHK(c, run_x<T>(c, p, X_STORE, a));
@@ -622,6 +694,8 @@ void scfft_default_rhs_opts(scfft_rhs_opts* o) {
   o->fixed_iter = 0;
   o->smooth_phi = 0;
   o->sigma_scale = 1.0;
+  o->fuse_xy = 1;
+  o->reserved = 0;
 }
 
 void scfft_default_ode_opts(scfft_ode_opts* o) {
@@ -789,7 +863,7 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   if (!ctx || !o) return SCFFT_ERR_ARG;
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
-      !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter)
+      !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2)
     return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");
   const bool resigma = o->sigma_scale != ctx->opts.sigma_scale;
   ctx->opts = *o;

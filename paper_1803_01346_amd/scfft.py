@@ -55,7 +55,8 @@ class Shape(C.Structure):
 
 class RhsOpts(C.Structure):
     _fields_ = [("delta_it", C.c_double), ("min_iter", C.c_int32), ("max_iter", C.c_int32),
-                ("fixed_iter", C.c_int32), ("smooth_phi", C.c_int32), ("sigma_scale", C.c_double)]
+                ("fixed_iter", C.c_int32), ("smooth_phi", C.c_int32), ("sigma_scale", C.c_double),
+                ("fuse_xy", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RhsStats(C.Structure):
@@ -372,7 +373,8 @@ def scfft_set_state(ctx, blob):
 
 
 KERNEL_KINDS = ["X_FWD", "X_LAW", "X_HIN", "X_MASK", "X_UPDATE", "X_UPDATE_LAST", "X_STORE",
-                "X_MOMENT", "Y_FWD", "Y_INV", "Z_CURL", "Z_PHI"]
+                "X_MOMENT", "Y_FWD", "Y_INV", "Z_CURL", "Z_PHI", "XY_FWD", "XY_HIN", "XY_MASK",
+                "XY_UPDATE", "XY_UPDATE_LAST", "XY_STORE"]
 
 
 def scfft_profile(ctx, enable):

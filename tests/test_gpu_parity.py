@@ -17,6 +17,7 @@ NONCUBIC = small_cfg((16, 32, 64), (1.5, 2.0, 3.0), workloads.shape_cup(1.0, 0.6
 TINY = small_cfg((8, 8, 8), (1.0, 1.0, 1.0), workloads.shape_cube(0.5))
 FLAT = small_cfg((64, 16, 8), (4.0, 1.0, 1.0), workloads.shape_cylinder(0.6, 1.2, axis=0))
 CUP64 = workloads.config("cup64")
+SQZ = small_cfg((32, 32, 16), (2.0, 2.0, 1.0), workloads.shape_cylinder(0.8, 1.2))
 
 
 def _np(t):
@@ -30,9 +31,11 @@ def _need_gpu():
     scfft.load()
 
 
-@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, FLAT, CUBE32, CUP64], ids=["8", "16x32x64", "64x16x8", "32", "64"])
-def test_curl_and_phi_fp64(cfg):
-    s = sim(cfg)
+@pytest.mark.parametrize("fuse", [2, 0])
+@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, FLAT, CUBE32, CUP64, SQZ],
+                         ids=["8", "16x32x64", "64x16x8", "32", "64", "32x32x16"])
+def test_curl_and_phi_fp64(cfg, fuse):
+    s = sim(cfg, fuse_xy=fuse)
     g, _ = oracle_problem(cfg)
     rng = np.random.default_rng(1)
     v = rng.normal(size=s.field_shape)               # full-band input, Nyquist included
@@ -48,9 +51,10 @@ def test_curl_and_phi_fp64(cfg):
     assert rel_max(_np(out), want) < 1e-12
 
 
-def test_curl_and_phi_fp64_128():
+@pytest.mark.parametrize("fuse", [2, 0])
+def test_curl_and_phi_fp64_128(fuse):
     cfg = workloads.config("cup128")
-    s = sim(cfg)
+    s = sim(cfg, fuse_xy=fuse)
     g, _ = oracle_problem(cfg)
     v = state(cfg, seed=3)
     dv = to_dev(torch, v, torch.float64)
@@ -60,9 +64,10 @@ def test_curl_and_phi_fp64_128():
     assert rel_max(_np(out), operators.curl_s(v, g.grid)) < 1e-12
 
 
-@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, CUBE32, CUP64], ids=["8", "16x32x64", "32", "64"])
-def test_rhs_fixed_iter_fp64(cfg):
-    s = sim(cfg, fixed_iter=3)
+@pytest.mark.parametrize("fuse", [2, 0])
+@pytest.mark.parametrize("cfg", [TINY, NONCUBIC, CUBE32, CUP64, SQZ], ids=["8", "16x32x64", "32", "64", "32x32x16"])
+def test_rhs_fixed_iter_fp64(cfg, fuse):
+    s = sim(cfg, fixed_iter=3, fuse_xy=fuse)
     prob, u = oracle_problem(cfg, fixed_iter=3)
     h = state(cfg, seed=2)
     dh = to_dev(torch, h, torch.float64)
@@ -88,9 +93,10 @@ def test_rhs_adaptive_fp64(cfg):
         assert rel_max(_np(out), want) < 1e-10
 
 
-def test_rhs_fp32_within_1e4():
+@pytest.mark.parametrize("fuse", [2, 0])
+def test_rhs_fp32_within_1e4(fuse):
     cfg = CUP64
-    s = sim(cfg, precision=scfft.F32, fixed_iter=3)
+    s = sim(cfg, precision=scfft.F32, fixed_iter=3, fuse_xy=fuse)
     prob, u = oracle_problem(cfg, fixed_iter=3)
     h = state(cfg, seed=5)
     out, _ = s.rhs_eval(0.004, to_dev(torch, h, torch.float32))
@@ -181,3 +187,27 @@ def test_integrate_adaptive_fp64_agrees_with_oracle():
                           breakpoints=prob.drive.breakpoints())
     assert abs(st.accepted - so.accepted) <= 2
     assert rel_max(_np(h), y) < 1e-6
+
+
+def test_rhs_fixed_iter_fp64_128_sampled():
+    """Full bench size (128^3 shield, fixed 3 iterations, fused passes): the
+    oracle checks the rate on Omega, where it equals -C_s e exactly (the
+    exterior iteration leaves it unchanged), and the fused and row/column
+    schedules agree everywhere."""
+    from oracle import law
+    cfg = workloads.config("cup128")
+    prob, u = oracle_problem(cfg)
+    h = state(cfg, seed=8, bg=(0.02, 0.0, 0.02))
+    dh = to_dev(torch, h, torch.float64)
+    fused = sim(cfg, fixed_iter=3, fuse_xy=2)
+    plain = sim(cfg, fixed_iter=3, fuse_xy=0)
+    a, _ = fused.rhs_eval(0.005, dh)
+    b, _ = plain.rhs_eval(0.005, dh)
+    torch.cuda.synchronize()
+    A, B = _np(a), _np(b)
+    assert rel_max(A, B) < 1e-12
+    j = operators.curl_s(h, prob.grid)
+    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out)
+    want = -operators.curl_s(e, prob.grid)
+    m = prob.chi == 1
+    assert np.max(np.abs(A[:, m] - want[:, m])) <= 1e-10 * np.max(np.abs(want[:, m]))
