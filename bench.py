@@ -17,7 +17,6 @@ import os
 import sys
 import time
 
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -26,40 +25,6 @@ HBM_PEAK_GBS = 8000.0
 FIXED_ITER = 3
 T_STAR = 0.005            # s: quarter period of the 50 Hz drive (peak field)
 DT_STEP = 1e-8            # s: fixed step of the timed integration
-
-
-def algorithmic_bytes(kind, n, w, frac_out, track=False):
-    """Bytes a kernel launch must move at minimum (one read of its inputs,
-    one write of its outputs), for an n = (nx, ny, nz) grid and word size w.
-    track=False is the fixed-iteration mode the benchmark runs: exterior
-    updates then read hdot only on Omega and the last one writes hdot and the
-    next warm start on Omega_out; track=True keeps every iterate (adaptive)."""
-    nx, ny, nz = n
-    nodes = nx * ny * nz
-    S = 3 * nz * ny * (nx // 2 + 1) * 2 * w        # half spectrum, 3 components
-    F = 3 * nodes * w                              # real 3-vector field
-    Mk = nodes                                     # uint8 mask
-    fo, fi = frac_out, 1.0 - frac_out
-    if track:
-        hin = S + Mk + F * fo + F + S              # warm read (out), hdot write (all)
-        upd = S + Mk + 2 * F * fo + S              # hdot read/write on Omega_out
-        last = S + Mk + 2 * F * fo
-    else:
-        hin = S + Mk + F * fo + F * fi + S         # warm read (out), hdot write (Omega)
-        upd = S + Mk + F * fi + S                  # hdot_in read (Omega)
-        last = S + Mk + 2 * F * fo                 # hdot and warm writes (out)
-    table = {
-        "X_FWD": F + S,
-        "X_LAW": S + Mk + S,
-        "X_HIN": hin,
-        "X_MASK": S + Mk + S,
-        "X_UPDATE": upd,
-        "X_UPDATE_LAST": last,
-        "X_STORE": S + F,
-        "X_MOMENT": S,
-        "Y_FWD": 2 * S, "Y_INV": 2 * S, "Z_CURL": 2 * S, "Z_PHI": 2 * S,
-    }
-    return int(table[kind])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs_passes_cup128_f64_hbm_traffic.md")
@@ -188,8 +153,6 @@ def main():
 
     sim = make_sim(cfg, scfft.F64, FIXED_ITER)
     h, h_np = initial_state(sim, cfg)
-    mask = sim.mask_host()
-    frac_out = float(np.mean(mask == 0))
     print("bench: %s FP64, warmup %d steps" % (args.config, args.warmup), file=sys.stderr, flush=True)
     run_steps(sim, h, T_STAR, args.warmup)
     torch.cuda.synchronize()
@@ -212,16 +175,16 @@ def main():
         run_steps(sim, h, T_STAR, args.steps)
         prof = scfft.scfft_profile_read(sim.ctx)
         scfft.scfft_profile(sim.ctx, 0)
-        for kind, (la, ms) in prof.items():
+        for kind, (la, ms, by) in prof.items():
             if la:
                 avg_s = ms / la * 1e-3
-                b = algorithmic_bytes(kind, n, 8, frac_out)
                 per_kind[kind] = dict(launches=la, avg_us=round(avg_s * 1e6, 2),
-                                      GBs=round(b / avg_s / 1e9, 1), total_ms=round(ms, 3))
+                                      bytes_per_launch=int(by / la),
+                                      GBs=round(by / (ms * 1e-3) / 1e9, 1), total_ms=round(ms, 3))
         dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
         dom_avg = per_kind[dom]["avg_us"] * 1e-6
-        dom_bytes = algorithmic_bytes(dom, n, 8, frac_out)
-        achieved = dom_bytes / dom_avg / 1e9
+        dom_bytes = per_kind[dom]["bytes_per_launch"]
+        achieved = per_kind[dom]["GBs"]
 
     # right-hand side alone (no integrator work)
     rhs_ps, hd64 = time_rhs_only(sim, h, 50)
@@ -275,7 +238,8 @@ def main():
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom),
-            "bytes_per_launch": dom_bytes, "avg_launch_us": per_kind[dom]["avg_us"]},
+            "bytes_per_launch": dom_bytes, "avg_launch_us": per_kind[dom]["avg_us"],
+            "launches": per_kind[dom]["launches"]},
         "kernels": per_kind,
         "cpu_baseline": cpu,
     }

@@ -127,7 +127,11 @@ typedef struct {
  *                fixed_iter) as one fused xy-plane pass instead of y inverse,
  *                x pass, y forward, where the plane fits on chip (Nx = Ny <=
  *                128): 0 never, 1 (default) where measured faster (FP32),
- *                2 always.  Results agree to rounding. */
+ *                2 always.  Results agree to rounding.
+ *   prune_box    1 (default): skip the parts of the transforms that only touch
+ *                zeros or unused values outside the bounding box of Omega
+ *                (fields masked to Omega, rates needed on Omega); 0: full
+ *                transforms.  Results are identical. */
 typedef struct {
   double delta_it;
   int32_t min_iter;
@@ -136,7 +140,7 @@ typedef struct {
   int32_t smooth_phi;
   double sigma_scale;
   int32_t fuse_xy;
-  int32_t reserved;
+  int32_t prune_box;
 } scfft_rhs_opts;
 
 typedef struct {
@@ -305,10 +309,13 @@ enum {
  * Each pass dispatch carries its own start/stop HIP event pair on the context
  * stream, so the durations are those of the kernel bodies. */
 scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable);
-/* Launch counts and summed kernel durations (ms) per kind since enable;
- * synchronises with the recorded events. */
+/* Launch counts, summed kernel durations (ms) and summed algorithmic bytes
+ * (one read of each launch's inputs and one write of its outputs, for the
+ * ranges it covered) per kind since enable; total_bytes may be NULL.
+ * Synchronises with the recorded events. */
 scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KINDS],
-                                double total_ms[SCFFT_KERNEL_KINDS]);
+                                double total_ms[SCFFT_KERNEL_KINDS],
+                                double total_bytes[SCFFT_KERNEL_KINDS]);
 
 /* ---- checkpoint ---- */
 

@@ -26,12 +26,28 @@ struct AxisTab {
 // Spectrum and sizes seen by the pass kernels.
 //   main[c][z][y][kx], kx = 0..nx/2-1   (x-transformed columns)
 //   nyq [c][z][y]                       (the kx = nx/2 column)
+// Index ranges that let passes skip work outside the bounding box of the
+// superconductor (fields masked to Omega vanish outside it; rates that are
+// masked afterwards are only needed inside it).  Half-open; full by default.
+struct Ranges {
+  int zlo, zhi;            // Y pass: planes processed;  Z pass: planes loaded (others 0)
+  int ylo_in, yhi_in;      // Y pass: rows loaded (others 0)
+  int ylo_out, yhi_out;    // Y pass: rows stored
+  int zlo_out, zhi_out;    // Z pass: planes stored
+  int xylo, xyhi, xzlo, xzhi;  // X pass: rows (y, z) processed
+  int iylo, iyhi, izlo, izhi;  // X_HIN: rows whose inverse transform is needed
+};
+
 template <typename T>
 struct Plan {
   int nx, ny, nz;
   C2<T>* main;
   C2<T>* nyq;
   AxisTab<T> ax, ay, az;
+  Ranges r;
+  void full_ranges() {
+    r = Ranges{0, nz, 0, ny, 0, ny, 0, nz, 0, ny, 0, nz, 0, ny, 0, nz};
+  }
 };
 
 enum XOp : int {

@@ -88,9 +88,9 @@ using ColLds = typename std::conditional<PP, LdsColsPP<T, N, COLS>, LdsCols<T, C
 // ---------------------------------------------------------------------------
 template <typename T, int NY, bool INV>
 __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
-                                                       C2<T>* __restrict__ nyq, int M,
-                                                       int ncols_main, int ncols_nyq,
-                                                       int nblk_main, const C2<T>* __restrict__ tw) {
+                                                       C2<T>* __restrict__ nyq, int M, int nz,
+                                                       Ranges R, int nblk_main,
+                                                       const C2<T>* __restrict__ tw) {
   constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
   constexpr int COLS = kBlock / TPT;
@@ -98,22 +98,28 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
+  const int nzr = R.zhi - R.zlo;                       // planes processed
   const bool is_nyq = (int)blockIdx.x >= nblk_main;
   const int q = (is_nyq ? (int)blockIdx.x - nblk_main : (int)blockIdx.x) * COLS + col;
-  const bool valid = q < (is_nyq ? ncols_nyq : ncols_main);
+  const bool valid = q < (is_nyq ? 3 * nzr : 3 * nzr * M);
   C2<T>* p;
   size_t es;
   if (!is_nyq) {
-    const int blk = q / M, kx = q % M;
-    p = main + (size_t)blk * NY * M + kx;
+    const int blk = q / M, kx = q % M;                 // blk = c * nzr + (z - zlo)
+    const int c = blk / nzr, z = R.zlo + blk % nzr;
+    p = main + ((size_t)c * nz + z) * NY * M + kx;
     es = (size_t)M;
   } else {
-    p = nyq + (size_t)q * NY;
+    const int c = q / nzr, z = R.zlo + q % nzr;
+    p = nyq + ((size_t)c * nz + z) * NY;
     es = 1;
   }
   C2<T> v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = valid ? p[(size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
+  for (int m = 0; m < E; ++m) {
+    const int y = j + m * TPT;
+    v[m] = (valid && y >= R.ylo_in && y < R.yhi_in) ? p[(size_t)y * es] : C2<T>{T(0), T(0)};
+  }
   ColLds<SCFFT_PP_Y, T, NY, COLS> lds{smem, col};
   if constexpr (INV)
     fft_inverse<T, NY, E>(v, j, lds, tw, 1);
@@ -121,7 +127,10 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
     fft_forward<T, NY, E>(v, j, lds, tw, 1);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) p[(size_t)(j + m * TPT) * es] = v[m];
+    for (int m = 0; m < E; ++m) {
+      const int y = j + m * TPT;
+      if (y >= R.ylo_out && y < R.yhi_out) p[(size_t)y * es] = v[m];
+    }
   }
 }
 
@@ -132,7 +141,7 @@ template <typename T, int NZ, int SYM>
 __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
                                                        C2<T>* __restrict__ nyq, int ny, int M,
                                                        int nblk_main, AxisTab<T> tx, AxisTab<T> ty,
-                                                       AxisTab<T> tz, T coef) {
+                                                       AxisTab<T> tz, T coef, Ranges R) {
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = kBlock / TPT;
@@ -169,8 +178,11 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-      v[c][m] = valid ? p[c * cs + (size_t)(j + m * TPT) * es] : C2<T>{T(0), T(0)};
+    for (int m = 0; m < E; ++m) {
+      const int z = j + m * TPT;
+      v[c][m] = (valid && z >= R.zlo && z < R.zhi) ? p[c * cs + (size_t)z * es]
+                                                   : C2<T>{T(0), T(0)};
+    }
   ColLds<SCFFT_PP_Z, T, NZ, COLS> lds{smem, col};
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
@@ -209,7 +221,10 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) p[c * cs + (size_t)(j + m * TPT) * es] = v[c][m];
+      for (int m = 0; m < E; ++m) {
+        const int z = j + m * TPT;
+        if (z >= R.zlo_out && z < R.zhi_out) p[c * cs + (size_t)z * es] = v[c][m];
+      }
   }
 }
 
@@ -274,9 +289,14 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   const int rl = tid / TPT;
   const int j = tid % TPT;
   const int nrows = P.ny * P.nz;
+  const int nyb = P.r.xyhi - P.r.xylo;                 // rows processed: y, z in the range
   const int r = blockIdx.x * ROWS + rl;
-  const bool valid = r < nrows;
-  const int rr = valid ? r : 0;
+  const bool valid = r < nyb * (P.r.xzhi - P.r.xzlo);
+  const int ry = P.r.xylo + (valid ? r % nyb : 0);
+  const int rz = P.r.xzlo + (valid ? r / nyb : 0);
+  const int rr = rz * P.ny + ry;                       // global row index
+  // rows whose inverse transform is needed (elsewhere the input counts as 0)
+  const bool inv_row = valid && ry >= P.r.iylo && ry < P.r.iyhi && rz >= P.r.izlo && rz < P.r.izhi;
   const size_t csm = (size_t)nrows * M;        // component stride, main spectrum
   const size_t csn = (size_t)nrows;            // component stride, Nyquist column
   const size_t csr = (size_t)nrows * NX;       // component stride, real field
@@ -303,8 +323,8 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       const int c = c0 + cc;
 #pragma unroll
       for (int m = 0; m < E; ++m)
-        Xs[cc][m] = valid ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-      Xn[cc] = (valid && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
+        Xs[cc][m] = inv_row ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
+      Xn[cc] = (inv_row && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
     }
   }
   uint8_t ch[2 * E];
@@ -499,7 +519,8 @@ constexpr int tpt_of() {
 template <typename T, int NX, int NC = 3>
 static int xblocks_n(const Plan<T>& p) {
   constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T, NC>()>();
-  return (p.ny * p.nz + ROWS - 1) / ROWS;
+  const int rows = (p.r.xyhi - p.r.xylo) * (p.r.xzhi - p.r.xzlo);
+  return (rows + ROWS - 1) / ROWS;
 }
 
 template <typename T>
@@ -518,7 +539,9 @@ int xpass_blocks(const Plan<T>& p) {
 
 template <typename T, int NX, int NC>
 static hipError_t xlaunch_nc(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
-  const dim3 grid(xblocks_n<T, NX, NC>(p), NC == 3 ? 1 : 3), block(kBlock);
+  const int nb = xblocks_n<T, NX, NC>(p);
+  if (nb <= 0) return hipSuccess;  // empty row range
+  const dim3 grid(nb, NC == 3 ? 1 : 3), block(kBlock);
   switch (op) {
     case X_FWD: launch(xpass_kernel<T, NX, X_FWD, NC>, grid, block, s, t, p, a); break;
     case X_HIN: launch(xpass_kernel<T, NX, X_HIN, NC>, grid, block, s, t, p, a); break;
@@ -571,13 +594,15 @@ template <typename T, int NY>
 static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
   constexpr int COLS = kBlock / tpt_of<NY, ey_max<T>()>();
   const int M = p.nx / 2;
-  const int ncm = 3 * p.nz * M, ncn = 3 * p.nz;
+  const int nzr = p.r.zhi - p.r.zlo;
+  if (nzr <= 0) return hipSuccess;  // nothing to transform
+  const int ncm = 3 * nzr * M, ncn = 3 * nzr;
   const int nbm = (ncm + COLS - 1) / COLS, nbn = (ncn + COLS - 1) / COLS;
   const dim3 grid(nbm + nbn), block(kBlock);
   if (inv)
-    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, p.nyq, M, ncm, ncn, nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, p.nyq, M, p.nz, p.r, nbm, p.ay.tw);
   else
-    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, p.nyq, M, ncm, ncn, nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, p.nyq, M, p.nz, p.r, nbm, p.ay.tw);
   return hipGetLastError();
 }
 
@@ -604,15 +629,15 @@ static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KT
   switch (sym) {
     case Z_CURL:
       launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
-             p.az, coef);
+             p.az, coef, p.r);
       break;
     case Z_PHI:
       launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
-             p.az, coef);
+             p.az, coef, p.r);
       break;
     case Z_PHI_SMOOTH:
       launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax,
-             p.ay, p.az, coef);
+             p.ay, p.az, coef, p.r);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -53,6 +53,7 @@ struct scfft_ctx {
   size_t wsize;  // element size
   bool has_mask = false, has_kappa = false, has_warm = false;
   int64_t n_in = 0, n_out = 0;
+  int box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};  // index bounding box of Omega (x, y, z)
   std::string err;
   int64_t clamp_seen = 0;
 
@@ -63,6 +64,7 @@ struct scfft_ctx {
   size_t ev_used = 0;
   int64_t prof_launches[SCFFT_KERNEL_KINDS] = {};
   double prof_ms[SCFFT_KERNEL_KINDS] = {};
+  double prof_bytes[SCFFT_KERNEL_KINDS] = {};  // algorithmic bytes of the timed launches
 };
 
 namespace {
@@ -130,7 +132,57 @@ Plan<T> make_plan(scfft_ctx* c) {
     tabs[a]->sm = wsp<T>(c, o + N * 4 * sizeof(T));
     o = align_up(o + N * 5 * sizeof(T));
   }
+  p.full_ranges();
   return p;
+}
+
+// Plans restricted to the bounding box of Omega (identical results: skipped
+// inputs are exact zeros, skipped outputs are never read).
+template <typename T>
+struct BoxPlans {
+  Plan<T> full;
+  Plan<T> z_store;    // Z pass: store only the box planes (output masked to Omega next)
+  Plan<T> y_inv;      // Y inverse: box planes, store box rows
+  Plan<T> x_box;      // X pass: box rows only
+  Plan<T> y_fwd;      // Y forward of a field zero outside the box
+  Plan<T> z_load;     // Z pass of a field zero outside the box planes
+  Plan<T> x_hin;      // X_HIN with a warm start: inverse only on box rows
+  Plan<T> xy_box;     // fused plane pass on box planes only
+  Plan<T> xy_hin;     // fused X_HIN: all planes, inverse on box planes
+};
+
+template <typename T>
+BoxPlans<T> box_plans(const scfft_ctx* c, const Plan<T>& p, bool prune) {
+  BoxPlans<T> b{p, p, p, p, p, p, p, p, p};
+  if (!prune) return b;
+  const int y0 = c->box_lo[1], y1 = c->box_hi[1], z0 = c->box_lo[2], z1 = c->box_hi[2];
+  b.z_store.r.zlo_out = z0;
+  b.z_store.r.zhi_out = z1;
+  b.y_inv.r.zlo = z0;
+  b.y_inv.r.zhi = z1;
+  b.y_inv.r.ylo_out = y0;
+  b.y_inv.r.yhi_out = y1;
+  b.x_box.r.xylo = y0;
+  b.x_box.r.xyhi = y1;
+  b.x_box.r.xzlo = z0;
+  b.x_box.r.xzhi = z1;
+  b.y_fwd.r.zlo = z0;
+  b.y_fwd.r.zhi = z1;
+  b.y_fwd.r.ylo_in = y0;
+  b.y_fwd.r.yhi_in = y1;
+  b.z_load.r.zlo = z0;
+  b.z_load.r.zhi = z1;
+  b.x_hin.r.iylo = y0;
+  b.x_hin.r.iyhi = y1;
+  b.x_hin.r.izlo = z0;
+  b.x_hin.r.izhi = z1;
+  b.xy_box.r.zlo = z0;
+  b.xy_box.r.zhi = z1;
+  b.xy_box.r.izlo = z0;
+  b.xy_box.r.izhi = z1;
+  b.xy_hin.r.izlo = z0;
+  b.xy_hin.r.izhi = z1;
+  return b;
 }
 
 // Axis tables in FP64 on the host (Sec. 2: wavenumbers on the box, Gaussian
@@ -209,9 +261,10 @@ hipError_t prof_harvest(scfft_ctx* c) {
 }
 
 // Event pair for the next launch of `kind` (none when timing is off).
-hipError_t prof_slot(scfft_ctx* c, int kind, KTime* t) {
+hipError_t prof_slot(scfft_ctx* c, int kind, KTime* t, double bytes) {
   *t = KTime{};
   if (!c->prof) return hipSuccess;
+  c->prof_bytes[kind] += bytes;
   if (2 * (c->ev_used + 1) > c->ev_pool.size()) {
     hipError_t e = prof_harvest(c);  // waits for the pending launches
     if (e != hipSuccess) return e;
@@ -228,10 +281,72 @@ hipError_t prof_done(scfft_ctx* c, hipError_t launch_err, const KTime& t) {
   return launch_err;
 }
 
+// Algorithmic bytes of one pass launch: one read of what it must read and one
+// write of what it must write, for the launch's ranges.  w = word size; the
+// mask-dependent terms use the node counts of Omega and Omega_out.
+template <typename T>
+double bytes_y(const scfft_ctx* c, const Plan<T>& p) {
+  const double cw = 2.0 * sizeof(T), kx = p.nx / 2 + 1;
+  const double planes = 3.0 * (p.r.zhi - p.r.zlo);
+  return planes * kx * cw * ((p.r.yhi_in - p.r.ylo_in) + (p.r.yhi_out - p.r.ylo_out));
+}
+template <typename T>
+double bytes_z(const scfft_ctx* c, const Plan<T>& p) {
+  const double cw = 2.0 * sizeof(T), col = 3.0 * p.ny * (p.nx / 2 + 1);
+  return col * cw * ((p.r.zhi - p.r.zlo) + (p.r.zhi_out - p.r.zlo_out));
+}
+template <typename T>
+double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
+  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2 + 1;
+  const double rows = (double)(p.r.xyhi - p.r.xylo) * (p.r.xzhi - p.r.xzlo);
+  const double inv_rows = (double)std::max(0, std::min(p.r.xyhi, p.r.iyhi) - std::max(p.r.xylo, p.r.iylo)) *
+                          std::max(0, std::min(p.r.xzhi, p.r.izhi) - std::max(p.r.xzlo, p.r.izlo));
+  const double spec = 3.0 * kx * cw;            // one row of the spectrum, 3 components
+  const double mask = (double)p.nx;             // one row of the mask
+  const double node = 3.0 * w;                  // one node of a real field
+  const double nin = (double)c->n_in, nout = (double)c->n_out, all = nin + nout;
+  const double frac = rows / ((double)p.ny * p.nz);  // share of the rows in the launch
+  switch (op) {
+    case X_FWD: return rows * p.nx * node + rows * spec;
+    case X_LAW: return inv_rows * spec + rows * mask + rows * spec;
+    case X_HIN: return inv_rows * spec + rows * mask + (a.warm ? nout * frac * node : 0.0) +
+                       (a.track ? all : nin) * frac * node + rows * spec;
+    case X_MASK: return inv_rows * spec + rows * mask + rows * spec;
+    case X_UPDATE: return inv_rows * spec + rows * mask + (a.track ? all + nout : nin) * frac * node +
+                          rows * spec;
+    case X_UPDATE_LAST: return inv_rows * spec + rows * mask +
+                               (a.track ? all + nout : (a.warm_out ? 2.0 : 1.0) * nout) * frac * node;
+    case X_STORE: return inv_rows * spec + rows * p.nx * node;
+    case X_MOMENT: return inv_rows * spec + (a.omega_only ? rows * mask : 0.0);
+  }
+  return 0.0;
+}
+template <typename T>
+double bytes_xy(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
+  // per component plane: spectrum in/out, mask and real-field terms as in X
+  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2 + 1;
+  const double planes = p.r.zhi - p.r.zlo;
+  const double inv_planes = std::max(0, std::min(p.r.zhi, p.r.izhi) - std::max(p.r.zlo, p.r.izlo));
+  const double spec = 3.0 * p.ny * kx * cw, mask = 3.0 * (double)p.nx * p.ny, node = 3.0 * w;
+  const double nin = (double)c->n_in, nout = (double)c->n_out, all = nin + nout;
+  const double frac = planes / p.nz;
+  switch (op) {
+    case XY_FWD: return planes * p.ny * p.nx * node + planes * spec;
+    case XY_HIN: return inv_planes * spec + planes * mask + (a.warm ? nout * frac * node : 0.0) +
+                        (a.track ? all : nin) * frac * node + planes * spec;
+    case XY_MASK: return inv_planes * spec + planes * mask + planes * spec;
+    case XY_UPDATE: return inv_planes * spec + planes * mask + nin * frac * node + planes * spec;
+    case XY_UPDATE_LAST: return inv_planes * spec + planes * mask +
+                                (a.warm_out ? 2.0 : 1.0) * nout * frac * node;
+    case XY_STORE: return inv_planes * spec + planes * p.ny * p.nx * node;
+  }
+  return 0.0;
+}
+
 template <typename T>
 hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   KTime t;
-  hipError_t e = prof_slot(c, SCFFT_KERNEL_X_FWD + op, &t);
+  hipError_t e = prof_slot(c, SCFFT_KERNEL_X_FWD + op, &t, c->prof ? bytes_x<T>(c, p, op, a) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_xpass<T>(p, op, a, c->stream, t), t);
 }
@@ -239,7 +354,8 @@ hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
 template <typename T>
 hipError_t run_y(scfft_ctx* c, const Plan<T>& p, bool inv) {
   KTime t;
-  hipError_t e = prof_slot(c, inv ? SCFFT_KERNEL_Y_INV : SCFFT_KERNEL_Y_FWD, &t);
+  hipError_t e = prof_slot(c, inv ? SCFFT_KERNEL_Y_INV : SCFFT_KERNEL_Y_FWD, &t,
+                           c->prof ? bytes_y<T>(c, p) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_ypass<T>(p, inv, c->stream, t), t);
 }
@@ -247,7 +363,8 @@ hipError_t run_y(scfft_ctx* c, const Plan<T>& p, bool inv) {
 template <typename T>
 hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
   KTime t;
-  hipError_t e = prof_slot(c, sym == Z_CURL ? SCFFT_KERNEL_Z_CURL : SCFFT_KERNEL_Z_PHI, &t);
+  hipError_t e = prof_slot(c, sym == Z_CURL ? SCFFT_KERNEL_Z_CURL : SCFFT_KERNEL_Z_PHI, &t,
+                           c->prof ? bytes_z<T>(c, p) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_zpass<T>(p, sym, (T)coef, c->stream, t), t);
 }
@@ -255,7 +372,7 @@ hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
 template <typename T>
 hipError_t run_xy(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   KTime t;
-  hipError_t e = prof_slot(c, SCFFT_KERNEL_XY_FWD + op, &t);
+  hipError_t e = prof_slot(c, SCFFT_KERNEL_XY_FWD + op, &t, c->prof ? bytes_xy<T>(c, p, op, a) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_xypass<T>(p, op, a, c->stream, t), t);
 }
@@ -288,6 +405,8 @@ scfft_status rhs_fused(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, const T* h, T
   const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
   const int fixed = c->opts.fixed_iter;
   T* warm = wsp<T>(c, c->off_warm);
+  const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
+  const bool warm_start = c->has_warm;
   a.in = h;
   a.out = hdot;
   a.track = 0;
@@ -296,13 +415,14 @@ scfft_status rhs_fused(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, const T* h, T
   HIPCHK(c, run_y<T>(c, p, true));
   HIPCHK(c, run_x<T>(c, p, X_LAW, a));                       // e (Eq. 1)
   HIPCHK(c, run_y<T>(c, p, false));
-  HIPCHK(c, run_z<T>(c, p, Z_CURL, -norm));                  // -C_s e (Eq. 3)
-  a.warm = c->has_warm ? warm : nullptr;
-  HIPCHK(c, run_xy<T>(c, p, XY_HIN, a));                     // hdot^0
+  // -C_s e (Eq. 3); with a warm start it is needed on Omega only
+  HIPCHK(c, run_z<T>(c, warm_start ? b.z_store : p, Z_CURL, -norm));
+  a.warm = warm_start ? warm : nullptr;
+  HIPCHK(c, run_xy<T>(c, warm_start ? b.xy_hin : p, XY_HIN, a));  // hdot^0
   for (int it = 0; it < fixed; ++it) {                       // iteration (5)
-    HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));                 // jdot^i
-    HIPCHK(c, run_xy<T>(c, p, XY_MASK, a));                  // jdot_in^i
-    HIPCHK(c, run_z<T>(c, p, phi_sym, norm));                // Phi[jdot_in^i] (Eq. 7)
+    HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));         // jdot^i (needed on Omega)
+    HIPCHK(c, run_xy<T>(c, b.xy_box, XY_MASK, a));           // jdot_in^i
+    HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));         // Phi[jdot_in^i] (Eq. 7)
     const bool last = it + 1 == fixed;
     a.warm_out = last ? warm : nullptr;
     HIPCHK(c, run_xy<T>(c, p, last ? XY_UPDATE_LAST : XY_UPDATE, a));
@@ -341,6 +461,8 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   for (int d = 0; d < 3; ++d) a.hedot[d] = (T)hedot[d];
 
   if (c->opts.fixed_iter > 0 && use_xy<T>(c, p)) return rhs_fused<T>(c, p, a, h, hdot, stats);
+  const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
+  const bool warm_start = c->has_warm;
 
   // j = C_s h  (Eq. 4)
   a.in = h;
@@ -348,13 +470,16 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
   // e (Eq. 1; rho_out j outside), then -C_s e (Eq. 3)
   HIPCHK(c, run_x<T>(c, p, X_LAW, a));
-  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, -norm));
+  // -C_s e (Eq. 3); with a warm start it is needed on Omega only
+  HIPCHK(c, run_y<T>(c, p, false));
+  HIPCHK(c, run_z<T>(c, warm_start ? b.z_store : p, Z_CURL, -norm));
+  HIPCHK(c, run_y<T>(c, warm_start ? b.y_inv : p, true));
   // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out
   const int fixed = c->opts.fixed_iter;
   a.out = hdot;
   a.warm = c->has_warm ? wsp<T>(c, c->off_warm) : nullptr;
   a.track = fixed > 0 ? 0 : 1;
-  HIPCHK(c, run_x<T>(c, p, X_HIN, a));
+  HIPCHK(c, run_x<T>(c, warm_start ? b.x_hin : p, X_HIN, a));
 
   // iteration (5)
   const int max_it = fixed > 0 ? fixed : c->opts.max_iter;
@@ -363,9 +488,15 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   bool converged = false;
   double last = 0.0;
   for (;;) {
-    HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));      // jdot^i = C_s hdot^i
-    HIPCHK(c, run_x<T>(c, p, X_MASK, a));             // jdot_in^i
-    HIPCHK(c, spectral_middle<T>(c, p, phi_sym, norm));      // Phi[jdot_in^i]  (Eq. 7)
+    // jdot^i = C_s hdot^i, needed on Omega only
+    HIPCHK(c, run_y<T>(c, p, false));
+    HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));
+    HIPCHK(c, run_y<T>(c, b.y_inv, true));
+    HIPCHK(c, run_x<T>(c, b.x_box, X_MASK, a));              // jdot_in^i
+    // Phi[jdot_in^i] (Eq. 7) of a field that vanishes outside the box
+    HIPCHK(c, run_y<T>(c, b.y_fwd, false));
+    HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));
+    HIPCHK(c, run_y<T>(c, p, true));
     const bool last_known = it + 1 >= max_it;
     // with a fixed count the last update also stores the next warm start
     a.warm_out = (last_known && fixed > 0) ? wsp<T>(c, c->off_warm) : nullptr;
@@ -653,7 +784,22 @@ scfft_status set_mask_host(scfft_ctx* c, const std::vector<uint8_t>& m) {
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   int64_t in = 0;
-  for (uint8_t v : m) in += v != 0;
+  int lo[3] = {c->n[0], c->n[1], c->n[2]}, hi[3] = {0, 0, 0};
+  for (int z = 0; z < c->n[2]; ++z)
+    for (int y = 0; y < c->n[1]; ++y)
+      for (int x = 0; x < c->n[0]; ++x)
+        if (m[((size_t)z * c->n[1] + y) * c->n[0] + x]) {
+          ++in;
+          const int id[3] = {x, y, z};
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], id[a]);
+            hi[a] = std::max(hi[a], id[a] + 1);
+          }
+        }
+  for (int a = 0; a < 3; ++a) {
+    c->box_lo[a] = in ? lo[a] : 0;
+    c->box_hi[a] = in ? hi[a] : 0;
+  }
   c->n_in = in;
   c->n_out = (int64_t)c->nodes - in;
   c->has_mask = true;
@@ -695,7 +841,7 @@ void scfft_default_rhs_opts(scfft_rhs_opts* o) {
   o->smooth_phi = 0;
   o->sigma_scale = 1.0;
   o->fuse_xy = 1;
-  o->reserved = 0;
+  o->prune_box = 1;
 }
 
 void scfft_default_ode_opts(scfft_ode_opts* o) {
@@ -1048,6 +1194,7 @@ scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable) {
     for (int k = 0; k < SCFFT_KERNEL_KINDS; ++k) {
       ctx->prof_launches[k] = 0;
       ctx->prof_ms[k] = 0.0;
+      ctx->prof_bytes[k] = 0.0;
     }
     ctx->ev_used = 0;
     ctx->prof = true;
@@ -1059,12 +1206,14 @@ scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable) {
 }
 
 scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KINDS],
-                                double total_ms[SCFFT_KERNEL_KINDS]) {
+                                double total_ms[SCFFT_KERNEL_KINDS],
+                                double total_bytes[SCFFT_KERNEL_KINDS]) {
   if (!ctx || !launches || !total_ms) return SCFFT_ERR_ARG;
   HIPCHK(ctx, prof_harvest(ctx));
   for (int k = 0; k < SCFFT_KERNEL_KINDS; ++k) {
     launches[k] = ctx->prof_launches[k];
     total_ms[k] = ctx->prof_ms[k];
+    if (total_bytes) total_bytes[k] = ctx->prof_bytes[k];
   }
   return SCFFT_OK;
 }

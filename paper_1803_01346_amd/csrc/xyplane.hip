@@ -145,8 +145,9 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   __shared__ C2<T> plane[NY * RS];
 
   const int nz = P.nz;
-  const int c = blockIdx.x / nz;
-  const int z = blockIdx.x % nz;
+  const int nzr = P.r.zhi - P.r.zlo;                  // planes of this launch
+  const int c = blockIdx.x / nzr;
+  const int z = P.r.zlo + blockIdx.x % nzr;
   const int t = threadIdx.x;
   const int gx = t / TPT, j = t % TPT;
   const size_t csr = (size_t)nz * NY * NX;                    // component stride, real field
@@ -187,11 +188,17 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
     }
   }
 
+  // planes outside [izlo, izhi) need no inverse transform (their input counts as 0)
+  const bool inv_plane = z >= P.r.izlo && z < P.r.izhi;
   if constexpr (HAS_INV) {
-    for (int i = t; i < NY * M; i += G::BLOCK) plane[(i / M) * RS + (i % M)] = P.main[sbase + i];
-    for (int y = t; y < NY; y += G::BLOCK) plane[y * RS + M] = P.nyq[nbase + y];
+    if (inv_plane) {
+      for (int i = t; i < NY * M; i += G::BLOCK) plane[(i / M) * RS + (i % M)] = P.main[sbase + i];
+      for (int y = t; y < NY; y += G::BLOCK) plane[y * RS + M] = P.nyq[nbase + y];
+    } else {
+      for (int i = t; i < NY * RS; i += G::BLOCK) plane[i] = C2<T>{T(0), T(0)};
+    }
     __syncthreads();
-    plane_columns<T, NX, NY, true>(plane, P.ay.tw);
+    if (inv_plane) plane_columns<T, NX, NY, true>(plane, P.ay.tw);  // uniform per block
     __syncthreads();
   }
 
@@ -244,7 +251,9 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 static hipError_t xylaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
-  const dim3 grid(3 * p.nz), block(xy_block<T>());
+  const int nzr = p.r.zhi - p.r.zlo;
+  if (nzr <= 0) return hipSuccess;
+  const dim3 grid(3 * nzr), block(xy_block<T>());
 #define SCFFT_XY_CASE(OPV)                                                                   \
   case OPV:                                                                                  \
     if (t.start)                                                                             \

@@ -56,7 +56,7 @@ class Shape(C.Structure):
 class RhsOpts(C.Structure):
     _fields_ = [("delta_it", C.c_double), ("min_iter", C.c_int32), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("smooth_phi", C.c_int32), ("sigma_scale", C.c_double),
-                ("fuse_xy", C.c_int32), ("reserved", C.c_int32)]
+                ("fuse_xy", C.c_int32), ("prune_box", C.c_int32)]
 
 
 class RhsStats(C.Structure):
@@ -114,7 +114,8 @@ _SIGS = {
     "scfft_get_state": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
     "scfft_set_state": (C.c_int, [_P, _P, C.c_size_t]),
     "scfft_profile": (C.c_int, [_P, C.c_int32]),
-    "scfft_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "scfft_profile_read": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
     "scfft_status_string": (C.c_char_p, [C.c_int]),
     "scfft_last_error": (C.c_char_p, [_P]),
 }
@@ -382,11 +383,11 @@ def scfft_profile(ctx, enable):
 
 
 def scfft_profile_read(ctx):
-    """{kind name: (launches, total_ms)}"""
+    """{kind name: (launches, total_ms, total_algorithmic_bytes)}"""
     n = len(KERNEL_KINDS)
-    la, ms = (C.c_int64 * n)(), (C.c_double * n)()
-    _check(load().scfft_profile_read(ctx, la, ms), ctx)
-    return {k: (la[i], ms[i]) for i, k in enumerate(KERNEL_KINDS)}
+    la, ms, by = (C.c_int64 * n)(), (C.c_double * n)(), (C.c_double * n)()
+    _check(load().scfft_profile_read(ctx, la, ms, by), ctx)
+    return {k: (la[i], ms[i], by[i]) for i, k in enumerate(KERNEL_KINDS)}
 
 
 def scfft_status_string(st):

@@ -211,3 +211,25 @@ def test_rhs_fixed_iter_fp64_128_sampled():
     want = -operators.curl_s(e, prob.grid)
     m = prob.chi == 1
     assert np.max(np.abs(A[:, m] - want[:, m])) <= 1e-10 * np.max(np.abs(want[:, m]))
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("fuse", [2, 0])
+@pytest.mark.parametrize("fixed", [3, 0])
+def test_box_pruning_is_exact(prec, fuse, fixed):
+    """Skipping the work outside Omega's bounding box changes nothing: the
+    skipped inputs are exact zeros and the skipped outputs are never read."""
+    cfg = CUP64
+    dtype = torch.float64 if prec == scfft.F64 else torch.float32
+    h = to_dev(torch, state(cfg, seed=9), dtype)
+    outs = []
+    for prune in (1, 0):
+        s = sim(cfg, precision=prec, fixed_iter=fixed, fuse_xy=fuse, prune_box=prune)
+        res = []
+        for t_s in (0.002, 0.0021):                     # second call: warm start
+            o, _ = s.rhs_eval(t_s, h)
+            res.append(o.clone())
+        torch.cuda.synchronize()
+        outs.append(res)
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
