@@ -68,8 +68,8 @@ def run_steps(sim, h, t0, k, with_moment=True):
     moments = []
 
     def obs(_u, t, _p):
-        if with_moment:
-            moments.append(scfft.scfft_moment(sim.ctx, h))
+        if with_moment:  # from the current density the step already formed
+            moments.append(scfft.scfft_step_moment(sim.ctx))
         return 0
 
     st = scfft.OdeStats()

@@ -180,9 +180,11 @@ typedef struct {
   double err_last;
 } scfft_ode_stats;
 
-/* Called after every accepted step with the time (s) and the device state;
- * it may call readout entry points on the same context.  A nonzero return
- * stops the integration (scfft_integrate then returns SCFFT_OK). */
+/* Called after every accepted step with the time (s) and the device state
+ * (the integrator's own copy of h, valid during the call only; read it, do
+ * not write it); it may call readout entry points on the same context, and
+ * scfft_step_moment.  A nonzero return stops the integration
+ * (scfft_integrate then returns SCFFT_OK). */
 typedef int32_t (*scfft_observer)(void* user, double t_s, const void* h_dev);
 
 /* Right-hand side on host arrays, for scfft_bs23_host. */
@@ -254,7 +256,10 @@ scfft_status scfft_rhs_eval(scfft_ctx* ctx, double t_s, const void* h_dev, void*
 
 /* Integrate h from t0_s to t1_s in place (method of lines, Sec. 2).  The
  * observer (may be NULL) sees every accepted step.  On SCFFT_ERR_NAN or
- * SCFFT_ERR_STEP_UNDERFLOW h holds the last accepted state. */
+ * SCFFT_ERR_STEP_UNDERFLOW h holds the last accepted state.  The state is
+ * advanced in a workspace buffer and copied back to h when the call ends;
+ * the Runge-Kutta stage arguments y + c k are formed inside the first
+ * transform pass of each evaluation. */
 scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_dev,
                              const scfft_ode_opts* o, scfft_observer obs, void* user,
                              scfft_ode_stats* stats);
@@ -270,6 +275,11 @@ scfft_status scfft_current(scfft_ctx* ctx, const void* h_dev, void* j_dev);
 /* Magnetic moment m = 1/2 sum (r x j) dV in A m^2, r from the box centre,
  * over all nodes (omega_only = 0) or Omega nodes only. */
 scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only, double m_Am2[3]);
+/* Inside an integrator observer: the moment (as scfft_moment) of the state
+ * just accepted, summed from the current density j = C_s h that the
+ * right-hand side already formed at that state (Eq. 4), so no transform runs.
+ * SCFFT_ERR_STATE when called outside an observer callback. */
+scfft_status scfft_step_moment(scfft_ctx* ctx, int32_t omega_only, double m_Am2[3]);
 /* Mean of |B| = mu0 |h| (tesla) over the nodes of a device region mask. */
 scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const uint8_t* dev_region,
                                      double* b_T);

@@ -15,10 +15,13 @@
 //
 // Ops provides (buffers are named by the enum below; Y is the state):
 //   int  rhs(double t, Buf src, Buf dst)          dst = f(t, src); < 0 = error
+//                                                 (src is a state: Y or Y1)
+//   int  rhs_at(double t, Buf y, Buf k, double c, Buf dst)   dst = f(t, y + c k),
+//                                                 may use Y1 as scratch
 //   int  combo(Buf out, Buf y, Buf a, double ca, Buf b, double cb, Buf c, double cc)
 //   int  errnorm(Buf y, Buf y1, double dt, double thr, double* err)   uses K1..K4
 //   int  rate(double thr, double* r)              max_i |K1_i| / max(|Y_i|, thr)
-//   int  accept()                                 Y = Y1, K1 <-> K4
+//   int  accept()                                 Y = Y1, K1 <-> K4 (may swap buffers)
 //   int  observe(double t, int* stop)
 #pragma once
 
@@ -44,10 +47,8 @@ scfft_status bs23_run(Ops& ops, double t0, double t1, const scfft_ode_opts& o,
 
   auto step = [&](double t, double dt, double* err) -> int {
     int r;
-    if ((r = ops.combo(B_Y1, B_Y, B_K1, 0.5 * dt, B_NONE, 0.0, B_NONE, 0.0)) < 0) return r;
-    if ((r = ops.rhs(t + 0.5 * dt, B_Y1, B_K2)) < 0) return r;
-    if ((r = ops.combo(B_Y1, B_Y, B_K2, 0.75 * dt, B_NONE, 0.0, B_NONE, 0.0)) < 0) return r;
-    if ((r = ops.rhs(t + 0.75 * dt, B_Y1, B_K3)) < 0) return r;
+    if ((r = ops.rhs_at(t + 0.5 * dt, B_Y, B_K1, 0.5 * dt, B_K2)) < 0) return r;
+    if ((r = ops.rhs_at(t + 0.75 * dt, B_Y, B_K2, 0.75 * dt, B_K3)) < 0) return r;
     if ((r = ops.combo(B_Y1, B_Y, B_K1, dt * (2.0 / 9.0), B_K2, dt * (1.0 / 3.0), B_K3,
                        dt * (4.0 / 9.0))) < 0)
       return r;

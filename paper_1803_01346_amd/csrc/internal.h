@@ -79,7 +79,9 @@ constexpr size_t kXYMaxLds = 160 * 1024;
 
 template <typename T>
 struct XArgs {
-  const T* in;           // X_FWD
+  const T* in;           // X_FWD: the input field is in + in2_coef * in2 (in2 may be null)
+  const T* in2;
+  T in2_coef;
   T* out;                // X_HIN, X_UPDATE*: hdot;  X_STORE: output field
   const T* warm;         // X_HIN: warm start (nullptr: Ohm-law start)
   const uint8_t* chi;    // mask [nz][ny][nx]
@@ -93,6 +95,8 @@ struct XArgs {
                          // |delta| (adaptive stopping); 0 = fixed iteration count:
                          // only the nodes a later pass reads are touched
   T* warm_out;           // X_UPDATE_LAST with track = 0: also store hdot on Omega_out here
+  double* mom_partials;  // X_LAW: if set, 6 doubles per block: sums of r x j over all
+                         // nodes (3) and over Omega nodes (3), for the moment readout
   double pos0[3];        // coordinate of node 0 along each axis (moment)
   double step[3];        // node spacing (moment)
 };

@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 
   T a[NC][2 * E];
   unsigned clamps = 0;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
   const int y = rr % P.ny;
   const int z = rr / P.ny;
   const size_t rowbase = (size_t)rr * NX;
@@ -345,8 +345,13 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       if constexpr (OP == X_UPDATE) need = need && (A.track || ch[e] != 0);
       if constexpr (OP == X_UPDATE_LAST) need = need && A.track;
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc)
-        aux[cc][e] = need ? auxp[(c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : T(0);
+      for (int cc = 0; cc < NC; ++cc) {
+        const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1);
+        aux[cc][e] = need ? auxp[ai] : T(0);
+        if constexpr (OP == X_FWD) {
+          if (need && A.in2) aux[cc][e] += A.in2_coef * A.in2[ai];  // stage argument y + c k
+        }
+      }
     }
   }
 
@@ -389,6 +394,22 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) a[cc][e] = aux[cc][e];
       } else if constexpr (OP == X_LAW) {
+        if (A.mom_partials && valid) {
+          // moment readout of the state whose current this is: r x j, all nodes and Omega
+          const double px = A.pos0[0] + A.step[0] * x;
+          const double py = A.pos0[1] + A.step[1] * y;
+          const double pz = A.pos0[2] + A.step[2] * z;
+          const double jx = a[0][e], jy = a[1][e], jz = a[2][e];
+          const double mx = py * jz - pz * jy, my = pz * jx - px * jz, mz = px * jy - py * jx;
+          acc0 += mx;
+          acc1 += my;
+          acc2 += mz;
+          if (in) {
+            acc3 += mx;
+            acc4 += my;
+            acc5 += mz;
+          }
+        }
         if (in) {
           const T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
           power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
@@ -454,6 +475,30 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
     }
   }
 
+  if constexpr (OP == X_LAW) {
+    if (A.mom_partials) {  // uniform across the block
+      // fixed-order tree: lanes of each wavefront, then the wavefronts
+      constexpr int NW = kBlock / 64;
+      __shared__ double wsum[6 * NW];
+      double v[6] = {acc0, acc1, acc2, acc3, acc4, acc5};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+      }
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wsum[q * NW + (tid >> 6)] = v[q];
+      }
+      __syncthreads();
+      if (tid < 6) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) r += wsum[tid * NW + w];
+        A.mom_partials[6 * blockIdx.x + tid] = r;
+      }
+    }
+  }
   if (REDUCE && (OP == X_MOMENT || A.track)) {  // uniform across the block
     red[tid] = acc0;
     red[kBlock + tid] = acc1;

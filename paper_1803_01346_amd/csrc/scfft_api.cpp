@@ -49,13 +49,17 @@ struct scfft_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_main, off_nyq, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
-      off_clamp, off_ode, off_probe, total;
+      off_clamp, off_mom, off_ode, off_probe, total;
   size_t wsize;  // element size
   bool has_mask = false, has_kappa = false, has_warm = false;
   int64_t n_in = 0, n_out = 0;
   int box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};  // index bounding box of Omega (x, y, z)
   std::string err;
   int64_t clamp_seen = 0;
+  // integrator: state whose moment partials the last power-law pass recorded,
+  // and whether an observer callback is running (scfft_step_moment)
+  const void* mom_state = nullptr;
+  const void* obs_state = nullptr;  // state shown to the running observer, else null
 
   // optional per-kernel timing with HIP events on the context stream
   bool prof = false;
@@ -106,7 +110,9 @@ void layout(scfft_ctx* c) {
   c->off_scal = o;  o = align_up(o + 16 * sizeof(double));
   c->off_delta = o; o = align_up(o + kMaxDeltaSlots * sizeof(double));
   c->off_clamp = o; o = align_up(o + sizeof(unsigned long long));
-  c->off_ode = o;   o = align_up(o + 5 * 3 * nodes * w);
+  // moment partials of the power-law pass (6 per block) and their sums
+  c->off_mom = o;   o = align_up(o + (6 * xb + 8) * sizeof(double));
+  c->off_ode = o;   o = align_up(o + 6 * 3 * nodes * w);
   c->off_probe = o; o = align_up(o + (size_t)kProbeChunk * 6 * sizeof(double));
   c->total = o;
 }
@@ -307,7 +313,7 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
   const double nin = (double)c->n_in, nout = (double)c->n_out, all = nin + nout;
   const double frac = rows / ((double)p.ny * p.nz);  // share of the rows in the launch
   switch (op) {
-    case X_FWD: return rows * p.nx * node + rows * spec;
+    case X_FWD: return (a.in2 ? 2.0 : 1.0) * rows * p.nx * node + rows * spec;
     case X_LAW: return inv_rows * spec + rows * mask + rows * spec;
     case X_HIN: return inv_rows * spec + rows * mask + (a.warm ? nout * frac * node : 0.0) +
                        (a.track ? all : nin) * frac * node + rows * spec;
@@ -331,7 +337,7 @@ double bytes_xy(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a)
   const double nin = (double)c->n_in, nout = (double)c->n_out, all = nin + nout;
   const double frac = planes / p.nz;
   switch (op) {
-    case XY_FWD: return planes * p.ny * p.nx * node + planes * spec;
+    case XY_FWD: return (a.in2 ? 2.0 : 1.0) * planes * p.ny * p.nx * node + planes * spec;
     case XY_HIN: return inv_planes * spec + planes * mask + (a.warm ? nout * frac * node : 0.0) +
                         (a.track ? all : nin) * frac * node + planes * spec;
     case XY_MASK: return inv_planes * spec + planes * mask + planes * spec;
@@ -446,7 +452,11 @@ scfft_status rhs_fused(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, const T* h, T
 }
 
 template <typename T>
-scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_stats* stats) {
+// The state is h + in2_coef * in2 (in2 may be null: a Runge-Kutta stage
+// argument is formed inside the first pass).  mom: if set, the power-law
+// pass also records moment partials of that state (6 per block).
+scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_stats* stats,
+                      const T* in2 = nullptr, double in2_coef = 0.0, double* mom = nullptr) {
   const Plan<T> p = make_plan<T>(c);
   const hipStream_t s = c->stream;
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
@@ -459,6 +469,9 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
 
   XArgs<T> a = base_args<T>(c);
   for (int d = 0; d < 3; ++d) a.hedot[d] = (T)hedot[d];
+  a.in2 = in2;
+  a.in2_coef = (T)in2_coef;
+  a.mom_partials = mom;
 
   if (c->opts.fixed_iter > 0 && use_xy<T>(c, p)) return rhs_fused<T>(c, p, a, h, hdot, stats);
   const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
@@ -602,10 +615,16 @@ struct DeviceOps {
   scfft_ode_stats* st;
   scfft_status last_warn = SCFFT_OK;
 
-  int rhs(double t, Buf src, Buf dst) {
+  // dst = f(t, y + coef k); a state (k = B_NONE) also records its moment
+  // partials when an observer may ask for them
+  int eval(double t, Buf y, Buf k, double coef, Buf dst) {
     scfft_rhs_stats rs;
-    scfft_status s = rhs_impl<T>(c, t, buf[src], buf[dst], c->opts.fixed_iter > 0 ? nullptr : &rs);
+    const bool state = k == B_NONE;
+    double* mom = state && obs ? wsp<double>(c, c->off_mom) : nullptr;
+    scfft_status s = rhs_impl<T>(c, t, buf[y], buf[dst], c->opts.fixed_iter > 0 ? nullptr : &rs,
+                                 state ? nullptr : buf[k], state ? 0.0 : coef, mom);
     if (s < 0) return s;
+    if (mom) c->mom_state = buf[y];
     if (c->opts.fixed_iter > 0) {
       st->iters_total += c->opts.fixed_iter;
     } else {
@@ -616,6 +635,8 @@ struct DeviceOps {
     if (s > 0) last_warn = s;
     return 0;
   }
+  int rhs(double t, Buf src, Buf dst) { return eval(t, src, B_NONE, 0.0, dst); }
+  int rhs_at(double t, Buf y, Buf k, double coef, Buf dst) { return eval(t, y, k, coef, dst); }
   int combo(Buf out, Buf y, Buf a, double ca, Buf b, double cb, Buf cc_, double cc) {
     hipError_t e = launch_combo<T>(buf[out], buf[y], a >= 0 ? buf[a] : nullptr, ca,
                                    b >= 0 ? buf[b] : nullptr, cb, cc_ >= 0 ? buf[cc_] : nullptr, cc,
@@ -642,15 +663,18 @@ struct DeviceOps {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "rate: %s", hipGetErrorString(e));
   }
-  int accept() {
-    hipError_t e = hipMemcpyAsync(buf[B_Y], buf[B_Y1], 3 * c->nodes * sizeof(T),
-                                  hipMemcpyDeviceToDevice, c->stream);
+  int accept() {  // the state lives in the workspace: swap, no copy
+    std::swap(buf[B_Y], buf[B_Y1]);
     std::swap(buf[B_K1], buf[B_K4]);
-    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "accept: %s", hipGetErrorString(e));
+    return 0;
   }
   int observe(double t, int* stop) {
     *stop = 0;
-    if (obs) *stop = obs(user, t * c->u.t0, buf[B_Y]);
+    if (obs) {
+      c->obs_state = buf[B_Y];
+      *stop = obs(user, t * c->u.t0, buf[B_Y]);
+      c->obs_state = nullptr;
+    }
     return 0;
   }
 };
@@ -671,6 +695,10 @@ struct HostOps {
   double* bp(Buf k) { return k == B_Y ? y : b[k].data(); }
   int rhs(double t, Buf src, Buf dst) {
     return f(user, t, bp(src), bp(dst)) == 0 ? 0 : SCFFT_ERR_ARG;
+  }
+  int rhs_at(double t, Buf yy, Buf k, double coef, Buf dst) {  // stage argument in Y1
+    int r = combo(B_Y1, yy, k, coef, B_NONE, 0.0, B_NONE, 0.0);
+    return r < 0 ? r : rhs(t, B_Y1, dst);
   }
   int combo(Buf out, Buf yy, Buf a, double ca, Buf bb, double cb, Buf cc_, double cc) {
     double *o = bp(out), *py = bp(yy);
@@ -725,19 +753,27 @@ bool valid_ode_opts(const scfft_ode_opts* o) {
 template <typename T>
 scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scfft_ode_opts* o,
                             scfft_observer obs, void* user, scfft_ode_stats* st) {
+  // the state is integrated in a workspace buffer (accepting a step swaps
+  // buffers) and copied back to h at the end, also after a failure
   DeviceOps<T> ops;
   ops.c = c;
-  ops.buf[B_Y] = h;
-  for (int k = 1; k < 6; ++k) ops.buf[k] = wsp<T>(c, c->off_ode + (size_t)(k - 1) * 3 * c->nodes * sizeof(T));
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  for (int k = 0; k < 6; ++k) ops.buf[k] = wsp<T>(c, c->off_ode + (size_t)k * fb);
   ops.obs = obs;
   ops.user = user;
   ops.st = st;
+  c->mom_state = nullptr;
+  HIPCHK(c, hipMemcpyAsync(ops.buf[B_Y], h, fb, hipMemcpyDeviceToDevice, c->stream));
   scfft_ode_opts od = *o;  // convert times to t' = t / t0
   od.dt0_s = o->dt0_s / c->u.t0;
   od.dt_max_s = o->dt_max_s / c->u.t0;
   std::vector<double> stops = c->drive.kinks();
   for (int i = 0; i < o->n_bp; ++i) stops.push_back(o->breakpoints_s[i] / c->u.t0);
   scfft_status s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
+  c->mom_state = nullptr;
+  c->obs_state = nullptr;
+  HIPCHK(c, hipMemcpyAsync(h, ops.buf[B_Y], fb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   st->t_s *= c->u.t0;
   st->dt_last_s *= c->u.t0;
   if (s == SCFFT_OK && st->not_converged > 0) s = SCFFT_WARN_NOT_CONVERGED;
@@ -1103,6 +1139,26 @@ scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only,
   if (!h_dev || !m_Am2) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
   return ctx->prec == SCFFT_F64 ? moment_impl<double>(ctx, (const double*)h_dev, omega_only, m_Am2)
                                 : moment_impl<float>(ctx, (const float*)h_dev, omega_only, m_Am2);
+}
+
+scfft_status scfft_step_moment(scfft_ctx* ctx, int32_t omega_only, double m_Am2[3]) {
+  if (!ctx || !m_Am2) return SCFFT_ERR_ARG;
+  if (!ctx->ws) return fail(ctx, SCFFT_ERR_WORKSPACE, "no workspace attached");
+  if (!ctx->obs_state || ctx->mom_state != ctx->obs_state)
+    return fail(ctx, SCFFT_ERR_STATE, "scfft_step_moment is valid inside an integrator observer only");
+  const int xb = ctx->prec == SCFFT_F64 ? xpass_blocks<double>(make_plan<double>(ctx))
+                                        : xpass_blocks<float>(make_plan<float>(ctx));
+  const double* part = wsp<double>(ctx, ctx->off_mom);
+  double* out = wsp<double>(ctx, ctx->off_mom) + 6 * ((size_t)ctx->n[1] * ctx->n[2]);
+  const int first = omega_only ? 3 : 0;
+  HIPCHK(ctx, launch_sum_partials(part + first, xb, 6, 3, out, ctx->stream));
+  double r[3];
+  HIPCHK(ctx, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const double dv = ctx->h[0] * ctx->h[1] * ctx->h[2];
+  const double scale = ctx->u.jc * std::pow(ctx->u.l, 4.0);  // m' -> A m^2
+  for (int d = 0; d < 3; ++d) m_Am2[d] = 0.5 * r[d] * dv * scale;
+  return SCFFT_OK;
 }
 
 scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const uint8_t* dev_region,

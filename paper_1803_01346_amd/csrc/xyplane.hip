@@ -184,6 +184,9 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
         if constexpr (OP == XY_HIN) need = need && !in;     // warm start on Omega_out
         if constexpr (OP == XY_UPDATE) need = need && in;   // hdot_in on Omega
         aux[r][e] = need ? auxp[idx] : T(0);
+        if constexpr (OP == XY_FWD) {
+          if (need && A.in2) aux[r][e] += A.in2_coef * A.in2[idx];  // stage argument y + c k
+        }
       }
     }
   }

@@ -109,6 +109,7 @@ _SIGS = {
     "scfft_phi": (C.c_int, [_P, _P, _P]),
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
+    "scfft_step_moment": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double)]),
     "scfft_region_mean_abs_b": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
     "scfft_probe_b": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]),
     "scfft_get_state": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
@@ -343,6 +344,12 @@ def scfft_current(ctx, h, j):
 def scfft_moment(ctx, h, omega_only=0):
     m = (C.c_double * 3)()
     _check(load().scfft_moment(ctx, _ptr(h), int(omega_only), m), ctx)
+    return np.array(m[:])
+
+
+def scfft_step_moment(ctx, omega_only=0):
+    m = (C.c_double * 3)()
+    _check(load().scfft_step_moment(ctx, int(omega_only), m), ctx)
     return np.array(m[:])
 
 

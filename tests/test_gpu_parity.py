@@ -153,9 +153,12 @@ def test_init_state_and_virgin_rhs():
     assert rel_max(_np(out), want) < 1e-10
 
 
-def test_integrate_fixed_steps_fp64():
+@pytest.mark.parametrize("fuse", [2, 0])
+def test_integrate_fixed_steps_fp64(fuse):
+    """Stage arguments y + c k formed inside the first pass (plane pass or
+    row pass) and the state kept in the workspace give the oracle's BS23."""
     cfg = dict(CUBE32, n_power=20.0)
-    s = sim(cfg, fixed_iter=2)
+    s = sim(cfg, fixed_iter=2, fuse_xy=fuse)
     prob, u = oracle_problem(cfg, fixed_iter=2)
     h = s.empty_field()
     scfft.scfft_init_state(s.ctx, 0.0, h)
@@ -169,6 +172,45 @@ def test_integrate_fixed_steps_fp64():
     y, so = ode.integrate(f, 0.0, 0.02 / u.t0, np.zeros((3,) + prob.grid.shape), fixed_steps=6)
     assert st.accepted == 6 and st.rhs_calls == so.rhs_calls and len(ms) == 6
     assert rel_max(_np(h), y) < 1e-10
+
+
+@pytest.mark.parametrize("prec,fuse", [(scfft.F64, 0), (scfft.F64, 2), (scfft.F32, 1)])
+def test_step_moment_in_observer(prec, fuse):
+    """The moment the power-law pass records for each accepted state equals the
+    stand-alone readout of the state the observer sees, and the oracle's
+    moment of the final state (Sec. 2 readout)."""
+    cfg = dict(CUBE32, n_power=20.0)
+    s = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=fuse)
+    prob, u = oracle_problem(cfg, fixed_iter=2)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    # a localized field (Gaussian window) so the moment is far above round-off
+    x, y, z = prob.grid.mesh_nodes()
+    h = to_dev(torch, state(cfg, seed=5) * np.exp(-(x * x + y * y + z * z) / 0.8), dt)
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_step_moment(s.ctx)
+    got = []
+
+    def obs(_u, t, p):
+        got.append((scfft.scfft_step_moment(s.ctx, 0), scfft.scfft_step_moment(s.ctx, 1),
+                    scfft.scfft_moment(s.ctx, p, 0), scfft.scfft_moment(s.ctx, p, 1)))
+        return 0
+
+    o = scfft.default_ode_opts(fixed_steps=3)
+    scfft.scfft_integrate(s.ctx, 0.0, 0.01, h, o, observer=obs)
+    assert len(got) == 3
+    tol = 1e-12 if prec == scfft.F64 else 1e-5
+    for m_all, m_in, r_all, r_in in got:
+        assert np.max(np.abs(m_all - r_all)) <= tol * np.max(np.abs(r_all))
+        assert np.max(np.abs(m_in - r_in)) <= tol * np.max(np.abs(r_in))
+    # the last accepted state is h after the call: the oracle's moment of it
+    hn = _np(h).astype(np.float64)
+    want_all = u.moment_dimless_to_Am2(readouts.moment(prob.grid, prob.chi, hn))
+    want_in = u.moment_dimless_to_Am2(readouts.moment(prob.grid, prob.chi, hn, omega_only=True))
+    otol = 1e-10 if prec == scfft.F64 else 1e-4
+    assert np.max(np.abs(got[-1][0] - want_all)) <= otol * np.max(np.abs(want_all))
+    assert np.max(np.abs(got[-1][1] - want_in)) <= otol * np.max(np.abs(want_in))
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_step_moment(s.ctx)
 
 
 def test_integrate_adaptive_fp64_agrees_with_oracle():
