@@ -9,6 +9,10 @@ magnetic-moment readout of the accepted state; value = RHS evaluations per
 second over the timed steps.  Inputs are seeded synthetic fields resident in
 HBM before timing starts.
 
+Beside the headline line: the right-hand side alone (FP64 and FP32), the
+paper's stopping rule (delta_it = 2e-5) with its mean iteration count, and
+the 256^3 lens box in FP32, whose working set exceeds the last-level cache.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
 import argparse
@@ -91,6 +95,75 @@ def time_rhs_only(sim, h, calls, warm=5):
     return calls / (time.perf_counter() - t), hd
 
 
+def kernel_profile(sim, fn):
+    """Per-kernel-kind launches, average duration and achieved GB/s of the
+    algorithmic bytes, from HIP events the library attaches to each
+    dispatch on its stream while fn() runs."""
+    from paper_1803_01346_amd import scfft
+    scfft.scfft_profile(sim.ctx, 1)
+    fn()
+    prof = scfft.scfft_profile_read(sim.ctx)
+    scfft.scfft_profile(sim.ctx, 0)
+    per_kind = {}
+    for kind, (la, ms, by) in prof.items():
+        if la:
+            per_kind[kind] = dict(launches=la, avg_us=round(ms / la * 1e3, 2),
+                                  bytes_per_launch=int(by / la),
+                                  GBs=round(by / (ms * 1e-3) / 1e9, 1), total_ms=round(ms, 3))
+    return per_kind
+
+
+def roofline_of(per_kind, traffic=None):
+    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
+    d = per_kind[dom]
+    return {"bound": "hbm", "kernel": dom, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic(dom) if traffic else None,
+            "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+            "launches": d["launches"]}
+
+
+def converged_leg(cfg, h, calls=20):
+    """rhs_eval with the paper's stopping rule (delta_it = 2e-5) instead of a
+    fixed count, on consecutive stage times so each call starts from the
+    previous call's exterior rate: calls per second and mean iterations."""
+    import torch
+    from paper_1803_01346_amd import scfft
+    sim = scfft.Simulation(cfg, precision=scfft.F64)
+    hd = sim.empty_field()
+    st = scfft.RhsStats()
+    for i in range(3):
+        sim.rhs_eval(T_STAR - (3 - i) * DT_STEP, h, hd)
+    torch.cuda.synchronize()
+    iters = 0
+    t = time.perf_counter()
+    for i in range(calls):
+        sim.rhs_eval(T_STAR + i * DT_STEP, h, hd, st)
+        iters += st.iters
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    return dict(value=round(calls / el, 2), unit="RHS evals/s", mean_iters=round(iters / calls, 2),
+                delta_it=2e-5, calls=calls)
+
+
+def lens256_leg(calls=10):
+    """The 256^3 lens box in FP32 (working set beyond the 256 MB last-level
+    cache: the HBM regime): RHS/s with 3 exterior iterations and the
+    dominant kernel against the HBM peak."""
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    cfg = workloads.config("lens256")
+    sim = make_sim(cfg, scfft.F32, FIXED_ITER)
+    h = torch.from_numpy(workloads.synthetic_state(cfg, seed=0, background=(0.0, 0.0, 0.1))).to(
+        device="cuda", dtype=torch.float32).contiguous()
+    rate, _ = time_rhs_only(sim, h, calls, warm=3)
+    hd = sim.empty_field()
+    per_kind = kernel_profile(sim, lambda: [sim.rhs_eval(10.0, h, hd) for _ in range(3)])
+    out = dict(value=round(rate, 2), unit="RHS evals/s", dtype="f32", grid=[256, 256, 256],
+               exterior_iters=FIXED_ITER, roofline=roofline_of(per_kind), kernels=per_kind)
+    sim.close()
+    return out
+
+
 def cpu_baseline(cfg, h_np):
     """The oracle's rhs_eval on the same 128^3 state with one exterior
     iteration (4 of the 8 spectral operator applications of a k = 3 call),
@@ -133,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="skip the per-kernel event timing run")
+    ap.add_argument("--no-converged", action="store_true", help="skip the delta_it stopping-rule leg")
+    ap.add_argument("--no-lens", action="store_true", help="skip the 256^3 FP32 lens leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -169,22 +244,10 @@ def main():
     n = tuple(cfg["n"])
 
     # per-kernel durations with HIP events on the library's stream, same steps
-    per_kind, dom, dom_bytes, achieved = {}, None, None, None
+    per_kind, roof = {}, None
     if not args.no_events:
-        scfft.scfft_profile(sim.ctx, 1)
-        run_steps(sim, h, T_STAR, args.steps)
-        prof = scfft.scfft_profile_read(sim.ctx)
-        scfft.scfft_profile(sim.ctx, 0)
-        for kind, (la, ms, by) in prof.items():
-            if la:
-                avg_s = ms / la * 1e-3
-                per_kind[kind] = dict(launches=la, avg_us=round(avg_s * 1e6, 2),
-                                      bytes_per_launch=int(by / la),
-                                      GBs=round(by / (ms * 1e-3) / 1e9, 1), total_ms=round(ms, 3))
-        dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
-        dom_avg = per_kind[dom]["avg_us"] * 1e-6
-        dom_bytes = per_kind[dom]["bytes_per_launch"]
-        achieved = per_kind[dom]["GBs"]
+        per_kind = kernel_profile(sim, lambda: run_steps(sim, h, T_STAR, args.steps))
+        roof = roofline_of(per_kind, measured_traffic)
 
     # right-hand side alone (no integrator work)
     rhs_ps, hd64 = time_rhs_only(sim, h, 50)
@@ -210,6 +273,9 @@ def main():
         fp32 = dict(value=round(st32.rhs_calls / el32, 2), rhs_only=round(rhs32, 2),
                     rel_l2_vs_fp64=rel, ms_per_step=round(1e3 * el32 / args.steps, 3))
 
+    converged = None if args.no_converged else converged_leg(cfg, h)
+    lens = None if args.no_lens else lens256_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (about 30 s)", file=sys.stderr, flush=True)
@@ -234,12 +300,9 @@ def main():
                    "grid": list(n), "exterior_iters": FIXED_ITER, "rhs_per_step": 3},
         "rhs_only": round(rhs_ps, 2),
         "fp32": fp32,
-        "roofline": None if dom is None else {
-            "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom),
-            "bytes_per_launch": dom_bytes, "avg_launch_us": per_kind[dom]["avg_us"],
-            "launches": per_kind[dom]["launches"]},
+        "converged": converged,
+        "lens256_f32": lens,
+        "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,
     }

@@ -1,0 +1,123 @@
+"""Full-size checks on the 256^3 box (the lens workload), where the oracle's 3D
+transforms take minutes: properties that hold at any size.
+
+* C_s of a separable field v_c = f_c(x) g_c(y) q_c(z) with random, not
+  band-limited, profiles: the symbol S(k) i k_odd factorises over the axes
+  (S = S_x S_y S_z, each odd factor depends on one axis), so every term of
+  the cross product is a product of three 1D operators, applied here with the
+  oracle's direct 1D DFT.  Exact at every node, Nyquist planes included.
+* Phi of a band-limited current sum_q a_q cos(k_q.r + p_q): per mode
+  Phi = -sin(k_q.r + p_q) (k_q x a_q) / |k_q|^2 (Eq. 7, k != 0).
+* rhs_eval: on Omega the rate is -C_s e(C_s h) (Eqs. 1, 3, 4; the exterior
+  iteration leaves it unchanged); FP32 against FP64 within 1e-4 relative L2.
+"""
+import numpy as np
+import pytest
+
+from gpu_case import rel_l2, rel_max, sim, state, to_dev
+from oracle import fft as offt, grid as ogrid, geometry, law
+from paper_1803_01346_amd import scfft, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LENS = workloads.config("lens256")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    scfft.load()
+
+
+def _op1(u, g, a, deriv):
+    """1D factor along axis a: Re IDFT(S_a(k) [i k_odd] DFT u)."""
+    k = g.axis_k(a)
+    m = np.exp(-0.5 * g.sigma ** 2 * k * k)
+    if deriv:
+        m = m * 1j * g.axis_k_odd(a)
+    return np.real(offt.dft_direct(m * offt.dft_direct(u), inverse=True))
+
+
+def _separable_curl(prof, g):
+    """C_s v for v_c = f_c(x) g_c(y) q_c(z); prof[c] = (f, g, q)."""
+    def d(a, c):  # S i k_odd_a applied to component c
+        f, gg, q = (_op1(prof[c][ax], g, ax, ax == a) for ax in range(3))
+        return q[:, None, None] * gg[None, :, None] * f[None, None, :]
+    return np.stack([d(1, 2) - d(2, 1), d(2, 0) - d(0, 2), d(0, 1) - d(1, 0)])
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+def test_curl_separable_256(prec):
+    g = ogrid.Grid(LENS["n"], LENS["half_width"])
+    rng = np.random.default_rng(31)
+    prof = [[rng.normal(size=n) for n in g.n] for _ in range(3)]
+    v = np.stack([p[2][:, None, None] * p[1][None, :, None] * p[0][None, None, :] for p in prof])
+    want = _separable_curl(prof, g)
+    s = sim(LENS, precision=prec)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    out = s.empty_field()
+    scfft.scfft_curl(s.ctx, to_dev(torch, v, dt), out)
+    torch.cuda.synchronize()
+    err = rel_max(_np(out), want)
+    assert err < (1e-12 if prec == scfft.F64 else 2e-5), err
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+def test_phi_modes_256(prec):
+    g = ogrid.Grid(LENS["n"], LENS["half_width"])
+    x, y, z = g.mesh_nodes()
+    rng = np.random.default_rng(32)
+    j = np.zeros((3,) + g.shape)
+    want = np.zeros((3,) + g.shape)
+    for _ in range(6):
+        m = rng.integers(-g.n[0] // 8, g.n[0] // 8 + 1, size=3)
+        if not m.any():
+            m[2] = 1
+        k = np.pi * m / np.asarray(g.L)
+        a = rng.normal(size=3)
+        th = k[0] * x + k[1] * y + k[2] * z + rng.uniform(0.0, 2.0 * np.pi)
+        c, sn = np.cos(th), np.sin(th)
+        kxa = np.cross(k, a) / float(k @ k)
+        for comp in range(3):
+            j[comp] += a[comp] * c
+            want[comp] -= kxa[comp] * sn
+    s = sim(LENS, precision=prec)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    out = s.empty_field()
+    scfft.scfft_phi(s.ctx, to_dev(torch, j, dt), out)
+    torch.cuda.synchronize()
+    err = rel_max(_np(out), want)
+    assert err < (1e-12 if prec == scfft.F64 else 2e-5), err
+
+
+def test_rhs_lens_256():
+    """FP64 and FP32 right-hand sides at 256^3 (fixed 3 iterations)."""
+    cfg = LENS
+    h = state(cfg, seed=3, bg=(0.0, 0.0, 0.1))
+    s64 = sim(cfg, fixed_iter=3)
+    dh = to_dev(torch, h, torch.float64)
+    a, _ = s64.rhs_eval(10.0, dh)
+    jd = s64.empty_field()
+    scfft.scfft_current(s64.ctx, dh, jd)
+    torch.cuda.synchronize()
+    g = ogrid.Grid(cfg["n"], cfg["half_width"])
+    chi = geometry.voxelize(g, cfg["shapes"])
+    e = law.constitutive(_np(jd), chi, cfg["n_power"], cfg["rho_out"])
+    ce = s64.empty_field()
+    scfft.scfft_curl(s64.ctx, to_dev(torch, e, torch.float64), ce)
+    torch.cuda.synchronize()
+    A = _np(a)
+    want = -_np(ce)
+    m = chi == 1
+    assert np.max(np.abs(A[:, m] - want[:, m])) <= 1e-10 * np.max(np.abs(want[:, m]))
+    del jd, ce
+    s32 = sim(cfg, precision=scfft.F32, fixed_iter=3)
+    b, _ = s32.rhs_eval(10.0, dh.float())
+    torch.cuda.synchronize()
+    assert rel_l2(_np(b), A) < 1e-4
