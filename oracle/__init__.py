@@ -23,6 +23,8 @@ Modules
   ode        Bogacki-Shampine 3(2) method of lines integrator
   readouts   magnetic moment, region means, probe fields
   brute      brute-force sums: direct convolution kernels, free-space fields
+  adjoint    reverse-mode derivatives of the right-hand side (fixed iteration
+             count, explicit warm start) and of fixed-step BS23
 
 Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py)
 except where its docstring says "parity unpinned".
