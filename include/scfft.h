@@ -264,6 +264,52 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
                              const scfft_ode_opts* o, scfft_observer obs, void* user,
                              scfft_ode_stats* stats);
 
+/* ---- reverse mode (gradients) ----
+ *
+ * Differentiating the discrete map is an extension of the paper (Sec. 2
+ * gives the forward method only).  The map is made smooth by a fixed number
+ * K = fixed_iter > 0 of exterior iterations (Eq. 5) and by carrying the warm
+ * start as an explicit state: one right-hand-side call is
+ *   (h, w) -> (hdot, w' = (1 - chi) hdot),   hdot^0 = chi g + (1 - chi) w,
+ * g = -C_s e(C_s h) (Eqs. 1, 3, 4), a first call (no warm start) using
+ * hdot^0 = g.  C_s and Phi have Hermitian symbols and the Jacobian of Eq. 1
+ * is symmetric, so the reverse pass runs the forward passes in reverse order
+ * at about the cost of one call.  All fields are dimensionless (Eq. 8),
+ * layout [3][Nz][Ny][Nx], precision of the context; calls are synchronous.
+ * SCFFT_ERR_ARG when fixed_iter is 0 or outputs alias inputs. */
+
+/* Vector-Jacobian product of one call at state h: given lam = dL/dhdot and
+ * mu = dL/dw' (may be NULL: zero), writes hbar = dL/dh (all nodes) and, if
+ * wbar is non-NULL, wbar = dL/dw (zero in Omega); warm_used says whether the
+ * forward call had a warm start.  kappa_bar (scalar field [Nz][Ny][Nx], may
+ * be NULL) is ACCUMULATED with dL/dkappa, kappa = jc(x)/jc (1 where no map
+ * is set).  n_bar = dL/dn and hedot_bar = dL/d(dh_e'/dt') (may be NULL). */
+scfft_status scfft_rhs_vjp(scfft_ctx* ctx, const void* h_dev, int32_t warm_used,
+                           const void* lam_dev, const void* mu_dev, void* hbar_dev, void* wbar_dev,
+                           void* kappa_bar_dev, double* n_bar, double hedot_bar[3]);
+
+/* Device workspace (bytes, 256-byte aligned start) for scfft_integrate_adjoint:
+ * ceil(steps / checkpoint_every) checkpoints of 3 fields, a tape of
+ * 3 * checkpoint_every + 1 fields and 10 work fields. */
+scfft_status scfft_adjoint_workspace_size(const scfft_ctx* ctx, int32_t steps,
+                                          int32_t checkpoint_every, size_t* bytes);
+
+/* Gradient of a loss L(h(t1)) through `steps` equal Bogacki-Shampine steps
+ * (the fixed-step mode of scfft_integrate) from h0 at t0_s, started with no
+ * warm start (as after scfft_reset_warm).  The forward pass keeps
+ * checkpoints every checkpoint_every steps; the reverse pass recomputes one
+ * segment at a time and runs the adjoint steps backwards.  Given hT_bar =
+ * dL/dh(t1) it writes hT (the forward result, may be NULL), h0_bar =
+ * dL/dh0, n_bar (may be NULL) and p_bar = dL/dp (may be NULL) for the drive
+ * vector p = amplitude x direction (dimensionless) of a drive h_e = p f(t)
+ * (ramp-hold or sine; SCFFT_ERR_ARG for a PWL drive); kappa_bar (may be
+ * NULL) is accumulated.  The context's warm start is cleared on return. */
+scfft_status scfft_integrate_adjoint(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
+                                     int32_t checkpoint_every, void* adj_ws, size_t adj_bytes,
+                                     const void* h0_dev, const void* hT_bar_dev, void* hT_dev,
+                                     void* h0_bar_dev, void* kappa_bar_dev, double* n_bar,
+                                     double p_bar[3]);
+
 /* ---- operators and readouts ---- */
 
 /* out = C_s v, the smoothed spectral curl (derivatives of Eqs. 3, 4). */
@@ -312,6 +358,10 @@ enum {
   SCFFT_KERNEL_XY_UPDATE,
   SCFFT_KERNEL_XY_UPDATE_LAST,
   SCFFT_KERNEL_XY_STORE,
+  SCFFT_KERNEL_X_ADJ_START,  /* reverse mode: cotangent in, masked -> spectrum */
+  SCFFT_KERNEL_X_ADJ_ACC,    /* -> adjoint iterate, running sum -> spectrum  */
+  SCFFT_KERNEL_X_ADJ_LAST,   /* -> last adjoint iterate, gbar -> spectrum    */
+  SCFFT_KERNEL_X_ADJ_LAW,    /* -> ebar -> jbar (Eq. 1 transposed) -> spectrum */
   SCFFT_KERNEL_KINDS
 };
 

@@ -59,6 +59,13 @@ enum XOp : int {
   X_UPDATE_LAST,  // X_UPDATE without the forward transform
   X_STORE,        // spectrum -> real output
   X_MOMENT,       // spectrum -> j; sums of r x j over all nodes (or chi nodes)
+  // reverse mode of the right-hand side (fixed iteration count)
+  X_ADJ_START,    // l = in + (1-chi) in2 -> out (running sum); (1-chi) l -> spectrum
+  X_ADJ_ACC,      // spectrum -> l; out += l; (1-chi) l -> spectrum
+  X_ADJ_LAST,     // spectrum -> l0; c = out; wbar = (1-chi) l0 -> warm_out;
+                  // sums of (1-chi) c; gbar = chi c + (chi or 1) l0 -> spectrum
+  X_ADJ_LAW,      // spectrum -> ebar; jbar = (de/dj)^T ebar at j = in -> spectrum;
+                  // sums of ebar . e ln(|j|/kappa); kappa_bar += -n ebar . e / kappa
   X_NUM_OPS
 };
 
@@ -97,6 +104,8 @@ struct XArgs {
   T* warm_out;           // X_UPDATE_LAST with track = 0: also store hdot on Omega_out here
   double* mom_partials;  // X_LAW: if set, 6 doubles per block: sums of r x j over all
                          // nodes (3) and over Omega nodes (3), for the moment readout
+  T* kappa_bar;          // X_ADJ_LAW: accumulated d/dkappa (scalar field) or nullptr
+  int warm_used;         // X_ADJ_LAST: the forward call started from a warm start
   double pos0[3];        // coordinate of node 0 along each axis (moment)
   double step[3];        // node spacing (moment)
 };
@@ -124,6 +133,9 @@ hipError_t launch_xypass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_
 // ---- pointwise / reduction kernels (pointwise.hip) ----
 hipError_t launch_sum_partials(const double* partials, int n, int stride, int ncomp, double* out,
                                hipStream_t s);
+hipError_t launch_accum_partials(const double* partials, int n, int stride, int ncomp, double scale,
+                                 double* out, hipStream_t s);
+hipError_t launch_zero_doubles(double* p, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream_t s);
 // out = y + c1 k1 + c2 k2 + c3 k3 (terms with null k skipped)

@@ -272,15 +272,18 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
 template <typename T, int NX, int OP, int NC>
 __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   static_assert(NC == 3 || NC == 1, "components per block");
-  static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT), "needs all components");
+  static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT && OP != X_ADJ_LAST && OP != X_ADJ_LAW),
+                "needs all components");
   constexpr int M = NX / 2;
   constexpr int E = elems_per_thread(M, ex_max<T, NC>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
-  constexpr bool HAS_INV = OP != X_FWD;
+  constexpr bool HAS_INV = OP != X_FWD && OP != X_ADJ_START;
   constexpr bool HAS_FWD = OP == X_FWD || OP == X_LAW || OP == X_HIN || OP == X_MASK ||
-                           OP == X_UPDATE;
-  constexpr bool REDUCE = OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MOMENT;
+                           OP == X_UPDATE || OP >= X_ADJ_START;
+  constexpr bool REDUCE = OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MOMENT ||
+                          OP == X_ADJ_LAST || OP == X_ADJ_LAW;
+  constexpr bool REDUCE3 = OP == X_MOMENT || OP == X_ADJ_LAST;  // 3 sums per block
   using L = LdsRows<T, M, E>;
   __shared__ C2<T> smem[ROWS * L::STRIDE];
   __shared__ double red[REDUCE ? 3 * kBlock : 1];
@@ -312,9 +315,8 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   const size_t rowbase = (size_t)rr * NX;
 
   // ---- all global loads first, so their latencies overlap ----
-  constexpr bool NEED_CHI = OP == X_LAW || OP == X_HIN || OP == X_MASK || OP == X_UPDATE ||
-                            OP == X_UPDATE_LAST || OP == X_MOMENT;
-  constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST;
+  constexpr bool NEED_CHI = OP != X_FWD && OP != X_STORE;
+  constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST || OP >= X_ADJ_START;
   C2<T> Xs[HAS_INV ? NC : 1][E];
   C2<T> Xn[NC];
   if constexpr (HAS_INV) {
@@ -334,8 +336,11 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   }
   // X_FWD: the real input (all nodes); X_HIN: the warm start (Omega_out);
   // X_UPDATE*: hdot^i (all nodes when tracking iterates, else Omega only:
-  // with a fixed iteration count only hdot_in is read back)
-  const T* auxp = OP == X_FWD ? A.in : (OP == X_HIN ? A.warm : A.out);
+  // with a fixed iteration count only hdot_in is read back); X_ADJ_START:
+  // the cotangent of hdot; X_ADJ_ACC / LAST: the running sum; X_ADJ_LAW: j
+  const T* auxp = (OP == X_FWD || OP == X_ADJ_START || OP == X_ADJ_LAW)
+                      ? A.in
+                      : (OP == X_HIN ? A.warm : A.out);
   T aux[(NEED_AUX || OP == X_FWD) ? NC : 1][2 * E];
   if constexpr (NEED_AUX || OP == X_FWD) {
 #pragma unroll
@@ -344,12 +349,16 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       if constexpr (OP == X_HIN) need = need && ch[e] == 0;
       if constexpr (OP == X_UPDATE) need = need && (A.track || ch[e] != 0);
       if constexpr (OP == X_UPDATE_LAST) need = need && A.track;
+      if constexpr (OP == X_ADJ_LAW) need = need && ch[e] != 0;     // j is read in Omega only
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1);
         aux[cc][e] = need ? auxp[ai] : T(0);
         if constexpr (OP == X_FWD) {
           if (need && A.in2) aux[cc][e] += A.in2_coef * A.in2[ai];  // stage argument y + c k
+        }
+        if constexpr (OP == X_ADJ_START) {  // cotangent of hdot^K: lam + (1-chi) mu
+          if (need && A.in2 && ch[e] == 0) aux[cc][e] += A.in2[ai];
         }
       }
     }
@@ -455,6 +464,57 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
             }
           }
         }
+      } else if constexpr (OP == X_ADJ_START || OP == X_ADJ_ACC) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const T l = OP == X_ADJ_START ? aux[cc][e] : a[cc][e];
+          if (valid) A.out[(c0 + cc) * csr + idx] = OP == X_ADJ_START ? l : aux[cc][e] + l;
+          a[cc][e] = in ? T(0) : l;
+        }
+      } else if constexpr (OP == X_ADJ_LAST) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const T l0 = a[cc][e], cs = aux[cc][e];
+          if (valid && A.warm_out) A.warm_out[(c0 + cc) * csr + idx] = in ? T(0) : l0;
+          a[cc][e] = in ? cs + l0 : (A.warm_used ? T(0) : l0);
+        }
+        if (valid && !in) {
+          acc0 += (double)aux[0][e];
+          acc1 += (double)aux[1][e];
+          acc2 += (double)aux[2][e];
+        }
+      } else if constexpr (OP == X_ADJ_LAW) {
+        if (in) {
+          const T jx = aux[0][e], jy = aux[1][e], jz = aux[2][e];
+          const T ex = a[0][e], ey = a[1][e], ez = a[2][e];
+          const T s = jx * jx + jy * jy + jz * jz;
+          if (s > T(0)) {
+            const T kap = A.kappa ? A.kappa[idx] : T(1);
+            const T lnk = A.kappa ? dev_log<T>(kap) : T(0);
+            const T lna = T(0.5) * dev_log<T>(s);
+            T xp = (A.npow - T(1)) * (lna - lnk) - lnk;
+            const bool clamped = xp > A.expmax;
+            if (clamped) xp = A.expmax;
+            const T rho = dev_exp<T>(xp);
+            const T je = jx * ex + jy * ey + jz * ez;        // j . ebar
+            // (de/dj)^T ebar = rho (ebar + (n-1) j (j . ebar) / |j|^2)
+            const T q = clamped ? T(0) : (A.npow - T(1)) * je / s;
+            a[0][e] = rho * (ex + q * jx);
+            a[1][e] = rho * (ey + q * jy);
+            a[2][e] = rho * (ez + q * jz);
+            if (!clamped) {
+              const double ee = (double)rho * (double)je;    // ebar . e
+              acc0 += ee * (double)(lna - lnk);
+              if (A.kappa_bar && valid) A.kappa_bar[idx] += -A.npow * (T)ee / kap;
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[c][e] = T(0);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c][e] *= A.rho_out;
+        }
       } else if constexpr (OP == X_STORE) {
         if (valid) {
 #pragma unroll
@@ -499,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       }
     }
   }
-  if (REDUCE && (OP == X_MOMENT || A.track)) {  // uniform across the block
+  if (REDUCE && (OP == X_MOMENT || OP == X_ADJ_LAST || OP == X_ADJ_LAW || A.track)) {  // uniform
     red[tid] = acc0;
     red[kBlock + tid] = acc1;
     red[2 * kBlock + tid] = acc2;
@@ -513,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       __syncthreads();
     }
     if (tid == 0) {
-      if constexpr (OP == X_MOMENT) {
+      if constexpr (REDUCE3) {
         A.partials[3 * blockIdx.x + 0] = red[0];
         A.partials[3 * blockIdx.x + 1] = red[kBlock];
         A.partials[3 * blockIdx.x + 2] = red[2 * kBlock];
@@ -596,8 +656,18 @@ static hipError_t xlaunch_nc(const Plan<T>& p, int op, const XArgs<T>& a, hipStr
       launch(xpass_kernel<T, NX, X_UPDATE_LAST, NC>, grid, block, s, t, p, a);
       break;
     case X_STORE: launch(xpass_kernel<T, NX, X_STORE, NC>, grid, block, s, t, p, a); break;
+    case X_ADJ_START: launch(xpass_kernel<T, NX, X_ADJ_START, NC>, grid, block, s, t, p, a); break;
+    case X_ADJ_ACC: launch(xpass_kernel<T, NX, X_ADJ_ACC, NC>, grid, block, s, t, p, a); break;
     default:
       if constexpr (NC == 3) {
+        if (op == X_ADJ_LAST) {
+          launch(xpass_kernel<T, NX, X_ADJ_LAST, 3>, grid, block, s, t, p, a);
+          break;
+        }
+        if (op == X_ADJ_LAW) {
+          launch(xpass_kernel<T, NX, X_ADJ_LAW, 3>, grid, block, s, t, p, a);
+          break;
+        }
         if (op == X_LAW) {
           launch(xpass_kernel<T, NX, X_LAW, 3>, grid, block, s, t, p, a);
           break;
@@ -617,6 +687,7 @@ static hipError_t xlaunch_nc(const Plan<T>& p, int op, const XArgs<T>& a, hipStr
 template <typename T, int NX>
 static hipError_t xlaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
   const bool per_component = op == X_FWD || op == X_HIN || op == X_MASK || op == X_STORE ||
+                             op == X_ADJ_START || op == X_ADJ_ACC ||
                              ((op == X_UPDATE || op == X_UPDATE_LAST) && !a.track);
   return per_component ? xlaunch_nc<T, NX, 1>(p, op, a, s, t) : xlaunch_nc<T, NX, 3>(p, op, a, s, t);
 }

@@ -60,6 +60,35 @@ hipError_t launch_sum_partials(const double* partials, int n, int stride, int nc
   return hipGetLastError();
 }
 
+// out[c] += scale * sum_b partials[b * stride + c], one block.
+__global__ __launch_bounds__(kRB) void accum_partials_kernel(const double* __restrict__ p, int n,
+                                                             int stride, int ncomp, double scale,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[kRB];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRB) acc += p[(size_t)i * stride + c];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[c] += scale * r;
+  }
+}
+
+hipError_t launch_accum_partials(const double* partials, int n, int stride, int ncomp, double scale,
+                                 double* out, hipStream_t s) {
+  hipLaunchKernelGGL(accum_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, stride, ncomp,
+                     scale, out);
+  return hipGetLastError();
+}
+
+__global__ void zero_doubles_kernel(double* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+hipError_t launch_zero_doubles(double* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_doubles_kernel, dim3(1), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restrict__ p, int n,
                                                            double* __restrict__ out) {
   __shared__ double sh[kRB];
@@ -100,7 +129,7 @@ __global__ __launch_bounds__(kRB) void combo_kernel(T* __restrict__ out, const T
                                                     const T* __restrict__ k2, T c2,
                                                     const T* __restrict__ k3, T c3, size_t n) {
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
-    T v = y[i];
+    T v = y ? y[i] : T(0);
     if (k1) v += c1 * k1[i];
     if (k2) v += c2 * k2[i];
     if (k3) v += c3 * k3[i];

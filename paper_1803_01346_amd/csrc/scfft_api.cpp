@@ -49,7 +49,7 @@ struct scfft_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_main, off_nyq, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
-      off_clamp, off_mom, off_ode, off_probe, total;
+      off_clamp, off_mom, off_adj, off_adjs, off_ode, off_probe, total;
   size_t wsize;  // element size
   bool has_mask = false, has_kappa = false, has_warm = false;
   int64_t n_in = 0, n_out = 0;
@@ -112,6 +112,10 @@ void layout(scfft_ctx* c) {
   c->off_clamp = o; o = align_up(o + sizeof(unsigned long long));
   // moment partials of the power-law pass (6 per block) and their sums
   c->off_mom = o;   o = align_up(o + (6 * xb + 8) * sizeof(double));
+  // reverse mode: j of the forward call and the running sum of adjoint
+  // iterates (one field each), and device accumulators of scalar gradients
+  c->off_adj = o;   o = align_up(o + 2 * 3 * nodes * w);
+  c->off_adjs = o;  o = align_up(o + 16 * sizeof(double));
   c->off_ode = o;   o = align_up(o + 6 * 3 * nodes * w);
   c->off_probe = o; o = align_up(o + (size_t)kProbeChunk * 6 * sizeof(double));
   c->total = o;
@@ -324,6 +328,13 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
                                (a.track ? all + nout : (a.warm_out ? 2.0 : 1.0) * nout) * frac * node;
     case X_STORE: return inv_rows * spec + rows * p.nx * node;
     case X_MOMENT: return inv_rows * spec + (a.omega_only ? rows * mask : 0.0);
+    case X_ADJ_START: return rows * mask + rows * p.nx * node + (a.in2 ? nout * frac * node : 0.0) +
+                             rows * p.nx * node + rows * spec;
+    case X_ADJ_ACC: return inv_rows * spec + rows * mask + 2.0 * rows * p.nx * node + rows * spec;
+    case X_ADJ_LAST: return inv_rows * spec + rows * mask + (a.warm_out ? 2.0 : 1.0) * rows * p.nx * node +
+                            rows * spec;
+    case X_ADJ_LAW: return inv_rows * spec + rows * mask + nin * frac * node +
+                           (a.kappa ? (a.kappa_bar ? 3.0 : 1.0) * nin * frac * w : 0.0) + rows * spec;
   }
   return 0.0;
 }
@@ -352,7 +363,8 @@ double bytes_xy(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a)
 template <typename T>
 hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   KTime t;
-  hipError_t e = prof_slot(c, SCFFT_KERNEL_X_FWD + op, &t, c->prof ? bytes_x<T>(c, p, op, a) : 0.0);
+  const int kind = op < X_ADJ_START ? SCFFT_KERNEL_X_FWD + op : SCFFT_KERNEL_X_ADJ_START + (op - X_ADJ_START);
+  hipError_t e = prof_slot(c, kind, &t, c->prof ? bytes_x<T>(c, p, op, a) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_xpass<T>(p, op, a, c->stream, t), t);
 }
@@ -561,6 +573,72 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
     if (st == SCFFT_OK && new_clamps > 0) st = SCFFT_WARN_CLAMPED;
   }
   return st;
+}
+
+// Reverse mode of one right-hand-side call with a fixed iteration count K,
+// the transpose of (h, w) -> (hdot, w' = (1-chi) hdot), w the warm start.
+// The curl and Phi have Hermitian symbols (symmetric operators), the masks
+// are diagonal and the Jacobian of Eq. 1 is symmetric, so the passes of the
+// forward schedule run in reverse order:
+//   l^K = lam + (1-chi) mu;  l^i = C chi Phi (1-chi) l^{i+1};  c = sum_{i>=1} l^i
+//   gbar = chi c + (chi or 1) l^0;  wbar = (1-chi) l^0;  hedot_bar = sum (1-chi) c
+//   ebar = -C gbar;  jbar = (de/dj)^T ebar;  hbar = C jbar
+// The state is h + in2_coef in2 (a stage argument).  Scalars go to device
+// accumulators: sc[0] += nbar, sc[1..3] += rate_scale * hedot_bar;
+// kappa_bar (scalar field) is accumulated when non-null.
+template <typename T>
+scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coef, bool warm_used,
+                          const T* lam, const T* mu, T* hbar, T* wbar, T* kbar, double* sc,
+                          double rate_scale) {
+  const int K = c->opts.fixed_iter;
+  if (K <= 0) return fail(c, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  const Plan<T> p = make_plan<T>(c);
+  const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
+  const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
+  const int xb = xpass_blocks<T>(p);
+  T* jbuf = wsp<T>(c, c->off_adj);
+  T* acc = jbuf + 3 * c->nodes;
+  XArgs<T> a = base_args<T>(c);
+  // j = C h at the forward call's state (Eq. 4)
+  a.in = h;
+  a.in2 = in2;
+  a.in2_coef = (T)in2_coef;
+  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+  a.in2 = nullptr;
+  a.out = jbuf;
+  HIPCHK(c, run_x<T>(c, p, X_STORE, a));
+  // the exterior iteration (Eq. 5) transposed, last iterate first
+  a.in = lam;
+  a.in2 = mu;
+  a.out = acc;
+  HIPCHK(c, run_x<T>(c, p, X_ADJ_START, a));
+  a.in2 = nullptr;
+  for (int i = K - 1; i >= 0; --i) {
+    HIPCHK(c, spectral_middle<T>(c, p, phi_sym, norm));      // Phi (Eq. 7)
+    HIPCHK(c, run_x<T>(c, p, X_MASK, a));                     // chi
+    HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));        // C
+    if (i > 0) {
+      HIPCHK(c, run_x<T>(c, p, X_ADJ_ACC, a));
+    } else {
+      a.warm_out = wbar;
+      a.warm_used = warm_used ? 1 : 0;
+      HIPCHK(c, run_x<T>(c, p, X_ADJ_LAST, a));
+      HIPCHK(c, launch_accum_partials(a.partials, xb, 3, 3, rate_scale, sc + 1, c->stream));
+      a.warm_out = nullptr;
+    }
+  }
+  // ebar = -C gbar (Eq. 3); jbar = (de/dj)^T ebar (Eq. 1); hbar = C jbar (Eq. 4)
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, -norm));
+  a.in = jbuf;
+  a.kappa_bar = kbar;
+  HIPCHK(c, run_x<T>(c, p, X_ADJ_LAW, a));
+  HIPCHK(c, launch_accum_partials(a.partials, xb, 1, 1, 1.0, sc, c->stream));
+  a.kappa_bar = nullptr;
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+  a.out = hbar;
+  HIPCHK(c, run_x<T>(c, p, X_STORE, a));
+  return SCFFT_OK;
 }
 
 template <typename T>
@@ -778,6 +856,167 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
   st->dt_last_s *= c->u.t0;
   if (s == SCFFT_OK && st->not_converged > 0) s = SCFFT_WARN_NOT_CONVERGED;
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// reverse mode of fixed-step BS23
+// ---------------------------------------------------------------------------
+// Caller workspace: nseg checkpoints (state, k1, warm start at a segment's
+// first step), the tape of one segment (state, k1, k2 per step, and the
+// state after it), and 10 fields for the forward pass and the cotangents.
+struct AdjLayout {
+  size_t F = 0;
+  int nseg = 0, every = 0;
+  size_t off_tape = 0, off_vec = 0, total = 0;
+};
+
+AdjLayout adj_layout(const scfft_ctx* c, int steps, int every) {
+  AdjLayout L;
+  L.F = align_up(3 * (size_t)c->nodes * c->wsize);
+  L.every = every;
+  L.nseg = (steps + every - 1) / every;
+  L.off_tape = (size_t)L.nseg * 3 * L.F;
+  L.off_vec = L.off_tape + (size_t)(3 * every + 1) * L.F;
+  L.total = L.off_vec + 10 * L.F;
+  return L;
+}
+
+template <typename T>
+struct AdjRun {
+  scfft_ctx* c;
+  char* ws;
+  AdjLayout L;
+  T* f(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  T* cp(int seg, int k) const { return f(((size_t)seg * 3 + k) * L.F); }  // k: 0 y, 1 k1, 2 warm
+  T* tape(int m, int k) const { return f(L.off_tape + ((size_t)m * 3 + k) * L.F); }  // k: 0 y, 1 k1, 2 k2
+  T* yend() const { return f(L.off_tape + (size_t)(3 * L.every) * L.F); }
+  T* vec(int i) const { return f(L.off_vec + (size_t)i * L.F); }
+  size_t fb() const { return 3 * c->nodes * sizeof(T); }
+
+  scfft_status rhs(double t, const T* y, const T* k, double coef, T* out) {
+    return rhs_impl<T>(c, t, y, out, nullptr, k, coef, nullptr);
+  }
+  scfft_status combo(T* out, const T* y, const T* a, double ca, const T* b, double cb, const T* d,
+                     double cd) {
+    HIPCHK(c, launch_combo<T>(out, y, a, ca, b, cb, d, cd, 3 * c->nodes, c->stream));
+    return SCFFT_OK;
+  }
+  scfft_status copy(T* dst, const T* src) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, fb(), hipMemcpyDeviceToDevice, c->stream));
+    return SCFFT_OK;
+  }
+};
+
+#define ADJCHK(call)                  \
+  do {                                \
+    scfft_status s_ = (call);         \
+    if (s_ < 0) return s_;            \
+  } while (0)
+
+template <typename T>
+scfft_status integrate_adjoint_impl(scfft_ctx* c, double t0, double t1, int steps, int every,
+                                    char* ws, T* hT, const T* h0, const T* hT_bar, T* h0_bar, T* kbar,
+                                    double* n_bar, double p_bar[3]) {
+  AdjRun<T> R{c, ws, adj_layout(c, steps, every)};
+  const double dt = (t1 - t0) / steps;
+  auto t_of = [&](int s) { return s == 0 ? t0 : (s < steps ? t0 + s * dt : t1); };
+  double pv[3];
+  for (int d = 0; d < 3; ++d) pv[d] = c->drive.dir[d] * c->drive.amp;
+  const double pp = pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2];
+  auto rate = [&](double t) {  // f'(t) of a drive h_e = p f(t)
+    double he[3], hd[3];
+    c->drive.eval(t, he, hd);
+    return pp > 0.0 ? (hd[0] * pv[0] + hd[1] * pv[1] + hd[2] * pv[2]) / pp : 0.0;
+  };
+  T* warm = wsp<T>(c, c->off_warm);
+  const size_t wb = 3 * c->nodes * sizeof(T);
+
+  // ---- forward, checkpoint at the start of every segment ----
+  {
+    T *Y = R.vec(0), *Y1 = R.vec(1), *K1 = R.vec(2), *K2 = R.vec(3), *K3 = R.vec(4), *K4 = R.vec(5);
+    c->has_warm = false;
+    ADJCHK(R.copy(Y, h0));
+    ADJCHK(R.rhs(t0, Y, nullptr, 0.0, K1));
+    double t = t0;
+    for (int s = 0; s < steps; ++s) {
+      if (s % every == 0) {
+        const int seg = s / every;
+        ADJCHK(R.copy(R.cp(seg, 0), Y));
+        ADJCHK(R.copy(R.cp(seg, 1), K1));
+        HIPCHK(c, hipMemcpyAsync(R.cp(seg, 2), warm, wb, hipMemcpyDeviceToDevice, c->stream));
+      }
+      const double h = t_of(s + 1) - t;
+      ADJCHK(R.rhs(t + 0.5 * h, Y, K1, 0.5 * h, K2));
+      ADJCHK(R.rhs(t + 0.75 * h, Y, K2, 0.75 * h, K3));
+      ADJCHK(R.combo(Y1, Y, K1, h * (2.0 / 9.0), K2, h * (1.0 / 3.0), K3, h * (4.0 / 9.0)));
+      ADJCHK(R.rhs(t + h, Y1, nullptr, 0.0, K4));
+      std::swap(Y, Y1);
+      std::swap(K1, K4);
+      t = t_of(s + 1);
+    }
+    if (hT) ADJCHK(R.copy(hT, Y));
+  }
+
+  // ---- reverse ----
+  T *ybar = R.vec(0), *k1n = R.vec(1), *wbA = R.vec(2), *wbB = R.vec(3), *k1b = R.vec(4),
+    *k2b = R.vec(5), *k3b = R.vec(6), *ub = R.vec(7), *k3tmp = R.vec(8);
+  double* sc = wsp<double>(c, c->off_adjs);
+  HIPCHK(c, launch_zero_doubles(sc, 4, c->stream));
+  ADJCHK(R.copy(ybar, hT_bar));
+  ADJCHK(R.combo(k1n, nullptr, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0));   // zero
+  ADJCHK(R.combo(wbA, nullptr, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0));
+  for (int seg = R.L.nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * every, s1 = std::min(steps, s0 + every), len = s1 - s0;
+    auto yp = [&](int m) { return m == 0 ? R.cp(seg, 0) : (m < len ? R.tape(m, 0) : R.yend()); };
+    auto k1p = [&](int m) { return m == 0 ? R.cp(seg, 1) : R.tape(m, 1); };
+    // recompute the segment from its checkpoint (same arithmetic as the forward)
+    HIPCHK(c, hipMemcpyAsync(warm, R.cp(seg, 2), wb, hipMemcpyDeviceToDevice, c->stream));
+    c->has_warm = true;
+    double t = t_of(s0);
+    for (int m = 0; m < len; ++m) {
+      const double h = t_of(s0 + m + 1) - t;
+      ADJCHK(R.rhs(t + 0.5 * h, yp(m), k1p(m), 0.5 * h, R.tape(m, 2)));
+      ADJCHK(R.rhs(t + 0.75 * h, yp(m), R.tape(m, 2), 0.75 * h, k3tmp));
+      ADJCHK(R.combo(yp(m + 1), yp(m), k1p(m), h * (2.0 / 9.0), R.tape(m, 2), h * (1.0 / 3.0), k3tmp,
+                     h * (4.0 / 9.0)));
+      if (m + 1 < len) ADJCHK(R.rhs(t + h, yp(m + 1), nullptr, 0.0, R.tape(m + 1, 1)));
+      t = t_of(s0 + m + 1);
+    }
+    // adjoint steps, last first
+    for (int m = len - 1; m >= 0; --m) {
+      const double ts = t_of(s0 + m), h = t_of(s0 + m + 1) - ts;
+      // k4 = f(t + h, y_{n+1}; w3): cotangent k1n (the next step's k1), warm cotangent wbA
+      ADJCHK(rhs_vjp_impl<T>(c, yp(m + 1), nullptr, 0.0, true, k1n, wbA, ub, wbB, kbar, sc,
+                             rate(ts + h)));
+      ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
+      // y_{n+1} = y + h (2/9 k1 + 1/3 k2 + 4/9 k3)
+      ADJCHK(R.combo(k1b, nullptr, ybar, h * (2.0 / 9.0), nullptr, 0.0, nullptr, 0.0));
+      ADJCHK(R.combo(k2b, nullptr, ybar, h * (1.0 / 3.0), nullptr, 0.0, nullptr, 0.0));
+      ADJCHK(R.combo(k3b, nullptr, ybar, h * (4.0 / 9.0), nullptr, 0.0, nullptr, 0.0));
+      // k3 = f(t + 3h/4, y + 3h/4 k2; w2)
+      ADJCHK(rhs_vjp_impl<T>(c, yp(m), R.tape(m, 2), 0.75 * h, true, k3b, wbB, ub, wbA, kbar, sc,
+                             rate(ts + 0.75 * h)));
+      ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
+      ADJCHK(R.combo(k2b, k2b, ub, 0.75 * h, nullptr, 0.0, nullptr, 0.0));
+      // k2 = f(t + h/2, y + h/2 k1; w1)
+      ADJCHK(rhs_vjp_impl<T>(c, yp(m), k1p(m), 0.5 * h, true, k2b, wbA, ub, wbB, kbar, sc,
+                             rate(ts + 0.5 * h)));
+      ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
+      ADJCHK(R.combo(k1n, k1b, ub, 0.5 * h, nullptr, 0.0, nullptr, 0.0));
+      std::swap(wbA, wbB);
+    }
+  }
+  // the first evaluation k1 = f(t0, y0) started without a warm start
+  ADJCHK(rhs_vjp_impl<T>(c, h0, nullptr, 0.0, false, k1n, wbA, ub, nullptr, kbar, sc, rate(t0)));
+  ADJCHK(R.combo(h0_bar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
+  double r[4];
+  HIPCHK(c, hipMemcpyAsync(r, sc, sizeof r, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (n_bar) *n_bar = r[0];
+  if (p_bar)
+    for (int d = 0; d < 3; ++d) p_bar[d] = r[1 + d];
+  c->has_warm = false;  // the context's warm start no longer belongs to a caller's trajectory
+  return SCFFT_OK;
 }
 
 template <typename T>
@@ -1105,6 +1344,77 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
   return ctx->prec == SCFFT_F64
              ? integrate_impl<double>(ctx, t0_s, t1_s, (double*)h_dev, o, obs, user, s)
              : integrate_impl<float>(ctx, t0_s, t1_s, (float*)h_dev, o, obs, user, s);
+}
+
+scfft_status scfft_rhs_vjp(scfft_ctx* ctx, const void* h_dev, int32_t warm_used,
+                           const void* lam_dev, const void* mu_dev, void* hbar_dev, void* wbar_dev,
+                           void* kappa_bar_dev, double* n_bar, double hedot_bar[3]) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!h_dev || !lam_dev || !hbar_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  if (hbar_dev == h_dev || hbar_dev == lam_dev || hbar_dev == mu_dev ||
+      (wbar_dev && (wbar_dev == h_dev || wbar_dev == hbar_dev)))
+    return fail(ctx, SCFFT_ERR_ARG, "outputs must not alias inputs");
+  if (ctx->opts.fixed_iter <= 0)
+    return fail(ctx, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  double* sc = wsp<double>(ctx, ctx->off_adjs);
+  HIPCHK(ctx, launch_zero_doubles(sc, 4, ctx->stream));
+  st = ctx->prec == SCFFT_F64
+           ? rhs_vjp_impl<double>(ctx, (const double*)h_dev, nullptr, 0.0, warm_used != 0,
+                                  (const double*)lam_dev, (const double*)mu_dev, (double*)hbar_dev,
+                                  (double*)wbar_dev, (double*)kappa_bar_dev, sc, 1.0)
+           : rhs_vjp_impl<float>(ctx, (const float*)h_dev, nullptr, 0.0, warm_used != 0,
+                                 (const float*)lam_dev, (const float*)mu_dev, (float*)hbar_dev,
+                                 (float*)wbar_dev, (float*)kappa_bar_dev, sc, 1.0);
+  if (st < 0) return st;
+  double r[4];
+  HIPCHK(ctx, hipMemcpyAsync(r, sc, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (n_bar) *n_bar = r[0];
+  if (hedot_bar)
+    for (int d = 0; d < 3; ++d) hedot_bar[d] = r[1 + d];
+  return SCFFT_OK;
+}
+
+scfft_status scfft_adjoint_workspace_size(const scfft_ctx* ctx, int32_t steps,
+                                          int32_t checkpoint_every, size_t* bytes) {
+  if (!ctx || !bytes || steps <= 0 || checkpoint_every <= 0) return SCFFT_ERR_ARG;
+  *bytes = adj_layout(ctx, steps, std::min(checkpoint_every, steps)).total;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_integrate_adjoint(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
+                                     int32_t checkpoint_every, void* adj_ws, size_t adj_bytes,
+                                     const void* h0_dev, const void* hT_bar_dev, void* hT_dev,
+                                     void* h0_bar_dev, void* kappa_bar_dev, double* n_bar,
+                                     double p_bar[3]) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  if (steps <= 0 || checkpoint_every <= 0 || !(t1_s > t0_s))
+    return fail(ctx, SCFFT_ERR_ARG, "invalid steps, checkpoint interval or time span");
+  if (!h0_dev || !hT_bar_dev || !h0_bar_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  if (h0_bar_dev == h0_dev || h0_bar_dev == hT_bar_dev || (hT_dev && (hT_dev == h0_dev || hT_dev == h0_bar_dev)))
+    return fail(ctx, SCFFT_ERR_ARG, "outputs must not alias inputs");
+  if (ctx->opts.fixed_iter <= 0)
+    return fail(ctx, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  if (p_bar && ctx->drive.kind == SCFFT_DRIVE_PWL)
+    return fail(ctx, SCFFT_ERR_ARG, "p_bar needs a drive of the form p f(t) (ramp-hold or sine)");
+  const int every = std::min<int>(checkpoint_every, steps);
+  const AdjLayout L = adj_layout(ctx, steps, every);
+  if (!adj_ws || adj_bytes < L.total || (reinterpret_cast<uintptr_t>(adj_ws) & 255))
+    return fail(ctx, SCFFT_ERR_WORKSPACE, "adjoint workspace: %zu bytes at a 256-byte boundary needed",
+                L.total);
+  const double t0 = t0_s / ctx->u.t0, t1 = t1_s / ctx->u.t0;
+  return ctx->prec == SCFFT_F64
+             ? integrate_adjoint_impl<double>(ctx, t0, t1, steps, every, (char*)adj_ws, (double*)hT_dev,
+                                              (const double*)h0_dev, (const double*)hT_bar_dev,
+                                              (double*)h0_bar_dev, (double*)kappa_bar_dev, n_bar, p_bar)
+             : integrate_adjoint_impl<float>(ctx, t0, t1, steps, every, (char*)adj_ws, (float*)hT_dev,
+                                             (const float*)h0_dev, (const float*)hT_bar_dev,
+                                             (float*)h0_bar_dev, (float*)kappa_bar_dev, n_bar, p_bar);
 }
 
 scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev) {

@@ -110,6 +110,12 @@ _SIGS = {
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
     "scfft_step_moment": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double)]),
+    "scfft_rhs_vjp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
+    "scfft_adjoint_workspace_size": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scfft_integrate_adjoint": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, C.c_int32, _P,
+                                          C.c_size_t, _P, _P, _P, _P, _P, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]),
     "scfft_region_mean_abs_b": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
     "scfft_probe_b": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]),
     "scfft_get_state": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
@@ -353,6 +359,35 @@ def scfft_step_moment(ctx, omega_only=0):
     return np.array(m[:])
 
 
+def scfft_rhs_vjp(ctx, h, warm_used, lam, mu, hbar, wbar=None, kappa_bar=None):
+    """Returns (n_bar, hedot_bar); hbar (and wbar) are written, kappa_bar is
+    accumulated."""
+    nb = C.c_double()
+    hb = (C.c_double * 3)()
+    _check(load().scfft_rhs_vjp(ctx, _ptr(h), int(warm_used), _ptr(lam), _ptr(mu), _ptr(hbar),
+                                _ptr(wbar), _ptr(kappa_bar), C.byref(nb), hb), ctx)
+    return nb.value, np.array(hb[:])
+
+
+def scfft_adjoint_workspace_size(ctx, steps, checkpoint_every):
+    n = C.c_size_t()
+    _check(load().scfft_adjoint_workspace_size(ctx, int(steps), int(checkpoint_every), C.byref(n)), ctx)
+    return n.value
+
+
+def scfft_integrate_adjoint(ctx, t0_s, t1_s, steps, checkpoint_every, adj_ws, h0, hT_bar, hT,
+                            h0_bar, kappa_bar=None, want_p_bar=True):
+    """Returns (n_bar, p_bar or None); hT, h0_bar written, kappa_bar accumulated."""
+    nb = C.c_double()
+    pb = (C.c_double * 3)()
+    nbytes = adj_ws.numel() * adj_ws.element_size()
+    _check(load().scfft_integrate_adjoint(ctx, float(t0_s), float(t1_s), int(steps),
+                                          int(checkpoint_every), _ptr(adj_ws), nbytes, _ptr(h0),
+                                          _ptr(hT_bar), _ptr(hT), _ptr(h0_bar), _ptr(kappa_bar),
+                                          C.byref(nb), pb if want_p_bar else None), ctx)
+    return nb.value, (np.array(pb[:]) if want_p_bar else None)
+
+
 def scfft_region_mean_abs_b(ctx, h, dev_region):
     b = C.c_double()
     _check(load().scfft_region_mean_abs_b(ctx, _ptr(h), _ptr(dev_region), C.byref(b)), ctx)
@@ -382,7 +417,8 @@ def scfft_set_state(ctx, blob):
 
 KERNEL_KINDS = ["X_FWD", "X_LAW", "X_HIN", "X_MASK", "X_UPDATE", "X_UPDATE_LAST", "X_STORE",
                 "X_MOMENT", "Y_FWD", "Y_INV", "Z_CURL", "Z_PHI", "XY_FWD", "XY_HIN", "XY_MASK",
-                "XY_UPDATE", "XY_UPDATE_LAST", "XY_STORE"]
+                "XY_UPDATE", "XY_UPDATE_LAST", "XY_STORE", "X_ADJ_START", "X_ADJ_ACC", "X_ADJ_LAST",
+                "X_ADJ_LAW"]
 
 
 def scfft_profile(ctx, enable):

@@ -1,0 +1,189 @@
+"""Reverse mode on the GPU against the oracle's reverse mode (itself pinned by
+the affine-case adjoint identity and central differences): one
+right-hand-side call (fixed iteration count, explicit warm start) and the
+fixed-step integrator with checkpoints.  FP64 <= 1e-10 relative to the
+largest reference value; FP32 against FP64 <= 1e-4 relative L2."""
+import numpy as np
+import pytest
+
+from gpu_case import oracle_problem, rel_l2, rel_max, sim, small_cfg, state, to_dev
+from oracle import adjoint, operators
+from paper_1803_01346_amd import scfft, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CUBE32 = dict(workloads.config("cube32"), n_power=20.0)
+NONCUBIC = small_cfg((16, 32, 64), (1.5, 2.0, 3.0), workloads.shape_cup(1.0, 0.6, 3.0, 0.4, axis=1))
+SQZ = small_cfg((32, 32, 16), (2.0, 2.0, 1.0), workloads.shape_cylinder(0.8, 1.2))
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    scfft.load()
+
+
+def _scaled_state(cfg, prob, seed, bg=(0.0, 0.02, 0.05)):
+    """State whose smoothed current reaches 1.05 in Omega."""
+    h = state(cfg, seed=seed, bg=(0.0, 0.0, 0.0))
+    j = operators.curl_s(h, prob.grid)
+    a = np.sqrt(np.sum(j * j, axis=0))[prob.chi != 0]
+    return h * (1.05 / float(np.max(a))) + np.asarray(bg).reshape(3, 1, 1, 1)
+
+
+def _kappa(cfg, seed):
+    n = cfg["n"]
+    return 1.0 + 0.1 * np.random.default_rng(seed).normal(size=(n[2], n[1], n[0]))
+
+
+def _rel(x, r):
+    return abs(x - r) / max(abs(r), 1e-300)
+
+
+@pytest.mark.parametrize("cfg", [CUBE32, NONCUBIC], ids=["cube32", "noncubic"])
+@pytest.mark.parametrize("warm_used", [True, False])
+@pytest.mark.parametrize("with_kappa", [False, True])
+def test_rhs_vjp_fp64(cfg, warm_used, with_kappa):
+    K = 3
+    prob, u = oracle_problem(cfg, fixed_iter=K)
+    s = sim(cfg, fixed_iter=K)
+    kap = _kappa(cfg, 4) if with_kappa else None
+    if kap is not None:
+        prob.kappa = kap
+        dk = to_dev(torch, kap, torch.float64)
+        scfft.scfft_set_jc_map(s.ctx, dk)
+    h = _scaled_state(cfg, prob, 1)
+    lam = state(cfg, seed=2, bg=(0.0, 0.0, 0.0))
+    mu = state(cfg, seed=3, bg=(0.0, 0.0, 0.0))
+    dh, dl, dm = (to_dev(torch, a, torch.float64) for a in (h, lam, mu))
+    hbar, wbar = s.empty_field(), s.empty_field()
+    kbar = torch.zeros(prob.grid.shape, dtype=torch.float64, device="cuda")
+    nb, hb = scfft.scfft_rhs_vjp(s.ctx, dh, warm_used, dl, dm, hbar, wbar, kbar)
+    torch.cuda.synchronize()
+    r = adjoint.rhs_vjp(prob, 0.01, h, warm_used, lam, mu)
+    assert rel_max(_np(hbar), r["h_bar"]) < 1e-10
+    assert rel_max(_np(wbar), r["w_bar"]) < 1e-10
+    assert rel_max(_np(kbar), r["kappa_bar"]) < 1e-10
+    assert _rel(nb, r["n_bar"]) < 1e-10
+    assert np.max(np.abs(hb - r["hedot_bar"])) <= 1e-10 * np.max(np.abs(r["hedot_bar"]))
+
+
+def test_rhs_with_kappa_map_fp64():
+    """Forward right-hand side with a local critical-density map (Eq. 1 with
+    jc(x)) against the oracle."""
+    cfg = CUBE32
+    prob, u = oracle_problem(cfg, fixed_iter=3)
+    s = sim(cfg, fixed_iter=3)
+    prob.kappa = _kappa(cfg, 5)
+    scfft.scfft_set_jc_map(s.ctx, to_dev(torch, prob.kappa, torch.float64))
+    h = _scaled_state(cfg, prob, 6)
+    out, _ = s.rhs_eval(0.01 * u.t0, to_dev(torch, h, torch.float64))
+    want = adjoint.rhs_forward(prob, 0.01, h, None)[0]
+    assert rel_max(_np(out), want) < 1e-10
+
+
+def test_rhs_vjp_fp32_vs_fp64():
+    cfg = CUBE32
+    prob, _ = oracle_problem(cfg, fixed_iter=3)
+    h = _scaled_state(cfg, prob, 7)
+    lam = state(cfg, seed=8, bg=(0.0, 0.0, 0.0))
+    mu = state(cfg, seed=9, bg=(0.0, 0.0, 0.0))
+    res = []
+    for prec, dt in ((scfft.F64, torch.float64), (scfft.F32, torch.float32)):
+        s = sim(cfg, precision=prec, fixed_iter=3)
+        hbar, wbar = s.empty_field(), s.empty_field()
+        nb, hb = scfft.scfft_rhs_vjp(s.ctx, to_dev(torch, h, dt), True, to_dev(torch, lam, dt),
+                                     to_dev(torch, mu, dt), hbar, wbar)
+        torch.cuda.synchronize()
+        res.append((_np(hbar), _np(wbar), nb, hb))
+    (a, b, n64, h64), (c, d, n32, h32) = res
+    assert rel_l2(c, a) < 1e-4 and rel_l2(d, b) < 1e-4
+    assert _rel(n32, n64) < 1e-4
+    assert np.max(np.abs(h32 - h64)) <= 1e-4 * np.max(np.abs(h64))
+
+
+def _adjoint_run(s, cfg, h0, hT_bar, steps, every, t1_s, dtype=torch.float64, kbar=None):
+    nbytes = scfft.scfft_adjoint_workspace_size(s.ctx, steps, every)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + nbytes]
+    hT, h0b = s.empty_field(), s.empty_field()
+    nb, pb = scfft.scfft_integrate_adjoint(s.ctx, 0.0, t1_s, steps, every, ws, to_dev(torch, h0, dtype),
+                                           to_dev(torch, hT_bar, dtype), hT, h0b, kbar)
+    torch.cuda.synchronize()
+    return hT, h0b, nb, pb
+
+
+@pytest.mark.parametrize("cfg", [SQZ, NONCUBIC], ids=["sqz", "noncubic"])
+def test_integrate_adjoint_fp64(cfg):
+    K, steps, every = 2, 5, 2          # three segments, the last one ragged
+    prob, u = oracle_problem(cfg, fixed_iter=K)
+    s = sim(cfg, fixed_iter=K)
+    h0 = _scaled_state(cfg, prob, 11)
+    ybar = state(cfg, seed=12, bg=(0.0, 0.0, 0.0))
+    t1_s = 2e-3 * u.t0
+    kbar = torch.zeros(prob.grid.shape, dtype=torch.float64, device="cuda")
+    hT, h0b, nb, pb = _adjoint_run(s, cfg, h0, ybar, steps, every, t1_s, kbar=kbar)
+    yT, g = adjoint.integrate_adjoint(prob, 0.0, t1_s / u.t0, h0, steps, ybar)
+    assert rel_max(_np(hT), yT) < 1e-10
+    assert rel_max(_np(h0b), g["y0_bar"]) < 1e-10
+    assert rel_max(_np(kbar), g["kappa_bar"]) < 1e-10
+    assert _rel(nb, g["n_bar"]) < 1e-10
+    assert np.max(np.abs(pb - g["p_bar"])) <= 1e-10 * np.max(np.abs(g["p_bar"]))
+
+
+def test_integrate_adjoint_checkpoint_interval_and_forward_agree():
+    """Any checkpoint interval gives bitwise the same gradient (the recomputed
+    segments repeat the forward arithmetic), and the forward result is that of
+    scfft_integrate's fixed-step mode after a warm-start reset."""
+    cfg = SQZ
+    prob, u = oracle_problem(cfg, fixed_iter=2)
+    s = sim(cfg, fixed_iter=2)
+    h0 = _scaled_state(cfg, prob, 13)
+    ybar = state(cfg, seed=14, bg=(0.0, 0.0, 0.0))
+    t1_s, steps = 2e-3 * u.t0, 6
+    outs = [_adjoint_run(s, cfg, h0, ybar, steps, every, t1_s) for every in (1, 4, 6, 50)]
+    for hT, h0b, nb, pb in outs[1:]:
+        assert torch.equal(hT, outs[0][0]) and torch.equal(h0b, outs[0][1])
+        assert nb == outs[0][2] and np.array_equal(pb, outs[0][3])
+    scfft.scfft_reset_warm(s.ctx)
+    h = to_dev(torch, h0, torch.float64)
+    scfft.scfft_integrate(s.ctx, 0.0, t1_s, h, scfft.default_ode_opts(fixed_steps=steps))
+    torch.cuda.synchronize()
+    assert torch.equal(h, outs[0][0])
+
+
+def test_integrate_adjoint_fp32_vs_fp64():
+    cfg = SQZ
+    prob, u = oracle_problem(cfg, fixed_iter=2)
+    h0 = _scaled_state(cfg, prob, 15)
+    ybar = state(cfg, seed=16, bg=(0.0, 0.0, 0.0))
+    res = []
+    for prec, dt in ((scfft.F64, torch.float64), (scfft.F32, torch.float32)):
+        s = sim(cfg, precision=prec, fixed_iter=2)
+        hT, h0b, nb, pb = _adjoint_run(s, cfg, h0, ybar, 4, 2, 2e-3 * u.t0, dtype=dt)
+        res.append((_np(hT), _np(h0b), nb, pb))
+    assert rel_l2(res[1][0], res[0][0]) < 1e-4
+    assert rel_l2(res[1][1], res[0][1]) < 1e-4
+    assert _rel(res[1][2], res[0][2]) < 1e-4
+
+
+def test_reverse_mode_argument_errors():
+    cfg = SQZ
+    s = sim(cfg)                                    # adaptive iteration: no reverse mode
+    h = s.empty_field().zero_()
+    hb = s.empty_field()
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_rhs_vjp(s.ctx, h, True, h, None, hb)
+    s2 = sim(cfg, fixed_iter=2)
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_rhs_vjp(s2.ctx, h, True, h, None, h)           # output aliases input
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_integrate_adjoint(s2.ctx, 0.0, 1.0, 4, 2, small, h, h, None, hb)
