@@ -164,6 +164,50 @@ def lens256_leg(calls=10):
     return out
 
 
+def adjoint_leg(cfg, steps=100, every=50):
+    """Reverse-mode cost on the shield with a jc(x) map (kappa = 1 + 0.1 N(0,1),
+    seed 5) at a fixed step of 2e-5 s: time of the checkpointed adjoint
+    (forward with checkpoints, segment recomputation, reverse steps) over the
+    time of the plain forward integration of the same steps."""
+    import numpy as np
+    import torch
+    from paper_1803_01346_amd import autograd as sag, scfft
+    sim = make_sim(cfg, scfft.F64, FIXED_ITER)
+    n = cfg["n"]
+    kap = 1.0 + 0.1 * np.random.default_rng(5).normal(size=(n[2], n[1], n[0]))
+    dk = torch.from_numpy(kap).to(device="cuda").contiguous()
+    scfft.scfft_set_jc_map(sim.ctx, dk)
+    h0, _ = initial_state(sim, cfg)
+    t1 = steps * 2e-5
+    ws = sag.adjoint_workspace(sim, steps, every)
+    hT, h0b, ybar = sim.empty_field(), sim.empty_field(), torch.ones_like(h0)
+
+    def fwd():
+        h = h0.clone()
+        scfft.scfft_reset_warm(sim.ctx)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        scfft.scfft_integrate(sim.ctx, 0.0, t1, h, scfft.default_ode_opts(fixed_steps=steps))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def adj():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        scfft.scfft_integrate_adjoint(sim.ctx, 0.0, t1, steps, every, ws, h0, ybar, hT, h0b)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    fwd(), adj()                                   # warm-up
+    tf = min(fwd() for _ in range(2))
+    ta = min(adj() for _ in range(2))
+    out = dict(ratio=round(ta / tf, 3), forward_s=round(tf, 4), adjoint_s=round(ta, 4), steps=steps,
+               checkpoint_every=every, dt_s=2e-5, dtype="f64",
+               note="ratio = (forward with checkpoints + recomputation + reverse) / forward")
+    sim.close()
+    return out
+
+
 def cpu_baseline(cfg, h_np):
     """The oracle's rhs_eval on the same 128^3 state with one exterior
     iteration (4 of the 8 spectral operator applications of a k = 3 call),
@@ -208,6 +252,7 @@ def main():
     ap.add_argument("--no-events", action="store_true", help="skip the per-kernel event timing run")
     ap.add_argument("--no-converged", action="store_true", help="skip the delta_it stopping-rule leg")
     ap.add_argument("--no-lens", action="store_true", help="skip the 256^3 FP32 lens leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -275,6 +320,7 @@ def main():
 
     converged = None if args.no_converged else converged_leg(cfg, h)
     lens = None if args.no_lens else lens256_leg()
+    adj = None if args.no_adjoint else adjoint_leg(cfg)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -282,7 +328,7 @@ def main():
         cpu = cpu_baseline(cfg, h_np)
 
     line = {
-        "metric": "RHS evals/sec at 128^3 (FP64 vs FP32 @1e-4 rel err), % HBM peak",
+        "metric": "RHS evals/sec at 128³ (FP64 vs FP32 @1e-4 rel err), % HBM peak; adjoint cost",
         "value": round(value, 2),
         "unit": "RHS evals/s",
         "n_gpus": 1,
@@ -302,6 +348,7 @@ def main():
         "fp32": fp32,
         "converged": converged,
         "lens256_f32": lens,
+        "adjoint_cost": adj,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,

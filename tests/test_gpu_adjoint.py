@@ -187,3 +187,17 @@ def test_reverse_mode_argument_errors():
     small = torch.empty(1024, dtype=torch.uint8, device="cuda")
     with pytest.raises(scfft.ScfftError):
         scfft.scfft_integrate_adjoint(s2.ctx, 0.0, 1.0, 4, 2, small, h, h, None, hb)
+
+
+def test_autograd_gradcheck():
+    """torch.autograd.gradcheck (central differences of the GPU forward path
+    against the library's reverse mode) for one call and for the integrator."""
+    from paper_1803_01346_amd import autograd as sag
+    cfg = small_cfg((8, 8, 8), (1.0, 1.0, 1.0), workloads.shape_cube(0.5))
+    prob, u = oracle_problem(cfg, fixed_iter=2)
+    s = sim(cfg, fixed_iter=2)
+    h = to_dev(torch, _scaled_state(cfg, prob, 21), torch.float64).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: sag.RhsEval.apply(x, s, 0.01 * u.t0), (h,), eps=1e-6,
+                                    atol=1e-6, rtol=1e-4, fast_mode=True)
+    assert torch.autograd.gradcheck(lambda x: sag.Integrate.apply(x, s, 0.0, 1e-3 * u.t0, 3, 2), (h,),
+                                    eps=1e-6, atol=1e-6, rtol=1e-4, fast_mode=True)
