@@ -42,7 +42,6 @@ template <typename T>
 struct Plan {
   int nx, ny, nz;
   C2<T>* main;
-  C2<T>* nyq;
   AxisTab<T> ax, ay, az;
   Ranges r;
   void full_ranges() {

@@ -11,8 +11,9 @@
 //            transform, the operator's symbol (smoothed curl or Phi of
 //            Eq. 7, both cross products with i k), inverse transform
 // The spectrum of each component is stored as main[z][y][kx], kx < Nx/2,
-// plus the Nyquist column nyq[z][y] (kx = Nx/2), so every row of the main
-// part is a power of two long and column tiles stay aligned.
+// with the Nyquist plane (kx = Nx/2) packed into the kx = 0 column (see the
+// note before the Y pass), so every row is a power of two long, column tiles
+// stay aligned and the column passes have no leftover blocks.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -84,13 +85,40 @@ template <bool PP, typename T, int N, int COLS>
 using ColLds = typename std::conditional<PP, LdsColsPP<T, N, COLS>, LdsCols<T, COLS>>::type;
 
 // ---------------------------------------------------------------------------
+// The kx = 0 column of the half spectrum carries two real x-spectra: the
+// X pass stores X[0] + i X[Nx/2] there (both are real for a real field), so
+// every row of the spectrum is a power of two long and no column is left
+// over.  Along y the two are separated: after the forward y transform of
+// that column, P(ky) = A(ky) + i B(ky) with A = F_y X[0] and B = F_y X[Nx/2]
+// both Hermitian in ky, so the column is rewritten in a half-complex layout
+//   slot ky   = A(ky)             1 <= ky < Ny/2
+//   slot Ny-ky = B(ky)            1 <= ky < Ny/2
+//   slot 0, Ny/2 = A + i B        (A and B real there)
+// The Z pass transforms these columns like any other, using the Nyquist-plane
+// wavevector (kx = Nx/2, Ny - ky) for the B columns and separating A and B
+// along z in the two packed columns; the inverse y transform first rebuilds
+// P(ky) from the half-complex layout.
+// ---------------------------------------------------------------------------
+
+// Y forward, kx = 0 column, slot y: P = P(y), Q = P(Ny - y).
+template <typename T>
+__device__ __forceinline__ C2<T> dc_split(C2<T> P, C2<T> Q, bool low) {
+  if (low) return {T(0.5) * (P.x + Q.x), T(0.5) * (P.y - Q.y)};   // A(y) = (P + conj Q) / 2
+  return {T(0.5) * (Q.y + P.y), T(0.5) * (P.x - Q.x)};             // B(Ny-y) = (Q - conj P) / 2i
+}
+// Y inverse, kx = 0 column, slot y: S = slot y, R = slot Ny - y.
+template <typename T>
+__device__ __forceinline__ C2<T> dc_join(C2<T> S, C2<T> R, bool low) {
+  if (low) return {S.x - R.y, S.y + R.x};                          // A + i B, A = S, B = R
+  return {R.x + S.y, S.x - R.y};                                   // conj(A) + i conj(B), A = R, B = S
+}
+
+// ---------------------------------------------------------------------------
 // Y pass
 // ---------------------------------------------------------------------------
 template <typename T, int NY, bool INV>
-__global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
-                                                       C2<T>* __restrict__ nyq, int M, int nz,
-                                                       Ranges R, int nblk_main,
-                                                       const C2<T>* __restrict__ tw) {
+__global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main, int M, int nz,
+                                                       Ranges R, const C2<T>* __restrict__ tw) {
   constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
   constexpr int COLS = kBlock / TPT;
@@ -99,21 +127,16 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
   const int col = tid % COLS;
   const int j = tid / COLS;
   const int nzr = R.zhi - R.zlo;                       // planes processed
-  const bool is_nyq = (int)blockIdx.x >= nblk_main;
-  const int q = (is_nyq ? (int)blockIdx.x - nblk_main : (int)blockIdx.x) * COLS + col;
-  const bool valid = q < (is_nyq ? 3 * nzr : 3 * nzr * M);
-  C2<T>* p;
-  size_t es;
-  if (!is_nyq) {
-    const int blk = q / M, kx = q % M;                 // blk = c * nzr + (z - zlo)
-    const int c = blk / nzr, z = R.zlo + blk % nzr;
-    p = main + ((size_t)c * nz + z) * NY * M + kx;
-    es = (size_t)M;
-  } else {
-    const int c = q / nzr, z = R.zlo + q % nzr;
-    p = nyq + ((size_t)c * nz + z) * NY;
-    es = 1;
-  }
+  const int q0 = (int)blockIdx.x * COLS;
+  const int q = q0 + col;
+  const bool valid = q < 3 * nzr * M;
+  const int blk = q / M, kx = q % M;                   // blk = c * nzr + (z - zlo)
+  const int c = blk / nzr, z = R.zlo + blk % nzr;
+  C2<T>* p = main + ((size_t)c * nz + z) * NY * M + kx;
+  const size_t es = (size_t)M;
+  // blocks holding a kx = 0 column (uniform per block)
+  const bool dc_block = (q0 % M == 0) || (q0 / M != (q0 + COLS - 1) / M);
+  const bool dc = valid && kx == 0;
   C2<T> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -121,10 +144,37 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
     v[m] = (valid && y >= R.ylo_in && y < R.yhi_in) ? p[(size_t)y * es] : C2<T>{T(0), T(0)};
   }
   ColLds<SCFFT_PP_Y, T, NY, COLS> lds{smem, col};
-  if constexpr (INV)
+  if constexpr (INV) {
+    if (dc_block) {  // rebuild P(ky) of the kx = 0 column from its half-complex layout
+#pragma unroll
+      for (int m = 0; m < E; ++m) smem[(j + m * TPT) * COLS + col] = v[m];
+      __syncthreads();
+      if (dc) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int y = j + m * TPT;
+          if (y != 0 && 2 * y != NY) v[m] = dc_join(v[m], smem[(NY - y) * COLS + col], 2 * y < NY);
+        }
+      }
+      __syncthreads();
+    }
     fft_inverse<T, NY, E>(v, j, lds, tw, 1);
-  else
+  } else {
     fft_forward<T, NY, E>(v, j, lds, tw, 1);
+    if (dc_block) {  // split the kx = 0 column into A and B (half-complex layout)
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) smem[(j + m * TPT) * COLS + col] = v[m];
+      __syncthreads();
+      if (dc) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int y = j + m * TPT;
+          if (y != 0 && 2 * y != NY) v[m] = dc_split(v[m], smem[(NY - y) * COLS + col], 2 * y < NY);
+        }
+      }
+    }
+  }
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -137,11 +187,38 @@ __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main,
 // ---------------------------------------------------------------------------
 // Z pass: forward z transform of the three components, symbol, inverse.
 // ---------------------------------------------------------------------------
+// multiplier of the symbol at wavevector indices (ix, iy, iz)
+template <typename T, int SYM>
+__device__ __forceinline__ T zsym_factor(const AxisTab<T>& tx, const AxisTab<T>& ty,
+                                         const AxisTab<T>& tz, int ix, int iy, int iz, T coef) {
+  if constexpr (SYM == Z_CURL) {
+    return coef * tx.sm[ix] * ty.sm[iy] * tz.sm[iz];
+  } else {
+    const T k2 = tx.kk[ix] + ty.kk[iy] + tz.kk[iz];
+    T f = k2 > T(0) ? coef / k2 : T(0);
+    if constexpr (SYM == Z_PHI_SMOOTH) f = f * tx.sm[ix] * ty.sm[iy] * tz.sm[iz];
+    return f;
+  }
+}
+
+// i f (k_odd x v) for one wavevector
+template <typename T>
+__device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, T kyo, T kzo, T f) {
+  // k x v, then multiply by i f:  i (u + i w) f = (-w f, u f)
+  const C2<T> cx = {kyo * d.x - kzo * b.x, kyo * d.y - kzo * b.y};
+  const C2<T> cy = {kzo * a.x - kxo * d.x, kzo * a.y - kxo * d.y};
+  const C2<T> cz = {kxo * b.x - kyo * a.x, kxo * b.y - kyo * a.y};
+  a = {-cx.y * f, cx.x * f};
+  b = {-cy.y * f, cy.x * f};
+  d = {-cz.y * f, cz.x * f};
+}
+
+// FP64: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per CU, so
+// the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on 256 CUs
 template <typename T, int NZ, int SYM>
-__global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
-                                                       C2<T>* __restrict__ nyq, int ny, int M,
-                                                       int nblk_main, AxisTab<T> tx, AxisTab<T> ty,
-                                                       AxisTab<T> tz, T coef, Ranges R) {
+__global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
+    C2<T>* __restrict__ main, int ny, int M, AxisTab<T> tx, AxisTab<T> ty, AxisTab<T> tz, T coef,
+    Ranges R) {
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = kBlock / TPT;
@@ -149,31 +226,23 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
-  const bool is_nyq = (int)blockIdx.x >= nblk_main;
-  const int q = (is_nyq ? (int)blockIdx.x - nblk_main : (int)blockIdx.x) * COLS + col;
-  C2<T>* p;
-  size_t es, cs;
-  int kx, ky;
-  bool valid;
-  if (!is_nyq) {
-    valid = q < ny * M;
-    p = main + q;
-    es = (size_t)ny * M;
-    cs = (size_t)NZ * ny * M;
-    kx = q % M;
-    ky = q / M;
-  } else {
-    valid = q < ny;
-    p = nyq + q;
-    es = (size_t)ny;
-    cs = (size_t)NZ * ny;
+  const int q0 = (int)blockIdx.x * COLS;
+  const int q = q0 + col;
+  const bool valid = q < ny * M;
+  C2<T>* p = main + q;
+  const size_t es = (size_t)ny * M;
+  const size_t cs = (size_t)NZ * ny * M;
+  int kx = valid ? q % M : 0, ky = valid ? q / M : 0;
+  // kx = 0 columns (see the layout note above): ky in (0, ny/2) hold A, the
+  // kx = 0 plane; ky in (ny/2, ny) hold B of ky' = ny - ky, the Nyquist
+  // plane; ky = 0 and ny/2 hold A + i B, separated along z below.
+  const bool packed = valid && kx == 0 && (ky == 0 || 2 * ky == ny);
+  if (kx == 0 && 2 * ky > ny) {
     kx = M;
-    ky = q;
+    ky = ny - ky;
   }
-  if (!valid) {
-    kx = 0;
-    ky = 0;
-  }
+  const int qa = (ny / 2) * M;                      // the second packed column
+  const bool pk_block = q0 == 0 || (q0 <= qa && qa < q0 + COLS);  // uniform per block
   C2<T> v[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -187,17 +256,48 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
 
-  const T kxo = tx.kodd[kx], kyo = ty.kodd[ky];
-  T fxy;
-  if constexpr (SYM == Z_CURL) {
-    fxy = coef * tx.sm[kx] * ty.sm[ky];
-  } else {
-    fxy = tx.kk[kx] + ty.kk[ky];
+  // Packed columns P = A + i B: with A = (P + conj P(-k)) / 2 on the kx = 0
+  // plane and B = (P - conj P(-k)) / 2i on the Nyquist plane, and both planes
+  // sharing k_odd = (0, ky, kz), the result A' + i B' of the symbols i f0 k x
+  // and i fM k x equals i k x (a P + b conj P(-k)), a = (f0 + fM) / 2,
+  // b = (f0 - fM) / 2.  conj P(-k) comes through LDS, one component at a time.
+  if (pk_block) {
+    T fa[E], fb[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int kz = j + m * TPT;
+      const T f0 = packed ? zsym_factor<T, SYM>(tx, ty, tz, 0, ky, kz, coef) : T(0);
+      const T fm = packed ? zsym_factor<T, SYM>(tx, ty, tz, M, ky, kz, coef) : T(0);
+      fa[m] = T(0.5) * (f0 + fm);
+      fb[m] = T(0.5) * (f0 - fm);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) smem[(j + m * TPT) * COLS + col] = v[c][m];
+      __syncthreads();
+      if (packed) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int kz = j + m * TPT;
+          const C2<T> w = cconj(smem[((NZ - kz) & (NZ - 1)) * COLS + col]);
+          v[c][m] = {fa[m] * v[c][m].x + fb[m] * w.x, fa[m] * v[c][m].y + fb[m] * w.y};
+        }
+      }
+    }
+    __syncthreads();
   }
+
+  const T kxo = tx.kodd[kx], kyo = ty.kodd[ky];
+  T fxy;  // the x, y part of the multiplier (packed columns: already applied)
+  if constexpr (SYM == Z_CURL)
+    fxy = coef * tx.sm[kx] * ty.sm[ky];
+  else
+    fxy = tx.kk[kx] + ty.kk[ky];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = j + m * TPT;
-    const T kzo = tz.kodd[kz];
     T f;
     if constexpr (SYM == Z_CURL) {
       f = fxy * tz.sm[kz];
@@ -206,14 +306,8 @@ __global__ __launch_bounds__(kBlock) void zpass_kernel(C2<T>* __restrict__ main,
       f = k2 > T(0) ? coef / k2 : T(0);
       if constexpr (SYM == Z_PHI_SMOOTH) f = f * tx.sm[kx] * ty.sm[ky] * tz.sm[kz];
     }
-    const C2<T> a = v[0][m], b = v[1][m], d = v[2][m];
-    // k x v, then multiply by i f:  i (u + i w) f = (-w f, u f)
-    const C2<T> cx = {kyo * d.x - kzo * b.x, kyo * d.y - kzo * b.y};
-    const C2<T> cy = {kzo * a.x - kxo * d.x, kzo * a.y - kxo * d.y};
-    const C2<T> cz = {kxo * b.x - kyo * a.x, kxo * b.y - kyo * a.y};
-    v[0][m] = {-cx.y * f, cx.x * f};
-    v[1][m] = {-cy.y * f, cy.x * f};
-    v[2][m] = {-cz.y * f, cz.x * f};
+    if (packed) f = T(1);
+    zsym_apply(v[0][m], v[1][m], v[2][m], kxo, kyo, tz.kodd[kz], f);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_inverse<T, NZ, E>(v[c], j, lds, tz.tw, 1);
@@ -301,7 +395,6 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   // rows whose inverse transform is needed (elsewhere the input counts as 0)
   const bool inv_row = valid && ry >= P.r.iylo && ry < P.r.iyhi && rz >= P.r.izlo && rz < P.r.izhi;
   const size_t csm = (size_t)nrows * M;        // component stride, main spectrum
-  const size_t csn = (size_t)nrows;            // component stride, Nyquist column
   const size_t csr = (size_t)nrows * NX;       // component stride, real field
   const C2<T>* __restrict__ tw = P.ax.tw;      // exp(-2 pi i k / NX)
   const int c0 = NC == 3 ? 0 : (int)blockIdx.y;  // first component of this block
@@ -326,7 +419,9 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
       for (int m = 0; m < E; ++m)
         Xs[cc][m] = inv_row ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-      Xn[cc] = (inv_row && j == 0) ? P.nyq[c * csn + rr] : C2<T>{T(0), T(0)};
+      // the kx = 0 slot holds X[0] + i X[M] (both real)
+      Xn[cc] = {Xs[cc][0].y, T(0)};
+      if (j == 0) Xs[cc][0].y = T(0);
     }
   }
   uint8_t ch[2 * E];
@@ -604,10 +699,10 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
         const C2<T> s = Z[m] + pc, d = Z[m] - pc;
         const C2<T> ev = {T(0.5) * s.x, T(0.5) * s.y};         // E[k]
         const C2<T> od = {T(0.5) * d.y, T(-0.5) * d.x};        // O[k] = d / (2i)
-        const C2<T> X = ev + cmul(tw[k], od);
+        C2<T> X = ev + cmul(tw[k], od);
+        if (k == 0) X.y = Z[0].x - Z[0].y;                       // X[0] + i X[M]
         if (valid) P.main[c * csm + (size_t)rr * M + k] = X;
       }
-      if (j == 0 && valid) P.nyq[c * csn + rr] = C2<T>{Z[0].x - Z[0].y, T(0)};
       lds.sync();
     }
   }
@@ -712,13 +807,12 @@ static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) 
   const int M = p.nx / 2;
   const int nzr = p.r.zhi - p.r.zlo;
   if (nzr <= 0) return hipSuccess;  // nothing to transform
-  const int ncm = 3 * nzr * M, ncn = 3 * nzr;
-  const int nbm = (ncm + COLS - 1) / COLS, nbn = (ncn + COLS - 1) / COLS;
-  const dim3 grid(nbm + nbn), block(kBlock);
+  const int ncm = 3 * nzr * M;
+  const dim3 grid((ncm + COLS - 1) / COLS), block(kBlock);
   if (inv)
-    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, p.nyq, M, p.nz, p.r, nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw);
   else
-    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, p.nyq, M, p.nz, p.r, nbm, p.ay.tw);
+    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw);
   return hipGetLastError();
 }
 
@@ -740,20 +834,19 @@ template <typename T, int NZ>
 static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
   constexpr int COLS = kBlock / tpt_of<NZ, ez_max<T>()>();
   const int M = p.nx / 2;
-  const int nbm = (p.ny * M + COLS - 1) / COLS, nbn = (p.ny + COLS - 1) / COLS;
-  const dim3 grid(nbm + nbn), block(kBlock);
+  const dim3 grid((p.ny * M + COLS - 1) / COLS), block(kBlock);
   switch (sym) {
     case Z_CURL:
-      launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
-             p.az, coef, p.r);
+      launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
+             p.r);
       break;
     case Z_PHI:
-      launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax, p.ay,
-             p.az, coef, p.r);
+      launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
+             p.r);
       break;
     case Z_PHI_SMOOTH:
-      launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.nyq, p.ny, M, nbm, p.ax,
-             p.ay, p.az, coef, p.r);
+      launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay,
+             p.az, coef, p.r);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -48,7 +48,7 @@ struct scfft_ctx {
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_main, off_nyq, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
+  size_t off_main, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
       off_clamp, off_mom, off_adj, off_adjs, off_ode, off_probe, total;
   size_t wsize;  // element size
   bool has_mask = false, has_kappa = false, has_warm = false;
@@ -98,7 +98,6 @@ void layout(scfft_ctx* c) {
   const size_t M = (size_t)c->n[0] / 2;
   size_t o = 0;
   c->off_main = o;  o = align_up(o + 3 * (size_t)c->n[2] * c->n[1] * M * 2 * w);
-  c->off_nyq = o;   o = align_up(o + 3 * (size_t)c->n[2] * c->n[1] * 2 * w);
   c->off_warm = o;  o = align_up(o + 3 * nodes * w);
   c->off_chi = o;   o = align_up(o + nodes);
   c->off_kappa = o; o = align_up(o + nodes * w);
@@ -131,7 +130,6 @@ Plan<T> make_plan(scfft_ctx* c) {
   p.ny = c->n[1];
   p.nz = c->n[2];
   p.main = wsp<C2<T>>(c, c->off_main);
-  p.nyq = wsp<C2<T>>(c, c->off_nyq);
   size_t o = c->off_tab;
   AxisTab<T>* tabs[3] = {&p.ax, &p.ay, &p.az};
   for (int a = 0; a < 3; ++a) {
@@ -296,18 +294,18 @@ hipError_t prof_done(scfft_ctx* c, hipError_t launch_err, const KTime& t) {
 // mask-dependent terms use the node counts of Omega and Omega_out.
 template <typename T>
 double bytes_y(const scfft_ctx* c, const Plan<T>& p) {
-  const double cw = 2.0 * sizeof(T), kx = p.nx / 2 + 1;
+  const double cw = 2.0 * sizeof(T), kx = p.nx / 2;
   const double planes = 3.0 * (p.r.zhi - p.r.zlo);
   return planes * kx * cw * ((p.r.yhi_in - p.r.ylo_in) + (p.r.yhi_out - p.r.ylo_out));
 }
 template <typename T>
 double bytes_z(const scfft_ctx* c, const Plan<T>& p) {
-  const double cw = 2.0 * sizeof(T), col = 3.0 * p.ny * (p.nx / 2 + 1);
+  const double cw = 2.0 * sizeof(T), col = 3.0 * p.ny * (p.nx / 2);
   return col * cw * ((p.r.zhi - p.r.zlo) + (p.r.zhi_out - p.r.zlo_out));
 }
 template <typename T>
 double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
-  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2 + 1;
+  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2;
   const double rows = (double)(p.r.xyhi - p.r.xylo) * (p.r.xzhi - p.r.xzlo);
   const double inv_rows = (double)std::max(0, std::min(p.r.xyhi, p.r.iyhi) - std::max(p.r.xylo, p.r.iylo)) *
                           std::max(0, std::min(p.r.xzhi, p.r.izhi) - std::max(p.r.xzlo, p.r.izlo));
@@ -341,7 +339,7 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
 template <typename T>
 double bytes_xy(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   // per component plane: spectrum in/out, mask and real-field terms as in X
-  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2 + 1;
+  const double w = sizeof(T), cw = 2.0 * w, kx = p.nx / 2;
   const double planes = p.r.zhi - p.r.zlo;
   const double inv_planes = std::max(0, std::min(p.r.zhi, p.r.izhi) - std::max(p.r.zlo, p.r.izlo));
   const double spec = 3.0 * p.ny * kx * cw, mask = 3.0 * (double)p.nx * p.ny, node = 3.0 * w;

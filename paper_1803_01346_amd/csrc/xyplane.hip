@@ -9,7 +9,10 @@
 // a real field.  Global traffic is one read and one write of the plane.
 //
 // Plane layout in LDS: row y (fixed ky or y), entry k = kx (0..Nx/2), row
-// stride Nx/2 + 1 (odd, so the y columns spread over the banks).  Columns are
+// stride Nx/2 + 1 (odd, so the y columns spread over the banks).  In HBM the
+// kx = 0 column carries the Nyquist plane too (X[0] + i X[Nx/2] along x,
+// half-complex along y; the layout note of the column passes); the plane
+// unpacks it after loading and packs it before storing.  Columns are
 // transformed by Ny/8 lanes each and rows by Nx/8 lanes each, always inside
 // one wavefront, so every exchange needs only a wavefront barrier; block
 // barriers separate the column and row phases.
@@ -55,13 +58,13 @@ struct XYGeom {
   static_assert(TPTY <= 64 && TPTX <= 64, "a line must fit one wavefront");
 };
 
-// y transforms of all M + 1 columns of the plane, in place.
+// y transforms of the M columns kx < Nx/2 of the plane, in place.
 template <typename T, int NX, int NY, bool INV>
 __device__ __forceinline__ void plane_columns(C2<T>* plane, const C2<T>* __restrict__ tw) {
   using G = XYGeom<T, NX, NY>;
   const int t = threadIdx.x;
   const int g = t / G::TPTY, j = t % G::TPTY;
-  for (int col = g; col <= G::M; col += G::GY) {
+  for (int col = g; col < G::M; col += G::GY) {
     LdsLine<T, G::RS> lds{plane + col};
     C2<T> v[G::EY];
 #pragma unroll
@@ -129,9 +132,9 @@ __device__ __forceinline__ void row_r2c(C2<T>* row, int j, const C2<T>* __restri
     X[m] = ev + cmul(tw[k], od);
   }
   wave_sync();
+  if (j == 0) X[0].y = Z[0].x - Z[0].y;                  // X[0] + i X[M] in the kx = 0 slot
 #pragma unroll
   for (int m = 0; m < E; ++m) row[j + m * TPT] = X[m];
-  if (j == 0) row[M] = C2<T>{Z[0].x - Z[0].y, T(0)};
 }
 
 template <typename T, int NX, int NY, int OP>
@@ -152,8 +155,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   const int gx = t / TPT, j = t % TPT;
   const size_t csr = (size_t)nz * NY * NX;                    // component stride, real field
   const size_t rbase = (size_t)c * csr + (size_t)z * NY * NX;  // this plane, real field
-  const size_t sbase = ((size_t)c * nz + z) * NY * M;          // this plane, main spectrum
-  const size_t nbase = ((size_t)c * nz + z) * NY;              // this plane, Nyquist column
+  const size_t sbase = ((size_t)c * nz + z) * NY * M;          // this plane, spectrum
   const C2<T>* __restrict__ twx = P.ax.tw;
 
   // per-node inputs of the rows this thread transforms, fetched first; the
@@ -196,12 +198,27 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   if constexpr (HAS_INV) {
     if (inv_plane) {
       for (int i = t; i < NY * M; i += G::BLOCK) plane[(i / M) * RS + (i % M)] = P.main[sbase + i];
-      for (int y = t; y < NY; y += G::BLOCK) plane[y * RS + M] = P.nyq[nbase + y];
     } else {
       for (int i = t; i < NY * RS; i += G::BLOCK) plane[i] = C2<T>{T(0), T(0)};
     }
     __syncthreads();
-    if (inv_plane) plane_columns<T, NX, NY, true>(plane, P.ay.tw);  // uniform per block
+    if (inv_plane) {  // uniform per block
+      // kx = 0 column: P(ky) = A(ky) + i B(ky) from the half-complex layout
+      for (int y = 1 + t; 2 * y < NY; y += G::BLOCK) {
+        const C2<T> a = plane[y * RS], b = plane[(NY - y) * RS];
+        plane[y * RS] = C2<T>{a.x - b.y, a.y + b.x};
+        plane[(NY - y) * RS] = C2<T>{a.x + b.y, b.x - a.y};
+      }
+      __syncthreads();
+      plane_columns<T, NX, NY, true>(plane, P.ay.tw);
+      __syncthreads();
+      // X[0] + i X[M] of each row to the two real slots
+      for (int y = t; y < NY; y += G::BLOCK) {
+        const C2<T> pk = plane[y * RS];
+        plane[y * RS] = C2<T>{pk.x, T(0)};
+        plane[y * RS + M] = C2<T>{pk.y, T(0)};
+      }
+    }
     __syncthreads();
   }
 
@@ -246,8 +263,14 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
     __syncthreads();
     plane_columns<T, NX, NY, false>(plane, P.ay.tw);
     __syncthreads();
+    // kx = 0 column to the half-complex layout: A(ky) and B(ky)
+    for (int y = 1 + t; 2 * y < NY; y += G::BLOCK) {
+      const C2<T> p = plane[y * RS], q = plane[(NY - y) * RS];
+      plane[y * RS] = C2<T>{T(0.5) * (p.x + q.x), T(0.5) * (p.y - q.y)};
+      plane[(NY - y) * RS] = C2<T>{T(0.5) * (p.y + q.y), T(0.5) * (q.x - p.x)};
+    }
+    __syncthreads();
     for (int i = t; i < NY * M; i += G::BLOCK) P.main[sbase + i] = plane[(i / M) * RS + (i % M)];
-    for (int y = t; y < NY; y += G::BLOCK) P.nyq[nbase + y] = plane[y * RS + M];
   }
 }
 
