@@ -44,6 +44,7 @@ struct Plan {
   C2<T>* main;
   AxisTab<T> ax, ay, az;
   Ranges r;
+  const int* stop = nullptr;  // device flag: once nonzero, the passes of this plan return at once
   void full_ranges() {
     r = Ranges{0, nz, 0, ny, 0, ny, 0, nz, 0, ny, 0, nz, 0, ny, 0, nz};
   }
@@ -135,6 +136,18 @@ hipError_t launch_sum_partials(const double* partials, int n, int stride, int nc
 hipError_t launch_accum_partials(const double* partials, int n, int stride, int ncomp, double scale,
                                  double* out, hipStream_t s);
 hipError_t launch_zero_doubles(double* p, int n, hipStream_t s);
+// Device state of the stopping rule of iteration (5): flag (stop), iterations done, last mean
+// |delta|.  iter_decide sums the per-block |delta| sums of one X_UPDATE pass and sets the flag
+// when it >= min_iter and the mean over Omega_out nodes is below tol; it does nothing once
+// the flag is set.
+struct IterState {
+  int stop;
+  int iters;
+  double last;
+};
+hipError_t launch_iter_reset(IterState* st, hipStream_t s);
+hipError_t launch_iter_decide(const double* partials, int n, double n_out, double tol, int min_iter,
+                              IterState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream_t s);
 // out = y + c1 k1 + c2 k2 + c3 k3 (terms with null k skipped)

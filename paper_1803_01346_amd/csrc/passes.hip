@@ -118,7 +118,9 @@ __device__ __forceinline__ C2<T> dc_join(C2<T> S, C2<T> R, bool low) {
 // ---------------------------------------------------------------------------
 template <typename T, int NY, bool INV>
 __global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main, int M, int nz,
-                                                       Ranges R, const C2<T>* __restrict__ tw) {
+                                                       Ranges R, const C2<T>* __restrict__ tw,
+                                                       const int* __restrict__ stop) {
+  if (stop && *stop) return;  // uniform: the iteration has stopped
   constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
   constexpr int COLS = kBlock / TPT;
@@ -218,7 +220,8 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
 template <typename T, int NZ, int SYM>
 __global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
     C2<T>* __restrict__ main, int ny, int M, AxisTab<T> tx, AxisTab<T> ty, AxisTab<T> tz, T coef,
-    Ranges R) {
+    Ranges R, const int* __restrict__ stop) {
+  if (stop && *stop) return;  // uniform: the iteration has stopped
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = kBlock / TPT;
@@ -365,6 +368,7 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
 // (blockIdx.y), for the steps that act on each component alone.
 template <typename T, int NX, int OP, int NC>
 __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
+  if (P.stop && *P.stop) return;  // uniform: the iteration has stopped
   static_assert(NC == 3 || NC == 1, "components per block");
   static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT && OP != X_ADJ_LAST && OP != X_ADJ_LAW),
                 "needs all components");
@@ -810,9 +814,9 @@ static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) 
   const int ncm = 3 * nzr * M;
   const dim3 grid((ncm + COLS - 1) / COLS), block(kBlock);
   if (inv)
-    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw);
+    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop);
   else
-    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw);
+    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop);
   return hipGetLastError();
 }
 
@@ -838,15 +842,15 @@ static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KT
   switch (sym) {
     case Z_CURL:
       launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
-             p.r);
+             p.r, p.stop);
       break;
     case Z_PHI:
       launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
-             p.r);
+             p.r, p.stop);
       break;
     case Z_PHI_SMOOTH:
       launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay,
-             p.az, coef, p.r);
+             p.az, coef, p.r, p.stop);
       break;
     default: return hipErrorInvalidValue;
   }

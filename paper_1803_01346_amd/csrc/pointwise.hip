@@ -89,6 +89,43 @@ hipError_t launch_zero_doubles(double* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void iter_reset_kernel(IterState* st) {
+  if (threadIdx.x == 0) {
+    st->stop = 0;
+    st->iters = 0;
+    st->last = 0.0;
+  }
+}
+
+hipError_t launch_iter_reset(IterState* st, hipStream_t s) {
+  hipLaunchKernelGGL(iter_reset_kernel, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kRB) void iter_decide_kernel(const double* __restrict__ p, int n,
+                                                          double n_out, double tol, int min_iter,
+                                                          IterState* st) {
+  __shared__ double sh[kRB];
+  if (st->stop) return;  // uniform across the block
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kRB) acc += p[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const int it = st->iters + 1;
+    const double d = n_out > 0.0 ? r / n_out : 0.0;
+    st->iters = it;
+    st->last = d;
+    if (it >= min_iter && d < tol) st->stop = 1;
+  }
+}
+
+hipError_t launch_iter_decide(const double* partials, int n, double n_out, double tol, int min_iter,
+                              IterState* st, hipStream_t s) {
+  hipLaunchKernelGGL(iter_decide_kernel, dim3(1), dim3(kRB), 0, s, partials, n, n_out, tol, min_iter,
+                     st);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restrict__ p, int n,
                                                            double* __restrict__ out) {
   __shared__ double sh[kRB];

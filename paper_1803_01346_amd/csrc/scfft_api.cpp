@@ -21,6 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxDeltaSlots = 256;
+constexpr int kIterChunk = 4;  // adaptive iteration: launches between reads of the stop flag
 constexpr int kProbeChunk = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -505,63 +506,81 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   HIPCHK(c, run_x<T>(c, warm_start ? b.x_hin : p, X_HIN, a));
 
   // iteration (5)
-  const int max_it = fixed > 0 ? fixed : c->opts.max_iter;
-  double* deltas = wsp<double>(c, c->off_delta);
+  unsigned long long clamps_now = 0;
   int it = 0;
   bool converged = false;
   double last = 0.0;
-  for (;;) {
-    // jdot^i = C_s hdot^i, needed on Omega only
-    HIPCHK(c, run_y<T>(c, p, false));
-    HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));
-    HIPCHK(c, run_y<T>(c, b.y_inv, true));
-    HIPCHK(c, run_x<T>(c, b.x_box, X_MASK, a));              // jdot_in^i
-    // Phi[jdot_in^i] (Eq. 7) of a field that vanishes outside the box
-    HIPCHK(c, run_y<T>(c, b.y_fwd, false));
-    HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));
-    HIPCHK(c, run_y<T>(c, p, true));
-    const bool last_known = it + 1 >= max_it;
-    // with a fixed count the last update also stores the next warm start
-    a.warm_out = (last_known && fixed > 0) ? wsp<T>(c, c->off_warm) : nullptr;
-    HIPCHK(c, run_x<T>(c, p, last_known ? X_UPDATE_LAST : X_UPDATE, a));  // Eq. 5
-    if (fixed <= 0)
-      HIPCHK(c, launch_sum_partials(a.partials, xb, 1, 1, deltas + (it % kMaxDeltaSlots), s));
-    ++it;
-    if (fixed > 0) {
-      if (it >= fixed) {
-        converged = true;
+  // one iteration: jdot^i = C_s hdot^i (needed on Omega only), jdot_in^i, then
+  // Phi[jdot_in^i] (Eq. 7) of a field that vanishes outside the box, update (Eq. 5)
+  auto iteration = [&](const Plan<T>& pp, const BoxPlans<T>& bb, int op) -> hipError_t {
+    hipError_t e;
+    if ((e = run_y<T>(c, pp, false)) != hipSuccess) return e;
+    if ((e = run_z<T>(c, bb.z_store, Z_CURL, norm)) != hipSuccess) return e;
+    if ((e = run_y<T>(c, bb.y_inv, true)) != hipSuccess) return e;
+    if ((e = run_x<T>(c, bb.x_box, X_MASK, a)) != hipSuccess) return e;
+    if ((e = run_y<T>(c, bb.y_fwd, false)) != hipSuccess) return e;
+    if ((e = run_z<T>(c, bb.z_load, phi_sym, norm)) != hipSuccess) return e;
+    if ((e = run_y<T>(c, pp, true)) != hipSuccess) return e;
+    return run_x<T>(c, pp, op, a);
+  };
+  if (fixed > 0) {
+    for (it = 0; it < fixed; ++it) {
+      const bool lastit = it + 1 == fixed;
+      // the last update also stores the next warm start
+      a.warm_out = lastit ? wsp<T>(c, c->off_warm) : nullptr;
+      HIPCHK(c, iteration(p, b, lastit ? X_UPDATE_LAST : X_UPDATE));
+    }
+    converged = true;
+  } else {
+    // Stopping rule on the device: after each update a one-block kernel sums
+    // |delta| and sets a stop flag that makes every later pass of the loop
+    // return at once.  The host launches kIterChunk iterations at a time and
+    // reads the flag once per chunk instead of once per iteration.
+    IterState* ist = wsp<IterState>(c, c->off_delta);
+    HIPCHK(c, launch_iter_reset(ist, s));
+    Plan<T> pl = p;
+    pl.stop = &ist->stop;
+    const BoxPlans<T> bl = box_plans<T>(c, pl, c->opts.prune_box != 0);
+    const int max_it = std::max(1, c->opts.max_iter);
+    int launched = 0;
+    IterState hst{0, 0, 0.0};
+    while (launched < max_it) {
+      const int chunk = std::min(kIterChunk, max_it - launched);
+      for (int k = 0; k < chunk; ++k) {
+        HIPCHK(c, iteration(pl, bl, X_UPDATE));
+        HIPCHK(c, launch_iter_decide(a.partials, xb, (double)c->n_out, tol, c->opts.min_iter, ist, s));
+      }
+      launched += chunk;
+      if (launched >= max_it)  // warm start of the next call, read on Omega_out only
+        HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
+                                 hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(&hst, ist, sizeof hst, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(&clamps_now, wsp<unsigned long long>(c, c->off_clamp),
+                               sizeof clamps_now, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (hst.stop) {
+        if (launched < max_it)
+          HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
+                                   hipMemcpyDeviceToDevice, s));
         break;
       }
-      continue;
     }
-    double sum = 0.0;
-    HIPCHK(c, hipMemcpyAsync(&sum, deltas + ((it - 1) % kMaxDeltaSlots), sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    last = c->n_out > 0 ? sum / (double)c->n_out : 0.0;
-    if (it >= c->opts.min_iter && last < tol) {
-      converged = true;
-      break;
-    }
-    if (it >= max_it) break;
-    if (last_known) break;
+    it = hst.iters;
+    last = hst.last;
+    converged = hst.stop != 0;
   }
-  // warm start of the next call: hdot on Omega_out (only those nodes are read);
-  // with a fixed count the last update already stored it
-  if (fixed <= 0)
-    HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
-                             hipMemcpyDeviceToDevice, s));
   c->has_warm = true;
 
   scfft_status st = converged ? SCFFT_OK : SCFFT_WARN_NOT_CONVERGED;
   if (stats || fixed <= 0) {
-    unsigned long long cl = 0;
-    HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (fixed > 0) last = -1.0;  // not tracked with a fixed iteration count
-    const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
-    c->clamp_seen = (int64_t)cl;
+    if (fixed > 0) {  // the adaptive loop read the clamp counter with its last flag
+      HIPCHK(c, hipMemcpyAsync(&clamps_now, wsp<unsigned long long>(c, c->off_clamp), sizeof clamps_now,
+                               hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      last = -1.0;  // not tracked with a fixed iteration count
+    }
+    const int64_t new_clamps = (int64_t)clamps_now - c->clamp_seen;
+    c->clamp_seen = (int64_t)clamps_now;
     if (stats) {
       stats->iters = it;
       stats->converged = converged ? 1 : 0;
