@@ -208,6 +208,58 @@ def adjoint_leg(cfg, steps=100, every=50):
     return out
 
 
+def graph_leg(count=16, steps=10):
+    """Launch-bound regime: the 32^3 cube alone, and a batch of independent
+    instances of mixed size (32^3 and 64^3 boxes), integrated with fixed steps
+    (3 exterior iterations) either one after another with per-kernel launches
+    or with graph-replayed steps, one stream per instance, all in flight at
+    once.  Aggregate right-hand-side evaluations per second."""
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+
+    def plain(cfgs):
+        sims = [make_sim(c, scfft.F64, FIXED_ITER) for c in cfgs]
+        hs = [torch.from_numpy(workloads.synthetic_state(c, seed=i)).to("cuda") for i, c in enumerate(cfgs)]
+        o = scfft.default_ode_opts(fixed_steps=steps)
+        for s_, h in zip(sims, hs):
+            scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h.clone(), o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s_, h in zip(sims, hs):
+            scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h, o)
+        torch.cuda.synchronize()
+        return len(cfgs) * (1 + 3 * steps) / (time.perf_counter() - t)
+
+    def graphs(cfgs):
+        streams = [torch.cuda.Stream() for _ in cfgs]
+        sims = [scfft.Simulation(c, precision=scfft.F64, stream=st.cuda_stream,
+                                 rhs_opts=scfft.default_rhs_opts(fixed_iter=FIXED_ITER))
+                for c, st in zip(cfgs, streams)]
+        hs = [torch.from_numpy(workloads.synthetic_state(c, seed=i)).to("cuda") for i, c in enumerate(cfgs)]
+        wss = [scfft.device_buffer(scfft.scfft_graph_workspace_size(s_.ctx, steps)) for s_ in sims]
+        torch.cuda.synchronize()
+
+        def run(hh):
+            for s_, h, ws in zip(sims, hh, wss):
+                scfft.scfft_integrate_graph(s_.ctx, 0.0, 1e-3, steps, ws, h)
+            for s_ in sims:
+                scfft.scfft_integrate_wait(s_.ctx)
+        run([h.clone() for h in hs])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run(hs)
+        torch.cuda.synchronize()
+        return len(cfgs) * (1 + 3 * steps) / (time.perf_counter() - t)
+
+    cube = [workloads.config("cube32")]
+    batch = workloads.batch_instances(count)
+    out = dict(steps=steps, exterior_iters=FIXED_ITER, dtype="f64", unit="RHS evals/s",
+               cube32=dict(plain=round(plain(cube), 1), graph=round(graphs(cube), 1)),
+               batch=dict(instances=count, edges=sorted({c["n"][0] for c in batch}),
+                          plain=round(plain(batch), 1), graph_streams=round(graphs(batch), 1)))
+    return out
+
+
 def cpu_baseline(cfg, h_np):
     """The oracle's rhs_eval on the same 128^3 state with one exterior
     iteration (4 of the 8 spectral operator applications of a k = 3 call),
@@ -253,6 +305,7 @@ def main():
     ap.add_argument("--no-converged", action="store_true", help="skip the delta_it stopping-rule leg")
     ap.add_argument("--no-lens", action="store_true", help="skip the 256^3 FP32 lens leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -321,6 +374,7 @@ def main():
     converged = None if args.no_converged else converged_leg(cfg, h)
     lens = None if args.no_lens else lens256_leg()
     adj = None if args.no_adjoint else adjoint_leg(cfg)
+    gleg = None if args.no_graph else graph_leg()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -349,6 +403,7 @@ def main():
         "converged": converged,
         "lens256_f32": lens,
         "adjoint_cost": adj,
+        "graphs": gleg,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,

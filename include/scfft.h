@@ -264,6 +264,28 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
                              const scfft_ode_opts* o, scfft_observer obs, void* user,
                              scfft_ode_stats* stats);
 
+/* ---- graph-replayed fixed-step integration ----
+ *
+ * The fixed-step mode of scfft_integrate (equal steps (t1 - t0)/steps of the
+ * Bogacki-Shampine pair, Sec. 2 method of lines) with each step captured once
+ * as a HIP graph (two graphs: accepting a step swaps buffer roles) and
+ * replayed, so a whole integration is enqueued without host round trips.
+ * The applied-field rates at all stage times are tabulated on the host and
+ * read on the device by step number; the error norm of every step is kept
+ * on the device, and a non-finite one stops every later kernel.  Needs
+ * fixed_iter > 0; no observer.  Asynchronous on the context stream:
+ * scfft_integrate_graph enqueues and returns, scfft_integrate_wait
+ * synchronises, writes the last accepted state to h and fills the stats
+ * (SCFFT_ERR_NAN after a non-finite error norm).  In between, the context
+ * accepts no other call (SCFFT_ERR_STATE), h and the graph workspace must
+ * stay allocated, and contexts on different streams run concurrently (the
+ * batched use).  graph_ws: device buffer of scfft_graph_workspace_size bytes,
+ * 256-byte aligned, owned by the caller. */
+scfft_status scfft_graph_workspace_size(const scfft_ctx* ctx, int32_t steps, size_t* bytes);
+scfft_status scfft_integrate_graph(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
+                                   void* graph_ws, size_t graph_bytes, void* h_dev);
+scfft_status scfft_integrate_wait(scfft_ctx* ctx, scfft_ode_stats* stats);
+
 /* ---- reverse mode (gradients) ----
  *
  * Differentiating the discrete map is an extension of the paper (Sec. 2

@@ -105,6 +105,12 @@ struct XArgs {
   double* mom_partials;  // X_LAW: if set, 6 doubles per block: sums of r x j over all
                          // nodes (3) and over Omega nodes (3), for the moment readout
   T* kappa_bar;          // X_ADJ_LAW: accumulated d/dkappa (scalar field) or nullptr
+  // X_UPDATE*, XY_UPDATE*: if hedot_tab is set, the applied-field rate is
+  // hedot_tab[9 * (*hedot_step) + 3 * hedot_stage + c] instead of hedot[c]
+  // (graph replays of a step: one row of three stage rates per step)
+  const double* hedot_tab;
+  const int* hedot_step;
+  int hedot_stage;
   int warm_used;         // X_ADJ_LAST: the forward call started from a warm start
   double pos0[3];        // coordinate of node 0 along each axis (moment)
   double step[3];        // node spacing (moment)
@@ -146,6 +152,18 @@ struct IterState {
   double last;
 };
 hipError_t launch_iter_reset(IterState* st, hipStream_t s);
+// Device state of a graph-replayed fixed-step integration: stop flag (set at
+// the first step whose error norm is not finite; every later kernel of the
+// replays returns at once), accepted steps, first bad step (-1: none).
+struct GraphState {
+  int stop;
+  int step;
+  int bad;
+  int pad;
+};
+hipError_t launch_graph_reset(GraphState* g, hipStream_t s);
+// records err[0] as hist[step]; step += 1 if finite, else sets stop and bad
+hipError_t launch_graph_step_end(const double* err, GraphState* g, double* hist, hipStream_t s);
 hipError_t launch_iter_decide(const double* partials, int n, double n_out, double tol, int min_iter,
                               IterState* st, hipStream_t s);
 template <typename T>
@@ -153,17 +171,18 @@ hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream
 // out = y + c1 k1 + c2 k2 + c3 k3 (terms with null k skipped)
 template <typename T>
 hipError_t launch_combo(T* out, const T* y, const T* k1, double c1, const T* k2, double c2,
-                        const T* k3, double c3, size_t n, hipStream_t s);
+                        const T* k3, double c3, size_t n, hipStream_t s, const int* stop = nullptr);
 // per-block max of |dt (e1 k1 + e2 k2 + e3 k3 + e4 k4)| / max(|y|, |y1|, thr); NaN -> inf
 template <typename T>
 hipError_t launch_errnorm(const T* y, const T* y1, const T* k1, const T* k2, const T* k3,
                           const T* k4, double dt, double thr, size_t n, double* partials,
-                          int nblocks, hipStream_t s);
+                          int nblocks, hipStream_t s, const int* stop = nullptr);
 // per-block max of |a_i| / max(|y_i|, thr)
 template <typename T>
 hipError_t launch_ratio_max(const T* a, const T* y, double thr, size_t n, double* partials,
                             int nblocks, hipStream_t s);
-hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s);
+hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s,
+                               const int* stop = nullptr);
 // per-block sums of |h| and count over region nodes
 template <typename T>
 hipError_t launch_region_abs(const T* h, const uint8_t* region, size_t nodes, double* partials,

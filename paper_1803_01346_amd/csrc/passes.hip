@@ -406,6 +406,16 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 
   T a[NC][2 * E];
   unsigned clamps = 0;
+  T hdv[NC];  // applied-field rate of the exterior update
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) hdv[cc] = A.hedot[c0 + cc];
+  if constexpr (OP == X_UPDATE || OP == X_UPDATE_LAST) {
+    if (A.hedot_tab) {
+      const double* q = A.hedot_tab + 9 * (size_t)(*A.hedot_step) + 3 * A.hedot_stage;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) hdv[cc] = (T)q[c0 + cc];
+    }
+  }
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
   const int y = rr % P.ny;
   const int z = rr / P.ny;
@@ -544,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
           const T old = aux[cc][e];
-          const T nw = in ? old : A.hedot[c0 + cc] + a[cc][e];
+          const T nw = in ? old : hdv[cc] + a[cc][e];
           const T dd = nw - old;
           d2 += dd * dd;
           a[cc][e] = nw;

@@ -97,6 +97,37 @@ __global__ void iter_reset_kernel(IterState* st) {
   }
 }
 
+__global__ void graph_reset_kernel(GraphState* g) {
+  if (threadIdx.x == 0) {
+    g->stop = 0;
+    g->step = 0;
+    g->bad = -1;
+  }
+}
+
+hipError_t launch_graph_reset(GraphState* g, hipStream_t s) {
+  hipLaunchKernelGGL(graph_reset_kernel, dim3(1), dim3(64), 0, s, g);
+  return hipGetLastError();
+}
+
+__global__ void graph_step_end_kernel(const double* __restrict__ err, GraphState* g,
+                                      double* __restrict__ hist) {
+  if (threadIdx.x != 0 || g->stop) return;
+  const double e = *err;
+  hist[g->step] = e;
+  if (!isfinite(e)) {
+    g->stop = 1;
+    g->bad = g->step;
+  } else {
+    g->step += 1;
+  }
+}
+
+hipError_t launch_graph_step_end(const double* err, GraphState* g, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(graph_step_end_kernel, dim3(1), dim3(64), 0, s, err, g, hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_iter_reset(IterState* st, hipStream_t s) {
   hipLaunchKernelGGL(iter_reset_kernel, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
@@ -127,16 +158,19 @@ hipError_t launch_iter_decide(const double* partials, int n, double n_out, doubl
 }
 
 __global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restrict__ p, int n,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out,
+                                                           const int* __restrict__ stop) {
   __shared__ double sh[kRB];
+  if (stop && *stop) return;  // uniform
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += kRB) acc = fmax(acc, p[i]);
   const double r = block_max(acc, sh);
   if (threadIdx.x == 0) out[0] = r;
 }
 
-hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, out);
+hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s,
+                               const int* stop) {
+  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, out, stop);
   return hipGetLastError();
 }
 
@@ -164,7 +198,9 @@ template <typename T>
 __global__ __launch_bounds__(kRB) void combo_kernel(T* __restrict__ out, const T* __restrict__ y,
                                                     const T* __restrict__ k1, T c1,
                                                     const T* __restrict__ k2, T c2,
-                                                    const T* __restrict__ k3, T c3, size_t n) {
+                                                    const T* __restrict__ k3, T c3, size_t n,
+                                                    const int* __restrict__ stop) {
+  if (stop && *stop) return;  // uniform
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
     T v = y ? y[i] : T(0);
     if (k1) v += c1 * k1[i];
@@ -176,11 +212,11 @@ __global__ __launch_bounds__(kRB) void combo_kernel(T* __restrict__ out, const T
 
 template <typename T>
 hipError_t launch_combo(T* out, const T* y, const T* k1, double c1, const T* k2, double c2,
-                        const T* k3, double c3, size_t n, hipStream_t s) {
+                        const T* k3, double c3, size_t n, hipStream_t s, const int* stop) {
   const size_t want = (n + kRB - 1) / kRB;
   const int nb = (int)(want < 8192 ? want : 8192);
   hipLaunchKernelGGL((combo_kernel<T>), dim3(nb), dim3(kRB), 0, s, out, y, k1, (T)c1, k2, (T)c2,
-                     k3, (T)c3, n);
+                     k3, (T)c3, n, stop);
   return hipGetLastError();
 }
 
@@ -193,8 +229,10 @@ __global__ __launch_bounds__(kRB) void errnorm_kernel(const T* __restrict__ y,
                                                       const T* __restrict__ k3,
                                                       const T* __restrict__ k4, double dt,
                                                       double thr, size_t n,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials,
+                                                      const int* __restrict__ stop) {
   __shared__ double sh[kRB];
+  if (stop && *stop) return;  // uniform
   const double e1 = -5.0 / 72.0, e2 = 1.0 / 12.0, e3 = 1.0 / 9.0, e4 = -1.0 / 8.0;
   double acc = 0.0;
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
@@ -212,9 +250,9 @@ __global__ __launch_bounds__(kRB) void errnorm_kernel(const T* __restrict__ y,
 template <typename T>
 hipError_t launch_errnorm(const T* y, const T* y1, const T* k1, const T* k2, const T* k3,
                           const T* k4, double dt, double thr, size_t n, double* partials,
-                          int nblocks, hipStream_t s) {
+                          int nblocks, hipStream_t s, const int* stop) {
   hipLaunchKernelGGL((errnorm_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, y, y1, k1, k2, k3, k4,
-                     dt, thr, n, partials);
+                     dt, thr, n, partials, stop);
   return hipGetLastError();
 }
 
@@ -334,10 +372,10 @@ hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t n
 #define SCFFT_INST(T)                                                                          \
   template hipError_t launch_fill_uniform<T>(T*, size_t, const double[3], hipStream_t);        \
   template hipError_t launch_combo<T>(T*, const T*, const T*, double, const T*, double,        \
-                                      const T*, double, size_t, hipStream_t);                  \
+                                      const T*, double, size_t, hipStream_t, const int*);      \
   template hipError_t launch_errnorm<T>(const T*, const T*, const T*, const T*, const T*,      \
                                         const T*, double, double, size_t, double*, int,        \
-                                        hipStream_t);                                           \
+                                        hipStream_t, const int*);                               \
   template hipError_t launch_region_abs<T>(const T*, const uint8_t*, size_t, double*, int,     \
                                            hipStream_t);                                        \
   template hipError_t launch_probe<T>(const T*, int, int, int, const double*, int, double,     \

@@ -62,6 +62,21 @@ struct scfft_ctx {
   const void* mom_state = nullptr;
   const void* obs_state = nullptr;  // state shown to the running observer, else null
 
+  // graph-replayed fixed-step integration (scfft_integrate_graph): while a
+  // step is captured, passes take their stop flag and applied-field rates
+  // from these device locations
+  const int* graph_stop = nullptr;
+  const double* g_hedot_tab = nullptr;
+  const int* g_hedot_step = nullptr;
+  int g_hedot_stage = 0;
+  bool graph_busy = false;          // an integration is enqueued; scfft_integrate_wait ends it
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  std::vector<double> graph_hedot;  // host copy of the rate table (alive until the wait)
+  char* graph_ws = nullptr;
+  int graph_steps = 0;
+  double graph_t0 = 0.0, graph_dt = 0.0;
+  void* graph_h = nullptr;
+
   // optional per-kernel timing with HIP events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;          // pairs: 2i (start), 2i+1 (stop)
@@ -142,6 +157,7 @@ Plan<T> make_plan(scfft_ctx* c) {
     o = align_up(o + N * 5 * sizeof(T));
   }
   p.full_ranges();
+  p.stop = c->graph_stop;
   return p;
 }
 
@@ -222,6 +238,10 @@ std::vector<char> build_tables(const scfft_ctx* c) {
 }
 
 bool ready(scfft_ctx* c, bool need_mask, scfft_status* st) {
+  if (c->graph_busy) {
+    *st = fail(c, SCFFT_ERR_STATE, "a graph integration is enqueued: call scfft_integrate_wait first");
+    return false;
+  }
   if (!c->ws) {
     *st = fail(c, SCFFT_ERR_WORKSPACE, "no workspace attached");
     return false;
@@ -244,6 +264,9 @@ XArgs<T> base_args(scfft_ctx* c) {
   a.kappa = c->has_kappa ? wsp<T>(c, c->off_kappa) : nullptr;
   a.partials = wsp<double>(c, c->off_part);
   a.clamps = wsp<unsigned long long>(c, c->off_clamp);
+  a.hedot_tab = c->g_hedot_tab;
+  a.hedot_step = c->g_hedot_step;
+  a.hedot_stage = c->g_hedot_stage;
   a.npow = (T)c->mat.n_power;
   a.rho_out = (T)c->mat.rho_out;
   a.expmax = sizeof(T) == 4 ? (T)80.0 : (T)700.0;
@@ -1036,6 +1059,179 @@ scfft_status integrate_adjoint_impl(scfft_ctx* c, double t0, double t1, int step
   return SCFFT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// graph-replayed fixed-step integration
+// ---------------------------------------------------------------------------
+// Caller workspace: the device state of the replays, the error norm of each
+// step and the table of applied-field rates (3 stages x 3 components per step).
+struct GraphLayout {
+  size_t off_state = 0, off_err = 0, off_hist = 0, off_tab = 0, total = 0;
+};
+
+GraphLayout graph_layout(int steps) {
+  GraphLayout L;
+  size_t o = 0;
+  L.off_state = o;  o = align_up(o + sizeof(GraphState));
+  L.off_err = o;    o = align_up(o + sizeof(double));
+  L.off_hist = o;   o = align_up(o + (size_t)steps * sizeof(double));
+  L.off_tab = o;    o = align_up(o + (size_t)steps * 9 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+// One Bogacki-Shampine step as launched while a graph is captured: the
+// three right-hand sides read their applied-field rate from row *step of the
+// table, and every kernel returns at once after the stop flag is set.
+template <typename T>
+scfft_status graph_step(scfft_ctx* c, T* const r[6], double dt, GraphState* gs, double* err,
+                        double* hist) {
+  const double thr = 1e-6 / 2e-4;  // atol / rtol of the default controller
+  scfft_status st;
+  c->g_hedot_stage = 0;
+  if ((st = rhs_impl<T>(c, 0.0, r[B_Y], r[B_K2], nullptr, r[B_K1], 0.5 * dt)) < 0) return st;
+  c->g_hedot_stage = 1;
+  if ((st = rhs_impl<T>(c, 0.0, r[B_Y], r[B_K3], nullptr, r[B_K2], 0.75 * dt)) < 0) return st;
+  HIPCHK(c, launch_combo<T>(r[B_Y1], r[B_Y], r[B_K1], dt * (2.0 / 9.0), r[B_K2], dt * (1.0 / 3.0),
+                            r[B_K3], dt * (4.0 / 9.0), 3 * c->nodes, c->stream, &gs->stop));
+  c->g_hedot_stage = 2;
+  if ((st = rhs_impl<T>(c, 0.0, r[B_Y1], r[B_K4], nullptr)) < 0) return st;
+  double* part = wsp<double>(c, c->off_part);
+  HIPCHK(c, launch_errnorm<T>(r[B_Y], r[B_Y1], r[B_K1], r[B_K2], r[B_K3], r[B_K4], dt, thr,
+                              3 * c->nodes, part, kReduceBlocks, c->stream, &gs->stop));
+  HIPCHK(c, launch_max_partials(part, kReduceBlocks, err, c->stream, &gs->stop));
+  HIPCHK(c, launch_graph_step_end(err, gs, hist, c->stream));
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* h, char* gws) {
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  T* buf[6];
+  for (int k = 0; k < 6; ++k) buf[k] = wsp<T>(c, c->off_ode + (size_t)k * fb);
+  const double dt = (t1 - t0) / steps;
+  const GraphLayout L = graph_layout(steps);
+  GraphState* gs = reinterpret_cast<GraphState*>(gws + L.off_state);
+  double* err = reinterpret_cast<double*>(gws + L.off_err);
+  double* hist = reinterpret_cast<double*>(gws + L.off_hist);
+  double* tab = reinterpret_cast<double*>(gws + L.off_tab);
+  // applied-field rates at the stage times of every step, evaluated on the host
+  c->graph_hedot.assign((size_t)steps * 9, 0.0);
+  const double frac[3] = {0.5, 0.75, 1.0};
+  for (int s = 0; s < steps; ++s) {
+    const double ts = t0 + s * dt;
+    for (int q = 0; q < 3; ++q) {
+      double he[3], hd[3];
+      c->drive.eval(ts + frac[q] * dt, he, hd);
+      for (int d = 0; d < 3; ++d) c->graph_hedot[(size_t)s * 9 + q * 3 + d] = hd[d];
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(tab, c->graph_hedot.data(), c->graph_hedot.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_graph_reset(gs, c->stream));
+  // initial state and its rate (plain launches)
+  HIPCHK(c, hipMemcpyAsync(buf[B_Y], h, fb, hipMemcpyDeviceToDevice, c->stream));
+  scfft_status st = rhs_impl<T>(c, t0, buf[B_Y], buf[B_K1], nullptr);
+  if (st < 0) return st;
+  // capture one step for each parity of the buffer roles (accepting a step swaps Y/Y1, K1/K4)
+  hipStream_t cs = nullptr;
+  HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const hipStream_t saved = c->stream;
+  const bool saved_prof = c->prof;
+  c->stream = cs;
+  c->prof = false;
+  c->graph_stop = &gs->stop;
+  c->g_hedot_tab = tab;
+  c->g_hedot_step = &gs->step;
+  T* r[6];
+  for (int k = 0; k < 6; ++k) r[k] = buf[k];
+  st = SCFFT_OK;
+  for (int par = 0; par < 2 && st == SCFFT_OK; ++par) {
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+      break;
+    }
+    const scfft_status sst = graph_step<T>(c, r, dt, gs, err, hist);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (sst < 0) {
+      st = sst;
+    } else if (e != hipSuccess) {
+      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    } else {
+      e = hipGraphInstantiate(&c->graph_exec[par], g, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(c, SCFFT_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (g) (void)hipGraphDestroy(g);
+    std::swap(r[B_Y], r[B_Y1]);
+    std::swap(r[B_K1], r[B_K4]);
+  }
+  c->stream = saved;
+  c->prof = saved_prof;
+  c->graph_stop = nullptr;
+  c->g_hedot_tab = nullptr;
+  c->g_hedot_step = nullptr;
+  c->g_hedot_stage = 0;
+  (void)hipStreamDestroy(cs);
+  if (st == SCFFT_OK) {
+    for (int s = 0; s < steps; ++s) {
+      const hipError_t e = hipGraphLaunch(c->graph_exec[s & 1], c->stream);
+      if (e != hipSuccess) {
+        st = fail(c, SCFFT_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  if (st != SCFFT_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& x : c->graph_exec)
+      if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+    return st;
+  }
+  c->graph_busy = true;
+  c->graph_ws = gws;
+  c->graph_steps = steps;
+  c->graph_t0 = t0;
+  c->graph_dt = dt;
+  c->graph_h = h;
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
+  const GraphLayout L = graph_layout(c->graph_steps);
+  GraphState hs{0, 0, -1, 0};
+  hipError_t e = hipMemcpyAsync(&hs, c->graph_ws + L.off_state, sizeof hs, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  for (auto& x : c->graph_exec)
+    if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+  c->graph_busy = false;
+  if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "graph integration: %s", hipGetErrorString(e));
+  // the last accepted state is in the Y buffer of the parity of the next (or failed) step
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  const int next = hs.bad >= 0 ? hs.bad : hs.step;
+  const int slot = (next & 1) ? B_Y1 : B_Y;
+  HIPCHK(c, hipMemcpyAsync(c->graph_h, wsp<char>(c, c->off_ode + (size_t)slot * fb), fb,
+                           hipMemcpyDeviceToDevice, c->stream));
+  double err_last = 0.0;
+  const int last = hs.bad >= 0 ? hs.bad : hs.step - 1;
+  if (last >= 0)
+    HIPCHK(c, hipMemcpyAsync(&err_last, c->graph_ws + L.off_hist + (size_t)last * sizeof(double),
+                             sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->accepted = hs.step;
+    stats->rhs_calls = 1 + 3 * (int64_t)(hs.step + (hs.bad >= 0 ? 1 : 0));
+    stats->iters_total = stats->rhs_calls * c->opts.fixed_iter;
+    stats->t_s = (hs.step == c->graph_steps ? c->graph_t0 + c->graph_steps * c->graph_dt
+                                            : c->graph_t0 + hs.step * c->graph_dt) * c->u.t0;
+    stats->dt_last_s = c->graph_dt * c->u.t0;
+    stats->err_last = err_last;
+  }
+  return hs.bad >= 0 ? fail(c, SCFFT_ERR_NAN, "non-finite error norm at step %d", hs.bad) : SCFFT_OK;
+}
+
 template <typename T>
 scfft_status region_impl(scfft_ctx* c, const T* h, const uint8_t* region, double* b) {
   double* part = wsp<double>(c, c->off_part);
@@ -1228,6 +1424,9 @@ scfft_status scfft_create(scfft_ctx** out, const scfft_grid* g, const scfft_mate
 
 void scfft_destroy(scfft_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->graph_busy) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& x : ctx->graph_exec)
+    if (x) (void)hipGraphExecDestroy(x);
   for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -1432,6 +1631,36 @@ scfft_status scfft_integrate_adjoint(scfft_ctx* ctx, double t0_s, double t1_s, i
              : integrate_adjoint_impl<float>(ctx, t0, t1, steps, every, (char*)adj_ws, (float*)hT_dev,
                                              (const float*)h0_dev, (const float*)hT_bar_dev,
                                              (float*)h0_bar_dev, (float*)kappa_bar_dev, n_bar, p_bar);
+}
+
+scfft_status scfft_graph_workspace_size(const scfft_ctx* ctx, int32_t steps, size_t* bytes) {
+  if (!ctx || !bytes || steps <= 0) return SCFFT_ERR_ARG;
+  *bytes = graph_layout(steps).total;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_integrate_graph(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
+                                   void* graph_ws, size_t graph_bytes, void* h_dev) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  if (!h_dev || steps <= 0 || !(t1_s > t0_s)) return fail(ctx, SCFFT_ERR_ARG, "invalid integrate arguments");
+  if (ctx->opts.fixed_iter <= 0)
+    return fail(ctx, SCFFT_ERR_ARG, "graph replay needs a fixed iteration count (fixed_iter > 0)");
+  const size_t need = graph_layout(steps).total;
+  if (!graph_ws || graph_bytes < need || (reinterpret_cast<uintptr_t>(graph_ws) & 255))
+    return fail(ctx, SCFFT_ERR_WORKSPACE, "graph workspace: %zu bytes at a 256-byte boundary needed", need);
+  const double t0 = t0_s / ctx->u.t0, t1 = t1_s / ctx->u.t0;
+  return ctx->prec == SCFFT_F64
+             ? graph_begin_impl<double>(ctx, t0, t1, steps, (double*)h_dev, (char*)graph_ws)
+             : graph_begin_impl<float>(ctx, t0, t1, steps, (float*)h_dev, (char*)graph_ws);
+}
+
+scfft_status scfft_integrate_wait(scfft_ctx* ctx, scfft_ode_stats* stats) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (!ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "no graph integration is enqueued");
+  return ctx->prec == SCFFT_F64 ? graph_wait_impl<double>(ctx, stats) : graph_wait_impl<float>(ctx, stats);
 }
 
 scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev) {

@@ -146,6 +146,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   constexpr bool NEED_CHI = OP == XY_HIN || OP == XY_MASK || OP == XY_UPDATE || OP == XY_UPDATE_LAST;
   constexpr bool NEED_AUX = OP == XY_FWD || OP == XY_HIN || OP == XY_UPDATE;
   __shared__ C2<T> plane[NY * RS];
+  if (P.stop && *P.stop) return;  // uniform: a graph replay has stopped
 
   const int nz = P.nz;
   const int nzr = P.r.zhi - P.r.zlo;                  // planes of this launch
@@ -157,6 +158,10 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   const size_t rbase = (size_t)c * csr + (size_t)z * NY * NX;  // this plane, real field
   const size_t sbase = ((size_t)c * nz + z) * NY * M;          // this plane, spectrum
   const C2<T>* __restrict__ twx = P.ax.tw;
+  T hdc = A.hedot[c];  // applied-field rate of this component (exterior update)
+  if constexpr (OP == XY_UPDATE || OP == XY_UPDATE_LAST) {
+    if (A.hedot_tab) hdc = (T)A.hedot_tab[9 * (size_t)(*A.hedot_step) + 3 * A.hedot_stage + c];
+  }
 
   // per-node inputs of the rows this thread transforms, fetched first; the
   // mask of row round r is bit e of chm[r]
@@ -244,10 +249,10 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
         } else if constexpr (OP == XY_MASK) {
           if (!in) a[e] = T(0);
         } else if constexpr (OP == XY_UPDATE) {
-          a[e] = in ? aux[r][e] : A.hedot[c] + a[e];
+          a[e] = in ? aux[r][e] : hdc + a[e];
         } else if constexpr (OP == XY_UPDATE_LAST) {
           if (!in) {
-            const T v = A.hedot[c] + a[e];
+            const T v = hdc + a[e];
             A.out[idx] = v;
             if (A.warm_out) A.warm_out[idx] = v;
           }

@@ -110,6 +110,9 @@ _SIGS = {
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
     "scfft_step_moment": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double)]),
+    "scfft_graph_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scfft_integrate_graph": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, C.c_size_t, _P]),
+    "scfft_integrate_wait": (C.c_int, [_P, C.POINTER(OdeStats)]),
     "scfft_rhs_vjp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)]),
     "scfft_adjoint_workspace_size": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
@@ -357,6 +360,30 @@ def scfft_step_moment(ctx, omega_only=0):
     m = (C.c_double * 3)()
     _check(load().scfft_step_moment(ctx, int(omega_only), m), ctx)
     return np.array(m[:])
+
+
+def scfft_graph_workspace_size(ctx, steps):
+    n = C.c_size_t()
+    _check(load().scfft_graph_workspace_size(ctx, int(steps), C.byref(n)), ctx)
+    return n.value
+
+
+def scfft_integrate_graph(ctx, t0_s, t1_s, steps, graph_ws, h):
+    nbytes = graph_ws.numel() * graph_ws.element_size()
+    return _check(load().scfft_integrate_graph(ctx, float(t0_s), float(t1_s), int(steps), _ptr(graph_ws),
+                                               nbytes, _ptr(h)), ctx)
+
+
+def scfft_integrate_wait(ctx, stats=None):
+    return _check(load().scfft_integrate_wait(ctx, C.byref(stats) if stats is not None else None), ctx)
+
+
+def device_buffer(nbytes):
+    """A 256-byte aligned uint8 device tensor of nbytes (workspaces)."""
+    import torch
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + nbytes]
 
 
 def scfft_rhs_vjp(ctx, h, warm_used, lam, mu, hbar, wbar=None, kappa_bar=None):

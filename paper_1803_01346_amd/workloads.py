@@ -97,6 +97,26 @@ def config(name):
     return CONFIGS[name]
 
 
+def batch_instances(count=16, seed=4, edges=(32, 64)):
+    """Independent instances of mixed size for batched runs: grid edge drawn
+    from `edges`, body (cube, solid cylinder or cup, half the box wide) with
+    l = its half size, n ~ U[10, 100], log10 jc ~ U[7, 9], a ramp to
+    U[0.01, 0.2] T along a random direction.  Returns configuration dicts."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        edge = int(rng.choice(edges))
+        kind = int(rng.integers(3))
+        shapes = [shape_cube(1.0), shape_cylinder(1.0, 2.0), shape_cup(1.0, 0.8, 2.0, 0.2)][kind]
+        d = rng.normal(size=3)
+        out.append(dict(n=(edge, edge, edge), l_m=5e-3, half_width=(2.0, 2.0, 2.0), shapes=shapes,
+                        n_power=float(rng.uniform(10.0, 100.0)), jc=float(10.0 ** rng.uniform(7.0, 9.0)),
+                        e0=1e-4, rho_out=20.0,
+                        drive=dict(kind="ramp_hold", direction=tuple(float(v) for v in d / np.linalg.norm(d)),
+                                   amp_T=float(rng.uniform(0.01, 0.2)), t_ramp_s=1.0)))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Smooth random fields
 # --------------------------------------------------------------------------

@@ -1,0 +1,120 @@
+"""Graph-replayed fixed-step integration: the same trajectory as the plain
+fixed-step integrator (which is pinned to the oracle), the non-finite stop,
+the busy-context rule, and independent contexts on separate streams (the
+batched use) giving what each gives alone."""
+import numpy as np
+import pytest
+
+from gpu_case import oracle_problem, rel_max, sim, small_cfg, state, to_dev
+from paper_1803_01346_amd import scfft, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CUBE32 = dict(workloads.config("cube32"), n_power=20.0)
+SQZ = small_cfg((32, 32, 16), (2.0, 2.0, 1.0), workloads.shape_cylinder(0.8, 1.2))
+NONCUBIC = small_cfg((16, 32, 64), (1.5, 2.0, 3.0), workloads.shape_cup(1.0, 0.6, 3.0, 0.4, axis=1))
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    scfft.load()
+
+
+def _graph_run(s, h, t1_s, steps):
+    ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(s.ctx, steps))
+    st = scfft.OdeStats()
+    scfft.scfft_integrate_graph(s.ctx, 0.0, t1_s, steps, ws, h)
+    scfft.scfft_integrate_wait(s.ctx, st)
+    return st
+
+
+@pytest.mark.parametrize("prec,fuse", [(scfft.F64, 0), (scfft.F64, 2), (scfft.F32, 1)])
+def test_graph_matches_plain_fixed_steps(prec, fuse):
+    cfg = CUBE32
+    _, u = oracle_problem(cfg)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    h0 = to_dev(torch, state(cfg, seed=1, bg=(0.0, 0.01, 0.02)), dt)
+    t1_s, steps = 0.02, 7
+    a = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=fuse)
+    ha = h0.clone()
+    sa = scfft.OdeStats()
+    scfft.scfft_integrate(a.ctx, 0.0, t1_s, ha, scfft.default_ode_opts(fixed_steps=steps), stats=sa)
+    b = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=fuse)
+    hb = h0.clone()
+    sb = _graph_run(b, hb, t1_s, steps)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == scfft.F64 else 1e-5
+    assert rel_max(hb.double().cpu().numpy(), ha.double().cpu().numpy()) < tol
+    assert sb.accepted == steps and sb.rhs_calls == sa.rhs_calls
+    assert abs(sb.t_s - sa.t_s) <= 1e-12 * sa.t_s
+    assert abs(sb.err_last - sa.err_last) <= 1e-6 * abs(sa.err_last)
+    # the context is usable again, and a second graph run continues the same way
+    scfft.scfft_rhs_eval(b.ctx, 0.0, hb, b.empty_field())
+
+
+def test_graph_stops_at_non_finite_error():
+    cfg = SQZ
+    s = sim(cfg, fixed_iter=2)
+    h0 = to_dev(torch, state(cfg, seed=2), torch.float64)
+    h0[1, 3, 5, 7] = float("nan")
+    h = h0.clone()
+    ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(s.ctx, 5))
+    scfft.scfft_integrate_graph(s.ctx, 0.0, 0.01, 5, ws, h)
+    with pytest.raises(scfft.ScfftError):              # busy until the wait
+        scfft.scfft_rhs_eval(s.ctx, 0.0, h0, s.empty_field())
+    st = scfft.OdeStats()
+    with pytest.raises(scfft.ScfftError) as ei:
+        scfft.scfft_integrate_wait(s.ctx, st)
+    assert ei.value.status == scfft.ERR_NAN
+    assert st.accepted == 0
+    same = (h == h0) | (torch.isnan(h) & torch.isnan(h0))
+    assert bool(same.all())                               # the last accepted state: the start
+    with pytest.raises(scfft.ScfftError):                 # nothing left to wait for
+        scfft.scfft_integrate_wait(s.ctx, st)
+
+
+def test_graph_needs_fixed_iterations_and_workspace():
+    cfg = SQZ
+    s = sim(cfg)                                          # adaptive iteration
+    h = s.empty_field().zero_()
+    ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(s.ctx, 3))
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_integrate_graph(s.ctx, 0.0, 0.01, 3, ws, h)
+    s2 = sim(cfg, fixed_iter=2)
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_integrate_graph(s2.ctx, 0.0, 0.01, 3, ws[:64], h)
+
+
+def test_batched_contexts_on_streams():
+    """Three instances of different sizes enqueued on their own streams, then
+    waited for: each equals its own run alone (bitwise)."""
+    cfgs = [CUBE32, SQZ, NONCUBIC]
+    steps, t1_s = 4, 0.01
+    alone = []
+    for i, cfg in enumerate(cfgs):
+        s = sim(cfg, fixed_iter=2)
+        h = to_dev(torch, state(cfg, seed=10 + i), torch.float64)
+        _graph_run(s, h, t1_s, steps)
+        torch.cuda.synchronize()
+        alone.append(h)
+    streams = [torch.cuda.Stream() for _ in cfgs]
+    sims, hs, wss = [], [], []
+    for i, cfg in enumerate(cfgs):
+        s = scfft.Simulation(cfg, precision=scfft.F64, stream=streams[i].cuda_stream,
+                             rhs_opts=scfft.default_rhs_opts(fixed_iter=2))
+        h = to_dev(torch, state(cfg, seed=10 + i), torch.float64)
+        torch.cuda.synchronize()
+        ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(s.ctx, steps))
+        torch.cuda.synchronize()
+        scfft.scfft_integrate_graph(s.ctx, 0.0, t1_s, steps, ws, h)
+        sims.append(s), hs.append(h), wss.append(ws)
+    for s in sims:
+        st = scfft.OdeStats()
+        scfft.scfft_integrate_wait(s.ctx, st)
+        assert st.accepted == steps
+    torch.cuda.synchronize()
+    for a, b in zip(hs, alone):
+        assert torch.equal(a, b)
