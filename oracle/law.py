@@ -26,8 +26,23 @@ def power_law(j, n, kappa=None):
     return j * rho
 
 
-def constitutive(j, chi, n, rho_out, kappa=None):
-    """e = rho(|j|) j in the superconductor (chi = 1), rho_out j outside."""
+def field_kappa(kappa, h, field_law):
+    """Field-dependent critical density (the e(j, h) relation that Sec. 2
+    allows after Eq. 1; the paper fixes no form): a Kim-type decrease
+    kappa_eff = kappa / (1 + |h| / h_K)^alpha with field_law = (h_K, alpha),
+    h the local magnetic field, both dimensionless (Eq. 8)."""
+    hk, alpha = field_law
+    h = np.asarray(h, dtype=np.float64)
+    mag = np.sqrt(h[0] ** 2 + h[1] ** 2 + h[2] ** 2)
+    base = np.ones_like(mag) if kappa is None else np.asarray(kappa, dtype=np.float64)
+    return base / np.power(1.0 + mag / hk, alpha)
+
+
+def constitutive(j, chi, n, rho_out, kappa=None, h=None, field_law=None):
+    """e = rho(|j|) j in the superconductor (chi = 1), rho_out j outside; with
+    field_law the critical density depends on the local field h."""
     j = np.asarray(j, dtype=np.float64)
     inside = np.asarray(chi) != 0
+    if field_law is not None:
+        kappa = field_kappa(kappa, h, field_law)
     return np.where(inside, power_law(j, n, kappa), rho_out * j)

@@ -42,7 +42,7 @@ class Problem:
     """Everything rhs_eval needs besides the state: grid, mask, material,
     drive and options, plus the warm-start memory (hdot_out of the last call)."""
 
-    def __init__(self, grid, chi, n_power, rho_out, drive, opts=None, kappa=None):
+    def __init__(self, grid, chi, n_power, rho_out, drive, opts=None, kappa=None, field_law=None):
         self.grid = grid
         self.chi = np.asarray(chi, dtype=np.uint8)
         self.n = float(n_power)
@@ -50,6 +50,7 @@ class Problem:
         self.drive = drive
         self.opts = opts if opts is not None else RhsOptions()
         self.kappa = kappa
+        self.field_law = field_law  # (h_K, alpha): field-dependent critical density, or None
         self.warm = None            # hdot on Omega_out from the most recent call
         self.last_iters = 0
         self.last_deltas = []
@@ -65,7 +66,7 @@ def rhs_eval(prob, t, h):
     o = prob.opts
 
     j = operators.curl_s(h, g)                                   # Eq. 4
-    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out, prob.kappa)   # Eq. 1
+    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out, prob.kappa, h, prob.field_law)  # Eq. 1
     hdot_in = -operators.curl_s(e, g) * inside                   # Eq. 3 on Omega
     if prob.warm is None:
         hdot_out = -operators.curl_s(e, g) * outside             # Ohm-law start

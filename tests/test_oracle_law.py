@@ -62,3 +62,27 @@ def test_odd_and_isotropic():
     assert np.array_equal(law.power_law(-j, 30.0), -e)
     q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
     assert np.allclose(law.power_law(q @ j, 30.0), q @ e, rtol=1e-12, atol=1e-14 * np.abs(e).max())
+
+
+def test_field_dependent_critical_density():
+    # e(j, h) allowed after Eq. 1: kappa_eff = kappa / (1 + |h|/h_K)^alpha
+    rng = np.random.default_rng(3)
+    j = rng.normal(size=(3, 4, 5, 6))
+    chi = np.ones((4, 5, 6), dtype=np.uint8)
+    h = rng.normal(size=(3, 4, 5, 6))
+    kap = 1.0 + 0.1 * rng.normal(size=(4, 5, 6))
+    base = law.constitutive(j, chi, 25.0, 20.0, kap)
+    # alpha = 0, or a field far below h_K: the field-independent law
+    assert np.array_equal(law.constitutive(j, chi, 25.0, 20.0, kap, h, (0.7, 0.0)), base)
+    assert np.allclose(law.constitutive(j, chi, 25.0, 20.0, kap, h, (1e12, 1.0)), base, rtol=1e-9)
+    # Kim model (alpha = 1): at |h| = h_K the critical density halves, so a
+    # current of magnitude kappa/2 gives |e| = e0 (1 in Eq. 8 units)
+    hk = 0.37
+    hv = np.zeros((3, 4, 5, 6))
+    hv[1] = hk
+    u = j / np.sqrt(np.sum(j * j, axis=0))
+    e = law.constitutive(u * (kap / 2.0), chi, 25.0, 20.0, kap, hv, (hk, 1.0))
+    assert np.allclose(np.sqrt(np.sum(e * e, axis=0)), 1.0, rtol=1e-12)
+    # outside the superconductor the field law does not enter
+    chi0 = np.zeros((4, 5, 6), dtype=np.uint8)
+    assert np.array_equal(law.constitutive(j, chi0, 25.0, 20.0, kap, h, (hk, 1.0)), 20.0 * j)
