@@ -239,6 +239,12 @@ scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask);
  * context precision, all > 0; NULL clears it (kappa = 1).  Copied. */
 scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa);
 scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d);
+/* Field-dependent critical density, the e(j, h) relation that Sec. 2 allows
+ * after Eq. 1 (the paper fixes no form): a Kim-type law
+ *   jc(x, B) = jc kappa(x) / (1 + |B| / b0_T)^alpha,  B = mu0 h the local field,
+ * used in Eq. 1 in place of jc kappa(x).  b0_T = 0 switches it off (the
+ * default); alpha >= 0.  The reverse mode rejects it (SCFFT_ERR_ARG). */
+scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha);
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o);
 /* Forget the warm start of iteration (5): the next RHS starts from Ohm's law. */
 scfft_status scfft_reset_warm(scfft_ctx* ctx);

@@ -96,6 +96,9 @@ struct XArgs {
   double* partials;      // X_UPDATE*: one double per block; X_MOMENT: 3 per block
   unsigned long long* clamps;
   T npow, rho_out, expmax;
+  // X_LAW: field-dependent critical density kappa / (1 + |h| hk_inv)^kim_alpha,
+  // h = in + in2_coef in2 read at Omega nodes; hk_inv = 0: independent of h
+  T hk_inv, kim_alpha;
   T hedot[3];
   int omega_only;        // X_MOMENT: 1 = chi nodes only
   int track;             // X_HIN, X_UPDATE*: 1 = keep every iterate in `out` and sum

@@ -340,6 +340,12 @@ template <>
 __device__ __forceinline__ double dev_log<double>(double x) { return log(x); }
 template <>
 __device__ __forceinline__ float dev_log<float>(float x) { return logf(x); }
+template <typename T>
+__device__ __forceinline__ T dev_log1p(T x);
+template <>
+__device__ __forceinline__ double dev_log1p<double>(double x) { return log1p(x); }
+template <>
+__device__ __forceinline__ float dev_log1p<float>(float x) { return log1pf(x); }
 
 // e = (|j|/kappa)^(n-1) j / kappa evaluated as j exp((n-1) (ln|j| - ln kappa) - ln kappa)
 template <typename T>
@@ -529,7 +535,17 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           }
         }
         if (in) {
-          const T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
+          T lnk = A.kappa ? dev_log<T>(A.kappa[idx]) : T(0);
+          if (A.hk_inv > T(0)) {  // e(j, h): the local field lowers the critical density
+            T hs = T(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              T hc = A.in[c * csr + idx];
+              if (A.in2) hc += A.in2_coef * A.in2[c * csr + idx];
+              hs += hc * hc;
+            }
+            lnk -= A.kim_alpha * dev_log1p<T>(sqrt(hs) * A.hk_inv);
+          }
           power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
         } else {
 #pragma unroll

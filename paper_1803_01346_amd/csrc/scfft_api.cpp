@@ -69,6 +69,7 @@ struct scfft_ctx {
   const double* g_hedot_tab = nullptr;
   const int* g_hedot_step = nullptr;
   int g_hedot_stage = 0;
+  double field_hk_inv = 0.0, field_alpha = 0.0;  // e(j, h): 1/h_K (dimensionless), exponent
   bool graph_busy = false;          // an integration is enqueued; scfft_integrate_wait ends it
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   std::vector<double> graph_hedot;  // host copy of the rate table (alive until the wait)
@@ -267,6 +268,8 @@ XArgs<T> base_args(scfft_ctx* c) {
   a.hedot_tab = c->g_hedot_tab;
   a.hedot_step = c->g_hedot_step;
   a.hedot_stage = c->g_hedot_stage;
+  a.hk_inv = (T)c->field_hk_inv;
+  a.kim_alpha = (T)c->field_alpha;
   a.npow = (T)c->mat.n_power;
   a.rho_out = (T)c->mat.rho_out;
   a.expmax = sizeof(T) == 4 ? (T)80.0 : (T)700.0;
@@ -340,7 +343,8 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
   const double frac = rows / ((double)p.ny * p.nz);  // share of the rows in the launch
   switch (op) {
     case X_FWD: return (a.in2 ? 2.0 : 1.0) * rows * p.nx * node + rows * spec;
-    case X_LAW: return inv_rows * spec + rows * mask + rows * spec;
+    case X_LAW: return inv_rows * spec + rows * mask + rows * spec +
+                       (a.hk_inv > 0 ? (a.in2 ? 2.0 : 1.0) * nin * frac * node : 0.0);
     case X_HIN: return inv_rows * spec + rows * mask + (a.warm ? nout * frac * node : 0.0) +
                        (a.track ? all : nin) * frac * node + rows * spec;
     case X_MASK: return inv_rows * spec + rows * mask + rows * spec;
@@ -632,6 +636,8 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
                           double rate_scale) {
   const int K = c->opts.fixed_iter;
   if (K <= 0) return fail(c, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  if (c->field_hk_inv > 0.0)
+    return fail(c, SCFFT_ERR_ARG, "reverse mode of the field-dependent law is not implemented");
   const Plan<T> p = make_plan<T>(c);
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
   const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
@@ -1494,6 +1500,17 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
   if (!dr.set(*d, ctx->u, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
   ctx->drive = dr;
   ctx->has_drive = true;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  if (!(b0_T >= 0.0) || !(alpha >= 0.0) || !std::isfinite(b0_T) || !std::isfinite(alpha))
+    return fail(ctx, SCFFT_ERR_ARG, "field law needs b0_T >= 0 and alpha >= 0");
+  // |B| / B0 = mu0 h_scale |h'| / B0 with h' the dimensionless field (Eq. 8)
+  ctx->field_hk_inv = b0_T > 0.0 ? kMu0 * ctx->u.h_scale / b0_T : 0.0;
+  ctx->field_alpha = b0_T > 0.0 ? alpha : 0.0;
   return SCFFT_OK;
 }
 

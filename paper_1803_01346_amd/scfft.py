@@ -99,6 +99,7 @@ _SIGS = {
     "scfft_set_mask": (C.c_int, [_P, _P]),
     "scfft_set_jc_map": (C.c_int, [_P, _P]),
     "scfft_set_drive": (C.c_int, [_P, C.POINTER(Drive)]),
+    "scfft_set_field_law": (C.c_int, [_P, C.c_double, C.c_double]),
     "scfft_set_rhs_opts": (C.c_int, [_P, C.POINTER(RhsOpts)]),
     "scfft_reset_warm": (C.c_int, [_P]),
     "scfft_init_state": (C.c_int, [_P, C.c_double, _P]),
@@ -312,6 +313,10 @@ def scfft_set_jc_map(ctx, dev_kappa):
 
 def scfft_set_drive(ctx, drive):
     return _check(load().scfft_set_drive(ctx, C.byref(drive)), ctx)
+
+
+def scfft_set_field_law(ctx, b0_T, alpha=1.0):
+    return _check(load().scfft_set_field_law(ctx, float(b0_T), float(alpha)), ctx)
 
 
 def scfft_set_rhs_opts(ctx, opts):
