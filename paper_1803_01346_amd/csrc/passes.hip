@@ -60,9 +60,16 @@ static void launch(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime t, Args
 #ifndef SCFFT_EX1_F32
 #define SCFFT_EX1_F32 8
 #endif
-// X passes: NC = 3 components per thread, or 1 (fewer registers: longer lines)
-template <typename T, int NC = 3>
+// X passes: NC = 3 components per thread, or 1 (fewer registers: longer lines).
+// In FP64 the per-component masks and exterior updates run shorter lines
+// (more rows per block) than the other per-component steps: measured faster.
+#ifndef SCFFT_EX1U_F64
+#define SCFFT_EX1U_F64 4
+#endif
+template <typename T, int NC = 3, int OP = -1>
 constexpr int ex_max() {
+  if (NC == 1 && sizeof(T) == 8 && (OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MASK))
+    return SCFFT_EX1U_F64;
   return NC == 1 ? (sizeof(T) == 8 ? SCFFT_EX1_F64 : SCFFT_EX1_F32)
                  : (sizeof(T) == 8 ? SCFFT_EX_F64 : SCFFT_EX_F32);
 }
@@ -379,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT && OP != X_ADJ_LAST && OP != X_ADJ_LAW),
                 "needs all components");
   constexpr int M = NX / 2;
-  constexpr int E = elems_per_thread(M, ex_max<T, NC>());
+  constexpr int E = elems_per_thread(M, ex_max<T, NC, OP>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
   constexpr bool HAS_INV = OP != X_FWD && OP != X_ADJ_START;
@@ -746,9 +753,9 @@ constexpr int tpt_of() {
   return N / elems_per_thread(N, EMAX);
 }
 
-template <typename T, int NX, int NC = 3>
+template <typename T, int NX, int NC = 3, int OP = -1>
 static int xblocks_n(const Plan<T>& p) {
-  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T, NC>()>();
+  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T, NC, OP>()>();
   const int rows = (p.r.xyhi - p.r.xylo) * (p.r.xzhi - p.r.xzlo);
   return (rows + ROWS - 1) / ROWS;
 }
@@ -767,38 +774,40 @@ int xpass_blocks(const Plan<T>& p) {
   return -1;
 }
 
+template <typename T, int NX, int OP, int NC>
+static void xlaunch_op(const Plan<T>& p, const XArgs<T>& a, hipStream_t s, KTime t) {
+  const int nb = xblocks_n<T, NX, NC, OP>(p);
+  if (nb <= 0) return;  // empty row range
+  launch(xpass_kernel<T, NX, OP, NC>, dim3(nb, NC == 3 ? 1 : 3), dim3(kBlock), s, t, p, a);
+}
+
 template <typename T, int NX, int NC>
 static hipError_t xlaunch_nc(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
-  const int nb = xblocks_n<T, NX, NC>(p);
-  if (nb <= 0) return hipSuccess;  // empty row range
-  const dim3 grid(nb, NC == 3 ? 1 : 3), block(kBlock);
   switch (op) {
-    case X_FWD: launch(xpass_kernel<T, NX, X_FWD, NC>, grid, block, s, t, p, a); break;
-    case X_HIN: launch(xpass_kernel<T, NX, X_HIN, NC>, grid, block, s, t, p, a); break;
-    case X_MASK: launch(xpass_kernel<T, NX, X_MASK, NC>, grid, block, s, t, p, a); break;
-    case X_UPDATE: launch(xpass_kernel<T, NX, X_UPDATE, NC>, grid, block, s, t, p, a); break;
-    case X_UPDATE_LAST:
-      launch(xpass_kernel<T, NX, X_UPDATE_LAST, NC>, grid, block, s, t, p, a);
-      break;
-    case X_STORE: launch(xpass_kernel<T, NX, X_STORE, NC>, grid, block, s, t, p, a); break;
-    case X_ADJ_START: launch(xpass_kernel<T, NX, X_ADJ_START, NC>, grid, block, s, t, p, a); break;
-    case X_ADJ_ACC: launch(xpass_kernel<T, NX, X_ADJ_ACC, NC>, grid, block, s, t, p, a); break;
+    case X_FWD: xlaunch_op<T, NX, X_FWD, NC>(p, a, s, t); break;
+    case X_HIN: xlaunch_op<T, NX, X_HIN, NC>(p, a, s, t); break;
+    case X_MASK: xlaunch_op<T, NX, X_MASK, NC>(p, a, s, t); break;
+    case X_UPDATE: xlaunch_op<T, NX, X_UPDATE, NC>(p, a, s, t); break;
+    case X_UPDATE_LAST: xlaunch_op<T, NX, X_UPDATE_LAST, NC>(p, a, s, t); break;
+    case X_STORE: xlaunch_op<T, NX, X_STORE, NC>(p, a, s, t); break;
+    case X_ADJ_START: xlaunch_op<T, NX, X_ADJ_START, NC>(p, a, s, t); break;
+    case X_ADJ_ACC: xlaunch_op<T, NX, X_ADJ_ACC, NC>(p, a, s, t); break;
     default:
       if constexpr (NC == 3) {
         if (op == X_ADJ_LAST) {
-          launch(xpass_kernel<T, NX, X_ADJ_LAST, 3>, grid, block, s, t, p, a);
+          xlaunch_op<T, NX, X_ADJ_LAST, 3>(p, a, s, t);
           break;
         }
         if (op == X_ADJ_LAW) {
-          launch(xpass_kernel<T, NX, X_ADJ_LAW, 3>, grid, block, s, t, p, a);
+          xlaunch_op<T, NX, X_ADJ_LAW, 3>(p, a, s, t);
           break;
         }
         if (op == X_LAW) {
-          launch(xpass_kernel<T, NX, X_LAW, 3>, grid, block, s, t, p, a);
+          xlaunch_op<T, NX, X_LAW, 3>(p, a, s, t);
           break;
         }
         if (op == X_MOMENT) {
-          launch(xpass_kernel<T, NX, X_MOMENT, 3>, grid, block, s, t, p, a);
+          xlaunch_op<T, NX, X_MOMENT, 3>(p, a, s, t);
           break;
         }
       }
