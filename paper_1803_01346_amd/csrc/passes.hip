@@ -88,6 +88,24 @@ constexpr int ez_max() { return sizeof(T) == 8 ? SCFFT_EZ_F64 : SCFFT_EZ_F32; }
 #ifndef SCFFT_PP_Z
 #define SCFFT_PP_Z 1
 #endif
+// Threads per block of a column pass: 256, doubled while the columns of one
+// block span fewer than 128 contiguous bytes of a row (FP32 at N = 256).
+#ifndef SCFFT_COL_BYTES
+#define SCFFT_COL_BYTES 128
+#endif
+// The Z pass widens only in FP64: its FP32 block of 512 threads would hold
+// 143 VGPRs per lane and leave one block per CU (measured slower at 256^3).
+#ifndef SCFFT_COL_BYTES_Z_F32
+#define SCFFT_COL_BYTES_Z_F32 64
+#endif
+template <typename T, int N, int EMAX, int BYTES = SCFFT_COL_BYTES>
+constexpr int col_block() {
+  const int tpt = N / elems_per_thread(N, EMAX);
+  int b = kBlock;
+  while ((b / tpt) * (int)sizeof(C2<T>) < BYTES && b < 1024) b *= 2;
+  return b;
+}
+
 template <bool PP, typename T, int N, int COLS>
 using ColLds = typename std::conditional<PP, LdsColsPP<T, N, COLS>, LdsCols<T, COLS>>::type;
 
@@ -124,13 +142,13 @@ __device__ __forceinline__ C2<T> dc_join(C2<T> S, C2<T> R, bool low) {
 // Y pass
 // ---------------------------------------------------------------------------
 template <typename T, int NY, bool INV>
-__global__ __launch_bounds__(kBlock) void ypass_kernel(C2<T>* __restrict__ main, int M, int nz,
+__global__ __launch_bounds__((col_block<T, NY, ey_max<T>()>())) void ypass_kernel(C2<T>* __restrict__ main, int M, int nz,
                                                        Ranges R, const C2<T>* __restrict__ tw,
                                                        const int* __restrict__ stop) {
   if (stop && *stop) return;  // uniform: the iteration has stopped
   constexpr int E = elems_per_thread(NY, ey_max<T>());
   constexpr int TPT = NY / E;
-  constexpr int COLS = kBlock / TPT;
+  constexpr int COLS = col_block<T, NY, ey_max<T>()>() / TPT;
   __shared__ C2<T> smem[(SCFFT_PP_Y ? 2 : 1) * NY * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
@@ -225,13 +243,13 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
 // FP64: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per CU, so
 // the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on 256 CUs
 template <typename T, int NZ, int SYM>
-__global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
+__global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>()), sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
     C2<T>* __restrict__ main, int ny, int M, AxisTab<T> tx, AxisTab<T> ty, AxisTab<T> tz, T coef,
     Ranges R, const int* __restrict__ stop) {
   if (stop && *stop) return;  // uniform: the iteration has stopped
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
-  constexpr int COLS = kBlock / TPT;
+  constexpr int COLS = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>() / TPT;
   __shared__ C2<T> smem[(SCFFT_PP_Z ? 2 : 1) * NZ * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
@@ -842,12 +860,13 @@ hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t
 
 template <typename T, int NY>
 static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
-  constexpr int COLS = kBlock / tpt_of<NY, ey_max<T>()>();
+  constexpr int BLOCK = col_block<T, NY, ey_max<T>()>();
+  constexpr int COLS = BLOCK / tpt_of<NY, ey_max<T>()>();
   const int M = p.nx / 2;
   const int nzr = p.r.zhi - p.r.zlo;
   if (nzr <= 0) return hipSuccess;  // nothing to transform
   const int ncm = 3 * nzr * M;
-  const dim3 grid((ncm + COLS - 1) / COLS), block(kBlock);
+  const dim3 grid((ncm + COLS - 1) / COLS), block(BLOCK);
   if (inv)
     launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop);
   else
@@ -871,9 +890,10 @@ hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
 
 template <typename T, int NZ>
 static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
-  constexpr int COLS = kBlock / tpt_of<NZ, ez_max<T>()>();
+  constexpr int BLOCK = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>();
+  constexpr int COLS = BLOCK / tpt_of<NZ, ez_max<T>()>();
   const int M = p.nx / 2;
-  const dim3 grid((p.ny * M + COLS - 1) / COLS), block(kBlock);
+  const dim3 grid((p.ny * M + COLS - 1) / COLS), block(BLOCK);
   switch (sym) {
     case Z_CURL:
       launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
