@@ -469,10 +469,24 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
       if (j == 0) Xs[cc][0].y = T(0);
     }
   }
+  // Nodes x = 2n, 2n+1 of one complex element n are adjacent: the mask and
+  // the real fields are read (and stored) two nodes per access.  Measured
+  // faster for every FP32 pass and for the FP64 updates; the FP64 input and
+  // warm-start passes keep one node per access.
+  constexpr bool PAIRED = sizeof(T) == 4 || !(OP == X_FWD || OP == X_HIN);
   uint8_t ch[2 * E];
-  if constexpr (NEED_CHI) {
+  if constexpr (NEED_CHI && !PAIRED) {
 #pragma unroll
     for (int e = 0; e < 2 * E; ++e) ch[e] = valid ? A.chi[rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : 0;
+  }
+  if constexpr (NEED_CHI && PAIRED) {
+    const uint16_t* chp = reinterpret_cast<const uint16_t*>(A.chi + rowbase);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const unsigned v = valid ? chp[j + m * TPT] : 0u;
+      ch[2 * m] = (uint8_t)(v & 0xffu);
+      ch[2 * m + 1] = (uint8_t)(v >> 8);
+    }
   }
   // X_FWD: the real input (all nodes); X_HIN: the warm start (Omega_out);
   // X_UPDATE*: hdot^i (all nodes when tracking iterates, else Omega only:
@@ -482,14 +496,11 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
                       ? A.in
                       : (OP == X_HIN ? A.warm : A.out);
   T aux[(NEED_AUX || OP == X_FWD) ? NC : 1][2 * E];
-  if constexpr (NEED_AUX || OP == X_FWD) {
+  if constexpr ((NEED_AUX || OP == X_FWD) && !PAIRED) {
 #pragma unroll
     for (int e = 0; e < 2 * E; ++e) {
       bool need = valid && auxp != nullptr;
       if constexpr (OP == X_HIN) need = need && ch[e] == 0;
-      if constexpr (OP == X_UPDATE) need = need && (A.track || ch[e] != 0);
-      if constexpr (OP == X_UPDATE_LAST) need = need && A.track;
-      if constexpr (OP == X_ADJ_LAW) need = need && ch[e] != 0;     // j is read in Omega only
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1);
@@ -497,9 +508,47 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
         if constexpr (OP == X_FWD) {
           if (need && A.in2) aux[cc][e] += A.in2_coef * A.in2[ai];  // stage argument y + c k
         }
-        if constexpr (OP == X_ADJ_START) {  // cotangent of hdot^K: lam + (1-chi) mu
-          if (need && A.in2 && ch[e] == 0) aux[cc][e] += A.in2[ai];
+      }
+    }
+  }
+  if constexpr ((NEED_AUX || OP == X_FWD) && PAIRED) {
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      bool need[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = 2 * m + h;
+        bool nd = valid && auxp != nullptr;
+        if constexpr (OP == X_HIN) nd = nd && ch[e] == 0;
+        if constexpr (OP == X_UPDATE) nd = nd && (A.track || ch[e] != 0);
+        if constexpr (OP == X_UPDATE_LAST) nd = nd && A.track;
+        if constexpr (OP == X_ADJ_LAW) nd = nd && ch[e] != 0;     // j is read in Omega only
+        need[h] = nd;
+      }
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + m * TPT);
+        T2 v = {T(0), T(0)};
+        if (need[0] || need[1]) {
+          v = *reinterpret_cast<const T2*>(auxp + ai);
+          if constexpr (OP == X_FWD) {
+            if (A.in2) {  // stage argument y + c k
+              const T2 w = *reinterpret_cast<const T2*>(A.in2 + ai);
+              v.x += A.in2_coef * w.x;
+              v.y += A.in2_coef * w.y;
+            }
+          }
+          if constexpr (OP == X_ADJ_START) {  // cotangent of hdot^K: lam + (1-chi) mu
+            if (A.in2) {
+              const T2 w = *reinterpret_cast<const T2*>(A.in2 + ai);
+              if (ch[2 * m] == 0) v.x += w.x;
+              if (ch[2 * m + 1] == 0) v.y += w.y;
+            }
+          }
         }
+        aux[cc][2 * m] = need[0] ? v.x : T(0);
+        aux[cc][2 * m + 1] = need[1] ? v.y : T(0);
       }
     }
   }
@@ -531,6 +580,8 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   }
 
   // ---- pointwise work on the nodes x = 2n, 2n+1, n = j + m TPT ----
+  // real-field stores are collected (bit e: node e) and issued two nodes per access
+  uint32_t st_out = 0, st_warm = 0;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
 #pragma unroll
@@ -582,8 +633,12 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           for (int cc = 0; cc < NC; ++cc) a[cc][e] = aux[cc][e];
         }
         if (valid && (A.track || in)) {
+          if constexpr (PAIRED) {
+            st_out |= 1u << e;
+          } else {
 #pragma unroll
-          for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
+            for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
+          }
         }
       } else if constexpr (OP == X_MASK) {
         if (!in) {
@@ -603,15 +658,10 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
         if (valid && !in) {
           if (A.track) {
             acc0 += sqrt((double)d2);
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
+            st_out |= 1u << e;
           } else if constexpr (OP == X_UPDATE_LAST) {
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
-            if (A.warm_out) {
-#pragma unroll
-              for (int cc = 0; cc < NC; ++cc) A.warm_out[(c0 + cc) * csr + idx] = a[cc][e];
-            }
+            st_out |= 1u << e;
+            if (A.warm_out) st_warm |= 1u << e;
           }
         }
       } else if constexpr (OP == X_ADJ_START || OP == X_ADJ_ACC) {
@@ -666,10 +716,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           for (int c = 0; c < 3; ++c) a[c][e] *= A.rho_out;
         }
       } else if constexpr (OP == X_STORE) {
-        if (valid) {
-#pragma unroll
-          for (int cc = 0; cc < NC; ++cc) A.out[(c0 + cc) * csr + idx] = a[cc][e];
-        }
+        if (valid) st_out |= 1u << e;
       } else if constexpr (OP == X_MOMENT) {
         const bool use = valid && (!A.omega_only || in);
         if (use) {
@@ -680,6 +727,31 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           acc0 += py * jz - pz * jy;
           acc1 += pz * jx - px * jz;
           acc2 += px * jy - py * jx;
+        }
+      }
+    }
+  }
+
+  if constexpr (OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_STORE) {
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const unsigned bo = (st_out >> (2 * m)) & 3u, bw = (st_warm >> (2 * m)) & 3u;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + m * TPT);
+        const T v0 = a[cc][2 * m], v1 = a[cc][2 * m + 1];
+        if (bo == 3u) {
+          *reinterpret_cast<T2*>(A.out + ai) = T2{v0, v1};
+        } else if (bo) {
+          if (bo & 1u) A.out[ai] = v0;
+          if (bo & 2u) A.out[ai + 1] = v1;
+        }
+        if (bw == 3u) {
+          *reinterpret_cast<T2*>(A.warm_out + ai) = T2{v0, v1};
+        } else if (bw) {
+          if (bw & 1u) A.warm_out[ai] = v0;
+          if (bw & 2u) A.warm_out[ai + 1] = v1;
         }
       }
     }
