@@ -19,6 +19,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace scfft {
@@ -166,6 +168,9 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   // per-node inputs of the rows this thread transforms, fetched first; the
   // mask of row round r is bit e of chm[r]
   static_assert(2 * E <= 32, "mask bits");
+  // nodes x = 2n, 2n+1 of one complex element are adjacent: mask and real
+  // fields are accessed two nodes at a time
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   uint32_t chm[G::RX];
   T aux[NEED_AUX ? G::RX : 1][2 * E];
   const T* auxp = OP == XY_FWD ? A.in : (OP == XY_HIN ? A.warm : A.out);
@@ -175,25 +180,42 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
     const bool ok = y < NY;
     uint32_t bits = 0;
     if constexpr (NEED_CHI) {
+      const uint16_t* chp =
+          reinterpret_cast<const uint16_t*>(A.chi + (size_t)z * NY * NX + (size_t)(ok ? y : 0) * NX);
 #pragma unroll
-      for (int e = 0; e < 2 * E; ++e) {
-        const size_t nidx = (size_t)z * NY * NX + (size_t)y * NX + 2 * (j + (e >> 1) * TPT) + (e & 1);
-        if (ok && A.chi[nidx]) bits |= 1u << e;
+      for (int m = 0; m < E; ++m) {
+        const unsigned v = ok ? chp[j + m * TPT] : 0u;
+        if (v & 0xffu) bits |= 1u << (2 * m);
+        if (v >> 8) bits |= 2u << (2 * m);
       }
     }
     chm[r] = bits;
     if constexpr (NEED_AUX) {
 #pragma unroll
-      for (int e = 0; e < 2 * E; ++e) {
-        const size_t idx = rbase + (size_t)y * NX + 2 * (j + (e >> 1) * TPT) + (e & 1);
-        const bool in = (bits >> e) & 1u;
-        bool need = ok && auxp != nullptr;
-        if constexpr (OP == XY_HIN) need = need && !in;     // warm start on Omega_out
-        if constexpr (OP == XY_UPDATE) need = need && in;   // hdot_in on Omega
-        aux[r][e] = need ? auxp[idx] : T(0);
-        if constexpr (OP == XY_FWD) {
-          if (need && A.in2) aux[r][e] += A.in2_coef * A.in2[idx];  // stage argument y + c k
+      for (int m = 0; m < E; ++m) {
+        const size_t idx = rbase + (size_t)y * NX + 2 * (j + m * TPT);
+        bool need[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool in = (bits >> (2 * m + h)) & 1u;
+          bool nd = ok && auxp != nullptr;
+          if constexpr (OP == XY_HIN) nd = nd && !in;     // warm start on Omega_out
+          if constexpr (OP == XY_UPDATE) nd = nd && in;   // hdot_in on Omega
+          need[h] = nd;
         }
+        T2 v = {T(0), T(0)};
+        if (need[0] || need[1]) {
+          v = *reinterpret_cast<const T2*>(auxp + idx);
+          if constexpr (OP == XY_FWD) {
+            if (A.in2) {  // stage argument y + c k
+              const T2 w = *reinterpret_cast<const T2*>(A.in2 + idx);
+              v.x += A.in2_coef * w.x;
+              v.y += A.in2_coef * w.y;
+            }
+          }
+        }
+        aux[r][2 * m] = need[0] ? v.x : T(0);
+        aux[r][2 * m + 1] = need[1] ? v.y : T(0);
       }
     }
   }
@@ -239,25 +261,45 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
 #pragma unroll
         for (int e = 0; e < 2 * E; ++e) a[e] = aux[r][e];
       }
+      uint32_t st_out = 0, st_warm = 0;  // bit e: store node e
 #pragma unroll
       for (int e = 0; e < 2 * E; ++e) {
         const bool in = (chm[r] >> e) & 1u;
-        const size_t idx = rbase + (size_t)y * NX + 2 * (j + (e >> 1) * TPT) + (e & 1);
         if constexpr (OP == XY_HIN) {
           if (!in && A.warm) a[e] = aux[r][e];
-          if (A.track || in) A.out[idx] = a[e];
+          if (A.track || in) st_out |= 1u << e;
         } else if constexpr (OP == XY_MASK) {
           if (!in) a[e] = T(0);
         } else if constexpr (OP == XY_UPDATE) {
           a[e] = in ? aux[r][e] : hdc + a[e];
         } else if constexpr (OP == XY_UPDATE_LAST) {
           if (!in) {
-            const T v = hdc + a[e];
-            A.out[idx] = v;
-            if (A.warm_out) A.warm_out[idx] = v;
+            a[e] = hdc + a[e];
+            st_out |= 1u << e;
+            if (A.warm_out) st_warm |= 1u << e;
           }
         } else if constexpr (OP == XY_STORE) {
-          A.out[idx] = a[e];
+          st_out |= 1u << e;
+        }
+      }
+      if constexpr (OP == XY_HIN || OP == XY_UPDATE_LAST || OP == XY_STORE) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const size_t idx = rbase + (size_t)y * NX + 2 * (j + m * TPT);
+          const unsigned bo = (st_out >> (2 * m)) & 3u, bw = (st_warm >> (2 * m)) & 3u;
+          const T v0 = a[2 * m], v1 = a[2 * m + 1];
+          if (bo == 3u) {
+            *reinterpret_cast<T2*>(A.out + idx) = T2{v0, v1};
+          } else if (bo) {
+            if (bo & 1u) A.out[idx] = v0;
+            if (bo & 2u) A.out[idx + 1] = v1;
+          }
+          if (bw == 3u) {
+            *reinterpret_cast<T2*>(A.warm_out + idx) = T2{v0, v1};
+          } else if (bw) {
+            if (bw & 1u) A.warm_out[idx] = v0;
+            if (bw & 2u) A.warm_out[idx + 1] = v1;
+          }
         }
       }
       if constexpr (HAS_FWD) row_r2c<T, NX, NY>(row, j, twx, a);
