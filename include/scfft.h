@@ -318,7 +318,7 @@ scfft_status scfft_rhs_vjp(scfft_ctx* ctx, const void* h_dev, int32_t warm_used,
 
 /* Device workspace (bytes, 256-byte aligned start) for scfft_integrate_adjoint:
  * ceil(steps / checkpoint_every) checkpoints of 3 fields, a tape of
- * 3 * checkpoint_every + 1 fields and 10 work fields. */
+ * 6 * checkpoint_every + 1 fields and 10 work fields. */
 scfft_status scfft_adjoint_workspace_size(const scfft_ctx* ctx, int32_t steps,
                                           int32_t checkpoint_every, size_t* bytes);
 

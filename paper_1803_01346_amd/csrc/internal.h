@@ -108,6 +108,7 @@ struct XArgs {
   double* mom_partials;  // X_LAW: if set, 6 doubles per block: sums of r x j over all
                          // nodes (3) and over Omega nodes (3), for the moment readout
   T* kappa_bar;          // X_ADJ_LAW: accumulated d/dkappa (scalar field) or nullptr
+  T* j_out;              // X_LAW: if set, j = C_s h is also stored here (all nodes)
   // X_UPDATE*, XY_UPDATE*: if hedot_tab is set, the applied-field rate is
   // hedot_tab[9 * (*hedot_step) + 3 * hedot_stage + c] instead of hedot[c]
   // (graph replays of a step: one row of three stage rates per step)

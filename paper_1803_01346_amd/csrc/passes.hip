@@ -582,6 +582,16 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   // ---- pointwise work on the nodes x = 2n, 2n+1, n = j + m TPT ----
   // real-field stores are collected (bit e: node e) and issued two nodes per access
   uint32_t st_out = 0, st_warm = 0;
+  if constexpr (OP == X_LAW) {
+    if (A.j_out && valid) {  // j itself, before the law (kept for the reverse mode)
+      using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          *reinterpret_cast<T2*>(A.j_out + c * csr + rowbase + 2 * (j + m * TPT)) = T2{a[c][2 * m], a[c][2 * m + 1]};
+    }
+  }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
 #pragma unroll

@@ -344,7 +344,8 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
   switch (op) {
     case X_FWD: return (a.in2 ? 2.0 : 1.0) * rows * p.nx * node + rows * spec;
     case X_LAW: return inv_rows * spec + rows * mask + rows * spec +
-                       (a.hk_inv > 0 ? (a.in2 ? 2.0 : 1.0) * nin * frac * node : 0.0);
+                       (a.hk_inv > 0 ? (a.in2 ? 2.0 : 1.0) * nin * frac * node : 0.0) +
+                       (a.j_out ? rows * p.nx * node : 0.0);
     case X_HIN: return inv_rows * spec + rows * mask + (a.warm ? nout * frac * node : 0.0) +
                        (a.track ? all : nin) * frac * node + rows * spec;
     case X_MASK: return inv_rows * spec + rows * mask + rows * spec;
@@ -494,7 +495,8 @@ template <typename T>
 // argument is formed inside the first pass).  mom: if set, the power-law
 // pass also records moment partials of that state (6 per block).
 scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_stats* stats,
-                      const T* in2 = nullptr, double in2_coef = 0.0, double* mom = nullptr) {
+                      const T* in2 = nullptr, double in2_coef = 0.0, double* mom = nullptr,
+                      T* j_out = nullptr) {
   const Plan<T> p = make_plan<T>(c);
   const hipStream_t s = c->stream;
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
@@ -510,6 +512,7 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   a.in2 = in2;
   a.in2_coef = (T)in2_coef;
   a.mom_partials = mom;
+  a.j_out = j_out;
 
   if (c->opts.fixed_iter > 0 && use_xy<T>(c, p)) return rhs_fused<T>(c, p, a, h, hdot, stats);
   const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
@@ -631,9 +634,10 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
 // accumulators: sc[0] += nbar, sc[1..3] += rate_scale * hedot_bar;
 // kappa_bar (scalar field) is accumulated when non-null.
 template <typename T>
+// j_known: j = C_s h of the forward call if the caller kept it (else recomputed).
 scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coef, bool warm_used,
                           const T* lam, const T* mu, T* hbar, T* wbar, T* kbar, double* sc,
-                          double rate_scale) {
+                          double rate_scale, const T* j_known = nullptr) {
   const int K = c->opts.fixed_iter;
   if (K <= 0) return fail(c, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
   if (c->field_hk_inv > 0.0)
@@ -645,15 +649,23 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
   T* jbuf = wsp<T>(c, c->off_adj);
   T* acc = jbuf + 3 * c->nodes;
   XArgs<T> a = base_args<T>(c);
-  // j = C h at the forward call's state (Eq. 4)
-  a.in = h;
-  a.in2 = in2;
-  a.in2_coef = (T)in2_coef;
-  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
-  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
-  a.in2 = nullptr;
-  a.out = jbuf;
-  HIPCHK(c, run_x<T>(c, p, X_STORE, a));
+  const T* jv = j_known;
+  if (!jv) {
+    // j = C h at the forward call's state (Eq. 4), taken from the power-law
+    // pass as in the forward call (bitwise the same j; its law output and
+    // clamp count are discarded)
+    a.in = h;
+    a.in2 = in2;
+    a.in2_coef = (T)in2_coef;
+    HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+    HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+    XArgs<T> al = a;
+    al.j_out = jbuf;
+    al.clamps = reinterpret_cast<unsigned long long*>(wsp<double>(c, c->off_adjs) + 8);
+    HIPCHK(c, run_x<T>(c, p, X_LAW, al));
+    a.in2 = nullptr;
+    jv = jbuf;
+  }
   // the exterior iteration (Eq. 5) transposed, last iterate first
   a.in = lam;
   a.in2 = mu;
@@ -676,7 +688,7 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
   }
   // ebar = -C gbar (Eq. 3); jbar = (de/dj)^T ebar (Eq. 1); hbar = C jbar (Eq. 4)
   HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, -norm));
-  a.in = jbuf;
+  a.in = jv;
   a.kappa_bar = kbar;
   HIPCHK(c, run_x<T>(c, p, X_ADJ_LAW, a));
   HIPCHK(c, launch_accum_partials(a.partials, xb, 1, 1, 1.0, sc, c->stream));
@@ -908,7 +920,8 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
 // reverse mode of fixed-step BS23
 // ---------------------------------------------------------------------------
 // Caller workspace: nseg checkpoints (state, k1, warm start at a segment's
-// first step), the tape of one segment (state, k1, k2 per step, and the
+// first step), the tape of one segment (per step: state, k1, k2 and the
+// current density j = C_s u of the three stage states u2, u3, u4; and the
 // state after it), and 10 fields for the forward pass and the cotangents.
 struct AdjLayout {
   size_t F = 0;
@@ -922,7 +935,7 @@ AdjLayout adj_layout(const scfft_ctx* c, int steps, int every) {
   L.every = every;
   L.nseg = (steps + every - 1) / every;
   L.off_tape = (size_t)L.nseg * 3 * L.F;
-  L.off_vec = L.off_tape + (size_t)(3 * every + 1) * L.F;
+  L.off_vec = L.off_tape + (size_t)(6 * every + 1) * L.F;
   L.total = L.off_vec + 10 * L.F;
   return L;
 }
@@ -934,13 +947,14 @@ struct AdjRun {
   AdjLayout L;
   T* f(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   T* cp(int seg, int k) const { return f(((size_t)seg * 3 + k) * L.F); }  // k: 0 y, 1 k1, 2 warm
-  T* tape(int m, int k) const { return f(L.off_tape + ((size_t)m * 3 + k) * L.F); }  // k: 0 y, 1 k1, 2 k2
-  T* yend() const { return f(L.off_tape + (size_t)(3 * L.every) * L.F); }
+  // k: 0 y, 1 k1, 2 k2, 3 j(u2), 4 j(u3), 5 j(u4)
+  T* tape(int m, int k) const { return f(L.off_tape + ((size_t)m * 6 + k) * L.F); }
+  T* yend() const { return f(L.off_tape + (size_t)(6 * L.every) * L.F); }
   T* vec(int i) const { return f(L.off_vec + (size_t)i * L.F); }
   size_t fb() const { return 3 * c->nodes * sizeof(T); }
 
-  scfft_status rhs(double t, const T* y, const T* k, double coef, T* out) {
-    return rhs_impl<T>(c, t, y, out, nullptr, k, coef, nullptr);
+  scfft_status rhs(double t, const T* y, const T* k, double coef, T* out, T* j_out = nullptr) {
+    return rhs_impl<T>(c, t, y, out, nullptr, k, coef, nullptr, j_out);
   }
   scfft_status combo(T* out, const T* y, const T* a, double ca, const T* b, double cb, const T* d,
                      double cd) {
@@ -977,20 +991,49 @@ scfft_status integrate_adjoint_impl(scfft_ctx* c, double t0, double t1, int step
   T* warm = wsp<T>(c, c->off_warm);
   const size_t wb = 3 * c->nodes * sizeof(T);
 
-  // ---- forward, checkpoint at the start of every segment ----
+  // Segment seg's states: y_m (checkpoint for m = 0, tape after), k1_m.
+  auto seg_len = [&](int seg) { return std::min(steps, (seg + 1) * every) - seg * every; };
+  auto yp = [&](int seg, int m) {
+    return m == 0 ? R.cp(seg, 0) : (m < seg_len(seg) ? R.tape(m, 0) : R.yend());
+  };
+  auto k1p = [&](int seg, int m) { return m == 0 ? R.cp(seg, 1) : R.tape(m, 1); };
+  T* k3tmp = R.vec(8);
+  // Steps of one segment from its checkpoint into the tape, with the
+  // current density of each stage state (same arithmetic as the forward);
+  // the context's warm start must be that of the checkpoint.
+  auto record = [&](int seg) -> scfft_status {
+    const int s0 = seg * every, len = seg_len(seg);
+    double t = t_of(s0);
+    for (int m = 0; m < len; ++m) {
+      const double h = t_of(s0 + m + 1) - t;
+      ADJCHK(R.rhs(t + 0.5 * h, yp(seg, m), k1p(seg, m), 0.5 * h, R.tape(m, 2), R.tape(m, 3)));
+      ADJCHK(R.rhs(t + 0.75 * h, yp(seg, m), R.tape(m, 2), 0.75 * h, k3tmp, R.tape(m, 4)));
+      ADJCHK(R.combo(yp(seg, m + 1), yp(seg, m), k1p(seg, m), h * (2.0 / 9.0), R.tape(m, 2),
+                     h * (1.0 / 3.0), k3tmp, h * (4.0 / 9.0)));
+      if (m + 1 < len)
+        ADJCHK(R.rhs(t + h, yp(seg, m + 1), nullptr, 0.0, R.tape(m + 1, 1), R.tape(m, 5)));
+      t = t_of(s0 + m + 1);
+    }
+    return SCFFT_OK;
+  };
+  const int last = R.L.nseg - 1;
+
+  // ---- forward: checkpoint at the start of every segment; the last segment
+  // goes straight into the tape (it is reversed first) ----
   {
     T *Y = R.vec(0), *Y1 = R.vec(1), *K1 = R.vec(2), *K2 = R.vec(3), *K3 = R.vec(4), *K4 = R.vec(5);
     c->has_warm = false;
     ADJCHK(R.copy(Y, h0));
     ADJCHK(R.rhs(t0, Y, nullptr, 0.0, K1));
     double t = t0;
-    for (int s = 0; s < steps; ++s) {
+    for (int s = 0; s <= last * every; ++s) {
       if (s % every == 0) {
         const int seg = s / every;
         ADJCHK(R.copy(R.cp(seg, 0), Y));
         ADJCHK(R.copy(R.cp(seg, 1), K1));
         HIPCHK(c, hipMemcpyAsync(R.cp(seg, 2), warm, wb, hipMemcpyDeviceToDevice, c->stream));
       }
+      if (s == last * every) break;
       const double h = t_of(s + 1) - t;
       ADJCHK(R.rhs(t + 0.5 * h, Y, K1, 0.5 * h, K2));
       ADJCHK(R.rhs(t + 0.75 * h, Y, K2, 0.75 * h, K3));
@@ -1000,53 +1043,44 @@ scfft_status integrate_adjoint_impl(scfft_ctx* c, double t0, double t1, int step
       std::swap(K1, K4);
       t = t_of(s + 1);
     }
-    if (hT) ADJCHK(R.copy(hT, Y));
+    ADJCHK(record(last));
+    if (hT) ADJCHK(R.copy(hT, R.yend()));
   }
 
   // ---- reverse ----
   T *ybar = R.vec(0), *k1n = R.vec(1), *wbA = R.vec(2), *wbB = R.vec(3), *k1b = R.vec(4),
-    *k2b = R.vec(5), *k3b = R.vec(6), *ub = R.vec(7), *k3tmp = R.vec(8);
+    *k2b = R.vec(5), *k3b = R.vec(6), *ub = R.vec(7);
   double* sc = wsp<double>(c, c->off_adjs);
   HIPCHK(c, launch_zero_doubles(sc, 4, c->stream));
   ADJCHK(R.copy(ybar, hT_bar));
   ADJCHK(R.combo(k1n, nullptr, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0));   // zero
   ADJCHK(R.combo(wbA, nullptr, nullptr, 0.0, nullptr, 0.0, nullptr, 0.0));
-  for (int seg = R.L.nseg - 1; seg >= 0; --seg) {
-    const int s0 = seg * every, s1 = std::min(steps, s0 + every), len = s1 - s0;
-    auto yp = [&](int m) { return m == 0 ? R.cp(seg, 0) : (m < len ? R.tape(m, 0) : R.yend()); };
-    auto k1p = [&](int m) { return m == 0 ? R.cp(seg, 1) : R.tape(m, 1); };
-    // recompute the segment from its checkpoint (same arithmetic as the forward)
-    HIPCHK(c, hipMemcpyAsync(warm, R.cp(seg, 2), wb, hipMemcpyDeviceToDevice, c->stream));
-    c->has_warm = true;
-    double t = t_of(s0);
-    for (int m = 0; m < len; ++m) {
-      const double h = t_of(s0 + m + 1) - t;
-      ADJCHK(R.rhs(t + 0.5 * h, yp(m), k1p(m), 0.5 * h, R.tape(m, 2)));
-      ADJCHK(R.rhs(t + 0.75 * h, yp(m), R.tape(m, 2), 0.75 * h, k3tmp));
-      ADJCHK(R.combo(yp(m + 1), yp(m), k1p(m), h * (2.0 / 9.0), R.tape(m, 2), h * (1.0 / 3.0), k3tmp,
-                     h * (4.0 / 9.0)));
-      if (m + 1 < len) ADJCHK(R.rhs(t + h, yp(m + 1), nullptr, 0.0, R.tape(m + 1, 1)));
-      t = t_of(s0 + m + 1);
+  for (int seg = last; seg >= 0; --seg) {
+    const int s0 = seg * every, len = seg_len(seg);
+    if (seg != last) {  // recompute the segment from its checkpoint
+      HIPCHK(c, hipMemcpyAsync(warm, R.cp(seg, 2), wb, hipMemcpyDeviceToDevice, c->stream));
+      c->has_warm = true;
+      ADJCHK(record(seg));
     }
     // adjoint steps, last first
     for (int m = len - 1; m >= 0; --m) {
       const double ts = t_of(s0 + m), h = t_of(s0 + m + 1) - ts;
       // k4 = f(t + h, y_{n+1}; w3): cotangent k1n (the next step's k1), warm cotangent wbA
-      ADJCHK(rhs_vjp_impl<T>(c, yp(m + 1), nullptr, 0.0, true, k1n, wbA, ub, wbB, kbar, sc,
-                             rate(ts + h)));
+      ADJCHK(rhs_vjp_impl<T>(c, yp(seg, m + 1), nullptr, 0.0, true, k1n, wbA, ub, wbB, kbar, sc,
+                             rate(ts + h), m + 1 < len ? R.tape(m, 5) : nullptr));
       ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
       // y_{n+1} = y + h (2/9 k1 + 1/3 k2 + 4/9 k3)
       ADJCHK(R.combo(k1b, nullptr, ybar, h * (2.0 / 9.0), nullptr, 0.0, nullptr, 0.0));
       ADJCHK(R.combo(k2b, nullptr, ybar, h * (1.0 / 3.0), nullptr, 0.0, nullptr, 0.0));
       ADJCHK(R.combo(k3b, nullptr, ybar, h * (4.0 / 9.0), nullptr, 0.0, nullptr, 0.0));
       // k3 = f(t + 3h/4, y + 3h/4 k2; w2)
-      ADJCHK(rhs_vjp_impl<T>(c, yp(m), R.tape(m, 2), 0.75 * h, true, k3b, wbB, ub, wbA, kbar, sc,
-                             rate(ts + 0.75 * h)));
+      ADJCHK(rhs_vjp_impl<T>(c, yp(seg, m), R.tape(m, 2), 0.75 * h, true, k3b, wbB, ub, wbA, kbar, sc,
+                             rate(ts + 0.75 * h), R.tape(m, 4)));
       ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
       ADJCHK(R.combo(k2b, k2b, ub, 0.75 * h, nullptr, 0.0, nullptr, 0.0));
       // k2 = f(t + h/2, y + h/2 k1; w1)
-      ADJCHK(rhs_vjp_impl<T>(c, yp(m), k1p(m), 0.5 * h, true, k2b, wbA, ub, wbB, kbar, sc,
-                             rate(ts + 0.5 * h)));
+      ADJCHK(rhs_vjp_impl<T>(c, yp(seg, m), k1p(seg, m), 0.5 * h, true, k2b, wbA, ub, wbB, kbar, sc,
+                             rate(ts + 0.5 * h), R.tape(m, 3)));
       ADJCHK(R.combo(ybar, ybar, ub, 1.0, nullptr, 0.0, nullptr, 0.0));
       ADJCHK(R.combo(k1n, k1b, ub, 0.5 * h, nullptr, 0.0, nullptr, 0.0));
       std::swap(wbA, wbB);
