@@ -1479,6 +1479,7 @@ scfft_status scfft_workspace_size(const scfft_ctx* ctx, size_t* bytes) {
 
 scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   if (!dev_ptr) return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace pointer is NULL");
   if (bytes < ctx->total)
     return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, ctx->total);
@@ -1493,6 +1494,7 @@ scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes) {
 
 scfft_status scfft_voxelize(scfft_ctx* ctx, const scfft_shape* shapes, int32_t n_shapes) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   const char* why = nullptr;
@@ -1504,6 +1506,7 @@ scfft_status scfft_voxelize(scfft_ctx* ctx, const scfft_shape* shapes, int32_t n
 
 scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!dev_mask) return fail(ctx, SCFFT_ERR_ARG, "mask pointer is NULL");
@@ -1515,6 +1518,7 @@ scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask) {
 
 scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!dev_kappa) {
@@ -1529,6 +1533,7 @@ scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
 
 scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
   if (!ctx || !d) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   const char* why = nullptr;
   Drive dr;
   if (!dr.set(*d, ctx->u, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
@@ -1550,6 +1555,7 @@ scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
 
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   if (!ctx || !o) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
       !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2)
     return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");
@@ -1565,6 +1571,7 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
 
 scfft_status scfft_reset_warm(scfft_ctx* ctx) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ctx->has_warm = false;
   return SCFFT_OK;
 }
@@ -1794,6 +1801,7 @@ scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_
 
 scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes) {
   if (!ctx || !bytes) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   const size_t wb = ctx->has_warm ? 3 * ctx->nodes * ctx->wsize : 0;
   const size_t need = sizeof(StateHeader) + wb;
   if (!blob) {
@@ -1822,6 +1830,7 @@ scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes) {
 
 scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes) {
   if (!ctx || !blob) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   StateHeader hd;
@@ -1847,6 +1856,7 @@ scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes) {
 
 scfft_status scfft_profile(scfft_ctx* ctx, int32_t enable) {
   if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   if (enable) {
     if (ctx->ev_pool.empty()) {
       const size_t pairs = 4096;
@@ -1872,6 +1882,7 @@ scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KI
                                 double total_ms[SCFFT_KERNEL_KINDS],
                                 double total_bytes[SCFFT_KERNEL_KINDS]) {
   if (!ctx || !launches || !total_ms) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   HIPCHK(ctx, prof_harvest(ctx));
   for (int k = 0; k < SCFFT_KERNEL_KINDS; ++k) {
     launches[k] = ctx->prof_launches[k];
