@@ -270,6 +270,15 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
                              const scfft_ode_opts* o, scfft_observer obs, void* user,
                              scfft_ode_stats* stats);
 
+/* Autotuner: times one right-hand-side call (fixed_iter > 0) under each pass
+ * schedule this grid supports (row/column passes; fused xy-plane passes where
+ * a z plane fits in LDS) on the caller's state h, calls times each after a
+ * warm-up call, and keeps the faster one as the rhs option fuse_xy (0 or 2).
+ * The warm start is restored afterwards.  fuse_xy and ms_per_call (may be
+ * NULL) receive the choice and its mean time per call.  Synchronous. */
+scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, int32_t* fuse_xy,
+                            double* ms_per_call);
+
 /* ---- graph-replayed fixed-step integration ----
  *
  * The fixed-step mode of scfft_integrate (equal steps (t1 - t0)/steps of the

@@ -98,6 +98,9 @@ constexpr int ez_max() { return sizeof(T) == 8 ? SCFFT_EZ_F64 : SCFFT_EZ_F32; }
 #ifndef SCFFT_COL_BYTES_Z_F32
 #define SCFFT_COL_BYTES_Z_F32 64
 #endif
+#ifndef SCFFT_COL_BYTES_Z_F64
+#define SCFFT_COL_BYTES_Z_F64 SCFFT_COL_BYTES
+#endif
 template <typename T, int N, int EMAX, int BYTES = SCFFT_COL_BYTES>
 constexpr int col_block() {
   const int tpt = N / elems_per_thread(N, EMAX);
@@ -243,13 +246,13 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
 // FP64: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per CU, so
 // the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on 256 CUs
 template <typename T, int NZ, int SYM>
-__global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>()), sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
+__global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>()), sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
     C2<T>* __restrict__ main, int ny, int M, AxisTab<T> tx, AxisTab<T> ty, AxisTab<T> tz, T coef,
     Ranges R, const int* __restrict__ stop) {
   if (stop && *stop) return;  // uniform: the iteration has stopped
   constexpr int E = elems_per_thread(NZ, ez_max<T>());
   constexpr int TPT = NZ / E;
-  constexpr int COLS = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>() / TPT;
+  constexpr int COLS = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>() / TPT;
   __shared__ C2<T> smem[(SCFFT_PP_Z ? 2 : 1) * NZ * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
@@ -972,7 +975,7 @@ hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
 
 template <typename T, int NZ>
 static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
-  constexpr int BLOCK = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES : SCFFT_COL_BYTES_Z_F32)>();
+  constexpr int BLOCK = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>();
   constexpr int COLS = BLOCK / tpt_of<NZ, ez_max<T>()>();
   const int M = p.nx / 2;
   const dim3 grid((p.ny * M + COLS - 1) / COLS), block(BLOCK);

@@ -1272,6 +1272,65 @@ scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
   return hs.bad >= 0 ? fail(c, SCFFT_ERR_NAN, "non-finite error norm at step %d", hs.bad) : SCFFT_OK;
 }
 
+// Autotuner over the pass schedules of one right-hand-side call: times each
+// candidate on the caller's state with HIP events on the context stream and
+// keeps the faster (rhs option fuse_xy).  The warm start is saved in an ODE
+// buffer and restored after every timed run.
+template <typename T>
+scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, double* ms_best) {
+  const Plan<T> p = make_plan<T>(c);
+  std::vector<int> cand = {0};
+  if (xypass_supported<T>(p)) cand.push_back(2);
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  T* out = wsp<T>(c, c->off_ode + 4 * fb);
+  T* saved = wsp<T>(c, c->off_ode + 5 * fb);
+  const bool had_warm = c->has_warm;
+  if (had_warm) HIPCHK(c, hipMemcpyAsync(saved, wsp<T>(c, c->off_warm), fb, hipMemcpyDeviceToDevice, c->stream));
+  auto restore = [&]() -> hipError_t {
+    c->has_warm = had_warm;
+    return had_warm ? hipMemcpyAsync(wsp<T>(c, c->off_warm), saved, fb, hipMemcpyDeviceToDevice, c->stream)
+                    : hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, SCFFT_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(he));
+  }
+  const int keep = c->opts.fuse_xy;
+  scfft_status st = SCFFT_OK;
+  double best = INFINITY;
+  int pick = keep;
+  for (int fx : cand) {
+    c->opts.fuse_xy = fx;
+    if ((he = restore()) != hipSuccess) break;
+    if ((st = rhs_impl<T>(c, 0.0, h, out, nullptr)) < 0) break;          // warm-up
+    if ((he = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+    for (int k = 0; k < calls && st >= 0; ++k) st = rhs_impl<T>(c, 0.0, h, out, nullptr);
+    if (st < 0) break;
+    if ((he = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+    if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.0f;
+    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    if (ms / calls < best) {
+      best = ms / calls;
+      pick = fx;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->opts.fuse_xy = keep;
+  if (st < 0) return st;
+  if (he != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "autotune: %s", hipGetErrorString(he));
+  HIPCHK(c, restore());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->opts.fuse_xy = pick;
+  if (choice) *choice = pick;
+  if (ms_best) *ms_best = best;
+  return SCFFT_OK;
+}
+
 template <typename T>
 scfft_status region_impl(scfft_ctx* c, const T* h, const uint8_t* region, double* b) {
   double* part = wsp<double>(c, c->off_part);
@@ -1567,6 +1626,22 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
     if (ctx->ws) return ctx->prec == SCFFT_F64 ? upload_tables<double>(ctx) : upload_tables<float>(ctx);
   }
   return SCFFT_OK;
+}
+
+scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, int32_t* fuse_xy,
+                            double* ms_per_call) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  if (!h_dev || calls < 1) return fail(ctx, SCFFT_ERR_ARG, "invalid autotune arguments");
+  if (ctx->opts.fixed_iter <= 0)
+    return fail(ctx, SCFFT_ERR_ARG, "autotune times a fixed iteration count (fixed_iter > 0)");
+  int pick = 0;
+  st = ctx->prec == SCFFT_F64 ? autotune_impl<double>(ctx, (const double*)h_dev, calls, &pick, ms_per_call)
+                              : autotune_impl<float>(ctx, (const float*)h_dev, calls, &pick, ms_per_call);
+  if (st == SCFFT_OK && fuse_xy) *fuse_xy = pick;
+  return st;
 }
 
 scfft_status scfft_reset_warm(scfft_ctx* ctx) {

@@ -111,6 +111,7 @@ _SIGS = {
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
     "scfft_step_moment": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double)]),
+    "scfft_autotune": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "scfft_graph_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
     "scfft_integrate_graph": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, C.c_size_t, _P]),
     "scfft_integrate_wait": (C.c_int, [_P, C.POINTER(OdeStats)]),
@@ -365,6 +366,14 @@ def scfft_step_moment(ctx, omega_only=0):
     m = (C.c_double * 3)()
     _check(load().scfft_step_moment(ctx, int(omega_only), m), ctx)
     return np.array(m[:])
+
+
+def scfft_autotune(ctx, h, calls=5):
+    """Returns (fuse_xy chosen, ms per call)."""
+    fx = C.c_int32()
+    ms = C.c_double()
+    _check(load().scfft_autotune(ctx, _ptr(h), int(calls), C.byref(fx), C.byref(ms)), ctx)
+    return fx.value, ms.value
 
 
 def scfft_graph_workspace_size(ctx, steps):

@@ -118,3 +118,27 @@ def test_batched_contexts_on_streams():
     torch.cuda.synchronize()
     for a, b in zip(hs, alone):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+def test_autotune_schedule(prec):
+    """The autotuner picks one of the two schedules, keeps the warm start, and
+    the next call gives what an untuned context gives (both schedules are
+    pinned to the oracle)."""
+    cfg = CUBE32
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    h = to_dev(torch, state(cfg, seed=3), dt)
+    a = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=0)
+    b = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=0)
+    a.rhs_eval(0.01, h)
+    b.rhs_eval(0.01, h)
+    fx, ms = scfft.scfft_autotune(b.ctx, h, calls=3)
+    assert fx in (0, 2) and ms > 0.0
+    oa, _ = a.rhs_eval(0.011, h)                  # second call: from the warm start
+    ob, _ = b.rhs_eval(0.011, h)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == scfft.F64 else 1e-5
+    assert rel_max(ob.double().cpu().numpy(), oa.double().cpu().numpy()) < tol
+    s0 = sim(cfg, precision=prec)                 # adaptive iteration: refused
+    with pytest.raises(scfft.ScfftError):
+        scfft.scfft_autotune(s0.ctx, h)
