@@ -47,6 +47,7 @@ typedef enum {
   SCFFT_OK = 0,
   SCFFT_WARN_NOT_CONVERGED = 1, /* iteration (5) stopped at max_iter        */
   SCFFT_WARN_CLAMPED = 2,       /* power-law exponent clamped (overflow)    */
+  SCFFT_WARN_TOPOLOGY = 3,      /* Omega not contourwise simply connected   */
   SCFFT_ERR_ARG = -1,           /* invalid argument (NULL, range, order)    */
   SCFFT_ERR_SHAPE = -2,         /* unsupported grid size                    */
   SCFFT_ERR_DEVICE = -3,        /* HIP runtime error or no device           */
@@ -210,6 +211,16 @@ scfft_status scfft_drive_eval(const scfft_drive* d, const scfft_material* m, dou
 scfft_status scfft_voxelize_host(const scfft_grid* g, const scfft_material* m,
                                  const scfft_shape* shapes, int32_t n_shapes, uint8_t* mask);
 
+/* Topology of a mask [Nz][Ny][Nx] (nonzero = Omega), taken as the union of
+ * the closed voxels of its nodes in R^3: betti[0] components, betti[1]
+ * independent closed contours that bound no surface inside Omega, betti[2]
+ * enclosed cavities.  Sec. 2 restricts the method to contourwise simply
+ * connected domains (every closed contour in Omega bounds a surface in
+ * Omega), i.e. betti[1] = 0; otherwise the return is SCFFT_WARN_TOPOLOGY and
+ * the exterior problem loses the circulation of h around the holes.
+ * SCFFT_ERR_SHAPE for 2^31 - 1 nodes or more. */
+scfft_status scfft_mask_betti_host(const int32_t n[3], const uint8_t* mask, int64_t betti[3]);
+
 /* Bogacki-Shampine 3(2) with the step control of scfft_integrate, on host
  * arrays y[n] (in/out) with a host right-hand side; t in the caller's units.
  * The device integrator runs the same controller. */
@@ -231,10 +242,16 @@ scfft_status scfft_workspace_size(const scfft_ctx* ctx, size_t* bytes);
  * and warm start. */
 scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes);
 
-/* Voxelize Omega on the host and upload the mask (synchronous). */
+/* Voxelize Omega on the host and upload the mask (synchronous).  Returns
+ * SCFFT_WARN_TOPOLOGY (the mask is still set) when Omega is not contourwise
+ * simply connected (scfft_mask_betti_host). */
 scfft_status scfft_voxelize(scfft_ctx* ctx, const scfft_shape* shapes, int32_t n_shapes);
-/* Copy a caller's device mask uint8 [Nz][Ny][Nx] into the workspace. */
+/* Copy a caller's device mask uint8 [Nz][Ny][Nx] into the workspace; the
+ * same topology warning. */
 scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask);
+/* Betti numbers of the current mask, as scfft_mask_betti_host returns them;
+ * SCFFT_ERR_GEOMETRY without a mask. */
+scfft_status scfft_mask_betti(const scfft_ctx* ctx, int64_t betti[3]);
 /* Optional local critical density kappa = jc(x)/jc [Nz][Ny][Nx] in the
  * context precision, all > 0; NULL clears it (kappa = 1).  Copied. */
 scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa);

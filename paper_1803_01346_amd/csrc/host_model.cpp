@@ -1,4 +1,5 @@
 // Host-side model pieces: scaling of Eq. 8, applied-field drives, voxelizer.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -157,6 +158,112 @@ void voxelize(const int n[3], const double half_width_dimless[3], double l_m,
       }
     }
   }
+}
+
+// ---- topology of Omega ----------------------------------------------------
+// Omega is taken as the union K of the closed voxels of its nodes.  b0 counts
+// the components of K (voxels touching at a face, edge or corner connect);
+// b2 counts the bounded components of the complement (empty voxels connect
+// only through faces, the consistent pairing with the 26-neighbourhood, and
+// everything outside the grid belongs to the unbounded one); the Euler
+// characteristic chi = V - E + F - C of the cubical complex gives
+// b1 = b0 + b2 - chi, the number of independent closed contours in Omega that
+// bound no surface inside it.
+
+namespace {
+
+int find_root(std::vector<int32_t>& p, int32_t a) {
+  while (p[a] != a) {
+    p[a] = p[p[a]];
+    a = p[a];
+  }
+  return a;
+}
+
+void unite(std::vector<int32_t>& p, int32_t a, int32_t b) {
+  a = find_root(p, a);
+  b = find_root(p, b);
+  if (a != b) p[std::max(a, b)] = std::min(a, b);
+}
+
+// chi contribution of the cells whose lowest corner is the lattice point p,
+// indexed by the 2x2x2 block of voxels around p (bit dx + 2 dy + 4 dz for the
+// voxel at offset (dx - 1, dy - 1, dz - 1) from p): the vertex p, the three
+// edges leaving p upwards, the three faces and the cube with lowest corner p.
+// A cell belongs to K when any voxel containing it is filled.
+struct ChiTable {
+  int8_t v[256];
+  ChiTable() {
+    for (int c = 0; c < 256; ++c) {
+      auto any = [c](int need_x, int need_y, int need_z) {
+        for (int b = 0; b < 8; ++b) {
+          const int dx = b & 1, dy = (b >> 1) & 1, dz = (b >> 2) & 1;
+          if ((need_x && !dx) || (need_y && !dy) || (need_z && !dz)) continue;
+          if (c & (1 << b)) return 1;
+        }
+        return 0;
+      };
+      v[c] = (int8_t)(any(0, 0, 0) - any(1, 0, 0) - any(0, 1, 0) - any(0, 0, 1) + any(1, 1, 0) +
+                      any(1, 0, 1) + any(0, 1, 1) - any(1, 1, 1));
+    }
+  }
+};
+
+}  // namespace
+
+void mask_betti(const int n[3], const uint8_t* mask, int64_t betti[3]) {
+  const int nx = n[0], ny = n[1], nz = n[2];
+  const size_t nodes = (size_t)nx * ny * nz;
+  if (nodes >= (size_t)INT32_MAX) {
+    betti[0] = betti[1] = betti[2] = -1;
+    return;
+  }
+  auto at = [&](int x, int y, int z) -> int {
+    if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) return 0;
+    return mask[((size_t)z * ny + y) * nx + x] != 0;
+  };
+  // Euler characteristic
+  static const ChiTable table;
+  int64_t chi = 0;
+  for (int z = 0; z <= nz; ++z)
+    for (int y = 0; y <= ny; ++y)
+      for (int x = 0; x <= nx; ++x) {
+        int c = 0;
+        for (int b = 0; b < 8; ++b)
+          c |= at(x - 1 + (b & 1), y - 1 + ((b >> 1) & 1), z - 1 + ((b >> 2) & 1)) << b;
+        chi += table.v[c];
+      }
+  // components: one union-find over all voxels plus the outside (index nodes)
+  std::vector<int32_t> p(nodes + 1);
+  for (size_t i = 0; i <= nodes; ++i) p[i] = (int32_t)i;
+  const int32_t outside = (int32_t)nodes;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int32_t i = (int32_t)(((size_t)z * ny + y) * nx + x);
+        if (at(x, y, z)) {
+          // earlier 26-neighbours (13 of them) of a filled voxel
+          for (int dz = -1; dz <= 0; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                if (dz == 0 && (dy > 0 || (dy == 0 && dx >= 0))) continue;
+                if (at(x + dx, y + dy, z + dz))
+                  unite(p, i, (int32_t)(((size_t)(z + dz) * ny + (y + dy)) * nx + (x + dx)));
+              }
+        } else {
+          if (x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1) unite(p, i, outside);
+          if (x > 0 && !at(x - 1, y, z)) unite(p, i, i - 1);
+          if (y > 0 && !at(x, y - 1, z)) unite(p, i, i - nx);
+          if (z > 0 && !at(x, y, z - 1)) unite(p, i, i - nx * ny);
+        }
+      }
+  int64_t b0 = 0, b2 = 0;
+  const int32_t root_out = find_root(p, outside);
+  for (size_t i = 0; i < nodes; ++i)
+    if (p[i] == (int32_t)i && (int32_t)i != root_out) (mask[i] ? b0 : b2) += 1;
+  betti[0] = b0;
+  betti[1] = b0 + b2 - chi;
+  betti[2] = b2;
 }
 
 }  // namespace scfft

@@ -39,4 +39,9 @@ bool validate_shapes(const scfft_shape* shapes, int n, const char** why);
 void voxelize(const int n[3], const double half_width_dimless[3], double l_m,
               const scfft_shape* shapes, int n_shapes, uint8_t* mask);
 
+// Betti numbers (b0, b1, b2) of the union of the closed voxels of mask
+// [Nz][Ny][Nx] (nonzero = Omega), as a subset of R^3; all -1 when the grid
+// has 2^31 - 1 nodes or more.
+void mask_betti(const int n[3], const uint8_t* mask, int64_t betti[3]);
+
 }  // namespace scfft

@@ -55,6 +55,7 @@ struct scfft_ctx {
   bool has_mask = false, has_kappa = false, has_warm = false;
   int64_t n_in = 0, n_out = 0;
   int box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};  // index bounding box of Omega (x, y, z)
+  int64_t betti[3] = {0, 0, 0};                      // of the mask's voxel union
   std::string err;
   int64_t clamp_seen = 0;
   // integrator: state whose moment partials the last power-law pass recorded,
@@ -1391,7 +1392,8 @@ scfft_status set_mask_host(scfft_ctx* c, const std::vector<uint8_t>& m) {
   c->n_out = (int64_t)c->nodes - in;
   c->has_mask = true;
   c->has_warm = false;
-  return SCFFT_OK;
+  mask_betti(c->n, m.data(), c->betti);
+  return c->betti[1] > 0 ? SCFFT_WARN_TOPOLOGY : SCFFT_OK;
 }
 
 template <typename T>
@@ -1470,6 +1472,16 @@ scfft_status scfft_voxelize_host(const scfft_grid* g, const scfft_material* m,
   }
   voxelize(g->n, hw, m->l_char_m, shapes, n_shapes, mask);
   return SCFFT_OK;
+}
+
+scfft_status scfft_mask_betti_host(const int32_t n[3], const uint8_t* mask, int64_t betti[3]) {
+  if (!n || !mask || !betti) return SCFFT_ERR_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 1) return SCFFT_ERR_SHAPE;
+  if ((int64_t)n[0] * n[1] * n[2] >= (int64_t)INT32_MAX) return SCFFT_ERR_SHAPE;
+  const int nn[3] = {n[0], n[1], n[2]};
+  mask_betti(nn, mask, betti);
+  return betti[1] > 0 ? SCFFT_WARN_TOPOLOGY : SCFFT_OK;
 }
 
 scfft_status scfft_bs23_host(int64_t n, double* y, double t0, double t1, scfft_host_rhs f,
@@ -1642,6 +1654,13 @@ scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, in
                               : autotune_impl<float>(ctx, (const float*)h_dev, calls, &pick, ms_per_call);
   if (st == SCFFT_OK && fuse_xy) *fuse_xy = pick;
   return st;
+}
+
+scfft_status scfft_mask_betti(const scfft_ctx* ctx, int64_t betti[3]) {
+  if (!ctx || !betti) return SCFFT_ERR_ARG;
+  if (!ctx->has_mask) return SCFFT_ERR_GEOMETRY;
+  for (int a = 0; a < 3; ++a) betti[a] = ctx->betti[a];
+  return betti[1] > 0 ? SCFFT_WARN_TOPOLOGY : SCFFT_OK;
 }
 
 scfft_status scfft_reset_warm(scfft_ctx* ctx) {
@@ -1972,6 +1991,7 @@ const char* scfft_status_string(scfft_status s) {
     case SCFFT_OK: return "ok";
     case SCFFT_WARN_NOT_CONVERGED: return "warning: exterior iteration did not converge";
     case SCFFT_WARN_CLAMPED: return "warning: power-law exponent clamped";
+    case SCFFT_WARN_TOPOLOGY: return "warning: Omega is not contourwise simply connected";
     case SCFFT_ERR_ARG: return "invalid argument";
     case SCFFT_ERR_SHAPE: return "unsupported grid size";
     case SCFFT_ERR_DEVICE: return "device error";

@@ -9,6 +9,7 @@ sequences, device arrays are torch tensors or raw integer addresses).
 """
 import ctypes as C
 import os
+import warnings
 
 import numpy as np
 
@@ -19,6 +20,7 @@ LIB_PATH = os.environ.get("SCFFT_LIBRARY") or os.path.join(_HERE, "libscfft.so")
 OK = 0
 WARN_NOT_CONVERGED = 1
 WARN_CLAMPED = 2
+WARN_TOPOLOGY = 3
 ERR_ARG, ERR_SHAPE, ERR_DEVICE, ERR_WORKSPACE = -1, -2, -3, -4
 ERR_NAN, ERR_STEP_UNDERFLOW, ERR_GEOMETRY, ERR_STATE = -5, -6, -7, -8
 F64, F32 = 0, 1
@@ -97,6 +99,8 @@ _SIGS = {
     "scfft_set_workspace": (C.c_int, [_P, _P, C.c_size_t]),
     "scfft_voxelize": (C.c_int, [_P, C.POINTER(Shape), C.c_int32]),
     "scfft_set_mask": (C.c_int, [_P, _P]),
+    "scfft_mask_betti": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "scfft_mask_betti_host": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]),
     "scfft_set_jc_map": (C.c_int, [_P, _P]),
     "scfft_set_drive": (C.c_int, [_P, C.POINTER(Drive)]),
     "scfft_set_field_law": (C.c_int, [_P, C.c_double, C.c_double]),
@@ -298,6 +302,23 @@ def scfft_workspace_size(ctx):
 
 def scfft_set_workspace(ctx, ws, nbytes):
     return _check(load().scfft_set_workspace(ctx, _ptr(ws), int(nbytes)), ctx)
+
+
+def scfft_mask_betti_host(mask):
+    """(b0, b1, b2) of a host mask [Nz][Ny][Nx] (nonzero = Omega)."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if m.ndim != 3:
+        raise ValueError("mask must be 3-D [Nz][Ny][Nx]")
+    n = (C.c_int32 * 3)(m.shape[2], m.shape[1], m.shape[0])
+    b = (C.c_int64 * 3)()
+    _check(load().scfft_mask_betti_host(n, m.ctypes.data_as(C.POINTER(C.c_uint8)), b))
+    return tuple(int(v) for v in b)
+
+
+def scfft_mask_betti(ctx):
+    b = (C.c_int64 * 3)()
+    _check(load().scfft_mask_betti(ctx, b), ctx)
+    return tuple(int(v) for v in b)
 
 
 def scfft_voxelize(ctx, shapes, n_shapes):
@@ -511,7 +532,9 @@ class Simulation:
         aligned = (base + 255) // 256 * 256
         scfft_set_workspace(self.ctx, aligned, nbytes)
         self.shapes, self.n_shapes = make_shapes(cfg["shapes"], l)
-        scfft_voxelize(self.ctx, self.shapes, self.n_shapes)
+        if scfft_voxelize(self.ctx, self.shapes, self.n_shapes) == WARN_TOPOLOGY:
+            warnings.warn("Omega is not contourwise simply connected (Betti numbers %s): "
+                          "the method assumes it is" % (scfft_mask_betti(self.ctx),), stacklevel=2)
         d = dict(cfg["drive"])
         self.drive = make_drive(d.pop("kind"), **d)
         scfft_set_drive(self.ctx, self.drive)

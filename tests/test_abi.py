@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for s in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8):
+    for s in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, -7, -8):
         assert scfft.scfft_status_string(s) != "unknown status"
 
 
