@@ -208,55 +208,66 @@ def adjoint_leg(cfg, steps=2000, every=50):
     return out
 
 
-def graph_leg(count=16, steps=10):
-    """Launch-bound regime: the 32^3 cube alone, and a batch of independent
-    instances of mixed size (32^3 and 64^3 boxes), integrated with fixed steps
-    (3 exterior iterations) either one after another with per-kernel launches
-    or with graph-replayed steps, one stream per instance, all in flight at
-    once.  Aggregate right-hand-side evaluations per second."""
+def graph_leg(count=64, steps=4):
+    """Launch-bound and batched regimes: the 32^3 cube alone, and a batch of
+    independent instances of mixed size (boxes of 48 to 192 nodes per edge,
+    radix-3 lengths included), integrated with fixed steps (3 exterior
+    iterations) either one after another with per-kernel launches or with
+    graph-replayed steps, one stream per instance, all in flight at once.
+    Aggregate right-hand-side evaluations per second."""
     import torch
     from paper_1803_01346_amd import scfft, workloads
 
-    def plain(cfgs):
-        sims = [make_sim(c, scfft.F64, FIXED_ITER) for c in cfgs]
-        hs = [torch.from_numpy(workloads.synthetic_state(c, seed=i)).to("cuda") for i, c in enumerate(cfgs)]
-        o = scfft.default_ode_opts(fixed_steps=steps)
-        for s_, h in zip(sims, hs):
-            scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h.clone(), o)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for s_, h in zip(sims, hs):
-            scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h, o)
-        torch.cuda.synchronize()
-        return len(cfgs) * (1 + 3 * steps) / (time.perf_counter() - t)
-
-    def graphs(cfgs):
+    def setup(cfgs):
         streams = [torch.cuda.Stream() for _ in cfgs]
         sims = [scfft.Simulation(c, precision=scfft.F64, stream=st.cuda_stream,
                                  rhs_opts=scfft.default_rhs_opts(fixed_iter=FIXED_ITER))
                 for c, st in zip(cfgs, streams)]
-        hs = [torch.from_numpy(workloads.synthetic_state(c, seed=i)).to("cuda") for i, c in enumerate(cfgs)]
+        hs = [workloads.synthetic_state_torch(c, seed=i) for i, c in enumerate(cfgs)]
         wss = [scfft.device_buffer(scfft.scfft_graph_workspace_size(s_.ctx, steps)) for s_ in sims]
         torch.cuda.synchronize()
+        return streams, sims, hs, wss
 
+    def plain(sims, hs):
+        o = scfft.default_ode_opts(fixed_steps=steps)
+
+        def run(hh):
+            for s_, h in zip(sims, hh):
+                scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h, o)
+            torch.cuda.synchronize()
+        run([h.clone() for h in hs])
+        t = time.perf_counter()
+        run([h.clone() for h in hs])
+        return len(sims) * (1 + 3 * steps) / (time.perf_counter() - t)
+
+    def graphs(sims, hs, wss):
         def run(hh):
             for s_, h, ws in zip(sims, hh, wss):
                 scfft.scfft_integrate_graph(s_.ctx, 0.0, 1e-3, steps, ws, h)
             for s_ in sims:
                 scfft.scfft_integrate_wait(s_.ctx)
+            torch.cuda.synchronize()
         run([h.clone() for h in hs])
+        hh = [h.clone() for h in hs]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        run(hs)
-        torch.cuda.synchronize()
-        return len(cfgs) * (1 + 3 * steps) / (time.perf_counter() - t)
+        run(hh)
+        return len(sims) * (1 + 3 * steps) / (time.perf_counter() - t)
 
-    cube = [workloads.config("cube32")]
+    out = dict(steps=steps, exterior_iters=FIXED_ITER, dtype="f64", unit="RHS evals/s")
+    _, sims, hs, wss = setup([workloads.config("cube32")])
+    out["cube32"] = dict(plain=round(plain(sims, hs), 1), graph=round(graphs(sims, hs, wss), 1))
     batch = workloads.batch_instances(count)
-    out = dict(steps=steps, exterior_iters=FIXED_ITER, dtype="f64", unit="RHS evals/s",
-               cube32=dict(plain=round(plain(cube), 1), graph=round(graphs(cube), 1)),
-               batch=dict(instances=count, edges=sorted({c["n"][0] for c in batch}),
-                          plain=round(plain(batch), 1), graph_streams=round(graphs(batch), 1)))
+    t = time.perf_counter()
+    _, sims, hs, wss = setup(batch)
+    t_setup = time.perf_counter() - t
+    edges = sorted({c["n"][0] for c in batch})
+    out["batch"] = dict(instances=count, edges=edges,
+                        per_edge={str(e): sum(c["n"][0] == e for c in batch) for e in edges},
+                        setup_s=round(t_setup, 1),
+                        plain=round(plain(sims, hs), 1), graph_streams=round(graphs(sims, hs, wss), 1))
+    for s_ in sims:
+        s_.close()
     return out
 
 

@@ -61,7 +61,8 @@ typedef enum {
 typedef enum { SCFFT_F64 = 0, SCFFT_F32 = 1 } scfft_precision;
 
 /* Grid of the padded FFT box D.  n[a] = node counts (x, y, z): each a power
- * of two in [8, 512].  half_width_m[a] = L_a in metres.  Sec. 2. */
+ * of two in [8, 512] or 3 * 2^k in [24, 192] (24, 48, 96, 192).
+ * half_width_m[a] = L_a in metres.  Sec. 2. */
 typedef struct {
   int32_t n[3];
   double half_width_m[3];

@@ -10,6 +10,8 @@
 // radices.  After the last pass that position is again v[q + r * E/R], so
 // the final pass needs no exchange.
 //
+// Lengths are powers of two or three times a power of two.
+//
 // Forward transforms use exp(-2 pi i k / N) (the paper's sign, Sec. 2 text
 // before Eq. 7); the inverse is conj(forward(conj(x))), unnormalised.
 #pragma once
@@ -36,7 +38,7 @@ __device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
 template <typename T>
 __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
 
-// ---- in-register DFTs of radix 2, 4, 8 (forward sign) ----
+// ---- in-register DFTs of radix 2, 3, 4, 8 (forward sign) ----
 
 template <typename T>
 __device__ __forceinline__ void dft2(C2<T>* v) {
@@ -78,27 +80,64 @@ __device__ __forceinline__ void dft8(C2<T>* v) {
   v[7] = e3 - t3;
 }
 
+// w3 = exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2:
+//   y0 = a + (b + c),  y1,2 = a - (b + c)/2 -/+ i sqrt(3)/2 (b - c)
+template <typename T>
+__device__ __forceinline__ void dft3(C2<T>* v) {
+  const T h = T(0.86602540378443864676372317075293618);
+  const C2<T> s = v[1] + v[2], d = v[1] - v[2];
+  const C2<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+  const C2<T> r = {h * d.y, -h * d.x};  // -i sqrt(3)/2 (b - c)
+  v[0] = v[0] + s;
+  v[1] = m + r;
+  v[2] = m - r;
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dftR(C2<T>* v) {
   if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3(v);
   else if constexpr (R == 4) dft4(v);
   else if constexpr (R == 8) dft8(v);
-  else static_assert(R == 2 || R == 4 || R == 8, "radix");
+  else static_assert(R == 2 || R == 3 || R == 4 || R == 8, "radix");
 }
 
 // ---- pass plan: radices for length N with E elements per thread ----
 
-__host__ __device__ constexpr int elems_per_thread(int n, int emax = 8) { return n >= emax ? emax : n; }
+// Lengths are 2^k or 3 * 2^k.  A length 3 * 2^k runs one radix-3 pass and
+// then radix-2^j passes; its threads hold 3 * E2 elements, E2 = emax / 2
+// (at least 2, at most the power-of-two factor), so that 3 and every later
+// radix divide E.
+__host__ __device__ constexpr int elems_per_thread(int n, int emax = 8) {
+  if (n % 3 == 0) {
+    int e2 = emax / 2 < 2 ? 2 : emax / 2;
+    if (e2 > n / 3) e2 = n / 3;
+    return 3 * e2;
+  }
+  return n >= emax ? emax : n;
+}
 
-// radix of pass p (0-based) for length N with E per thread: E while the
-// remaining factor allows, then the remainder.
+// radix of pass p (0-based) for length N with E per thread: for 3 * 2^k a
+// radix-3 pass first; then E (E / 3) while the remaining factor allows, then
+// the remainder.
 __host__ __device__ constexpr int pass_radix(int n, int e, int p) {
+  if (n % 3 == 0) {
+    if (p == 0) return 3;
+    n /= 3;
+    e /= 3;
+    --p;
+  }
   int rem = n;
   for (int i = 0; i < p; ++i) rem /= (rem >= e ? e : rem);
   return rem >= e ? e : rem;
 }
 __host__ __device__ constexpr int pass_count(int n, int e) {
   int c = 0;
+  if (n % 3 == 0) {
+    n /= 3;
+    e /= 3;
+    c = 1;
+  }
   for (int rem = n; rem > 1; rem /= (rem >= e ? e : rem)) ++c;
   return c;
 }
@@ -125,7 +164,7 @@ __device__ __forceinline__ void stockham_pass(C2<T> (&v)[E], int j, Lds& lds,
     C2<T> a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[q + r * Q];
-    const int kk = b & (NS - 1);
+    const int kk = b % NS;
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tw[(r * kk * (N / (NS * R))) * tws]);

@@ -312,7 +312,7 @@ __global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SC
 #pragma unroll
         for (int m = 0; m < E; ++m) {
           const int kz = j + m * TPT;
-          const C2<T> w = cconj(smem[((NZ - kz) & (NZ - 1)) * COLS + col]);
+          const C2<T> w = cconj(smem[(kz == 0 ? 0 : NZ - kz) * COLS + col]);
           v[c][m] = {fa[m] * v[c][m].x + fb[m] * w.x, fa[m] * v[c][m].y + fb[m] * w.y};
         }
       }
@@ -410,6 +410,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   constexpr int E = elems_per_thread(M, ex_max<T, NC, OP>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
+  static_assert(2 * E <= 32, "store masks hold one bit per node");
   constexpr bool HAS_INV = OP != X_FWD && OP != X_ADJ_START;
   constexpr bool HAS_FWD = OP == X_FWD || OP == X_LAW || OP == X_HIN || OP == X_MASK ||
                            OP == X_UPDATE || OP >= X_ADJ_START;
@@ -835,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int k = j + m * TPT;
-        const C2<T> pc = cconj(lds.load((M - k) & (M - 1)));   // conj Z[M-k], Z[M] = Z[0]
+        const C2<T> pc = cconj(lds.load(k == 0 ? 0 : M - k));   // conj Z[M-k], Z[M] = Z[0]
         const C2<T> s = Z[m] + pc, d = Z[m] - pc;
         const C2<T> ev = {T(0.5) * s.x, T(0.5) * s.y};         // E[k]
         const C2<T> od = {T(0.5) * d.y, T(-0.5) * d.x};        // O[k] = d / (2i)
@@ -873,6 +874,10 @@ int xpass_blocks(const Plan<T>& p) {
     case 128: return xblocks_n<T, 128>(p);
     case 256: return xblocks_n<T, 256>(p);
     case 512: return xblocks_n<T, 512>(p);
+    case 24: return xblocks_n<T, 24>(p);
+    case 48: return xblocks_n<T, 48>(p);
+    case 96: return xblocks_n<T, 96>(p);
+    case 192: return xblocks_n<T, 192>(p);
   }
   return -1;
 }
@@ -939,6 +944,10 @@ hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t
     case 128: return xlaunch_n<T, 128>(p, op, a, s, t);
     case 256: return xlaunch_n<T, 256>(p, op, a, s, t);
     case 512: return xlaunch_n<T, 512>(p, op, a, s, t);
+    case 24: return xlaunch_n<T, 24>(p, op, a, s, t);
+    case 48: return xlaunch_n<T, 48>(p, op, a, s, t);
+    case 96: return xlaunch_n<T, 96>(p, op, a, s, t);
+    case 192: return xlaunch_n<T, 192>(p, op, a, s, t);
   }
   return hipErrorInvalidValue;
 }
@@ -969,6 +978,10 @@ hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
     case 128: return ylaunch_n<T, 128>(p, inv, s, t);
     case 256: return ylaunch_n<T, 256>(p, inv, s, t);
     case 512: return ylaunch_n<T, 512>(p, inv, s, t);
+    case 24: return ylaunch_n<T, 24>(p, inv, s, t);
+    case 48: return ylaunch_n<T, 48>(p, inv, s, t);
+    case 96: return ylaunch_n<T, 96>(p, inv, s, t);
+    case 192: return ylaunch_n<T, 192>(p, inv, s, t);
   }
   return hipErrorInvalidValue;
 }
@@ -1007,6 +1020,10 @@ hipError_t launch_zpass(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime 
     case 128: return zlaunch_n<T, 128>(p, sym, coef, s, t);
     case 256: return zlaunch_n<T, 256>(p, sym, coef, s, t);
     case 512: return zlaunch_n<T, 512>(p, sym, coef, s, t);
+    case 24: return zlaunch_n<T, 24>(p, sym, coef, s, t);
+    case 48: return zlaunch_n<T, 48>(p, sym, coef, s, t);
+    case 96: return zlaunch_n<T, 96>(p, sym, coef, s, t);
+    case 192: return zlaunch_n<T, 192>(p, sym, coef, s, t);
   }
   return hipErrorInvalidValue;
 }

@@ -26,7 +26,12 @@ constexpr int kProbeChunk = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+// FFT lengths: powers of two in [8, 512] and 3 * 2^k in [24, 192].
+bool fft_length_supported(int n) {
+  auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (n % 3 == 0) return pow2(n / 3) && n >= 24 && n <= 192;
+  return pow2(n) && n >= 8 && n <= 512;
+}
 
 }  // namespace
 
@@ -1506,7 +1511,7 @@ scfft_status scfft_create(scfft_ctx** out, const scfft_grid* g, const scfft_mate
   if (!validate_material(*m, &why)) return SCFFT_ERR_ARG;
   if (prec != SCFFT_F64 && prec != SCFFT_F32) return SCFFT_ERR_ARG;
   for (int a = 0; a < 3; ++a) {
-    if (!pow2_in_range(g->n[a])) return SCFFT_ERR_SHAPE;
+    if (!fft_length_supported(g->n[a])) return SCFFT_ERR_SHAPE;
     if (!(g->half_width_m[a] > 0.0) || !std::isfinite(g->half_width_m[a])) return SCFFT_ERR_ARG;
   }
   int dev = -1;

@@ -97,11 +97,12 @@ def config(name):
     return CONFIGS[name]
 
 
-def batch_instances(count=16, seed=4, edges=(32, 64)):
-    """Independent instances of mixed size for batched runs: grid edge drawn
-    from `edges`, body (cube, solid cylinder or cup, half the box wide) with
-    l = its half size, n ~ U[10, 100], log10 jc ~ U[7, 9], a ramp to
-    U[0.01, 0.2] T along a random direction.  Returns configuration dicts."""
+def batch_instances(count=64, seed=4, edges=(48, 64, 96, 128, 192)):
+    """Independent instances of mixed size for batched runs: box edge drawn
+    from `edges` (the body spans half of it: 24 to 96 voxels across), body
+    (cube, solid cylinder or cup) with l = its half size, n ~ U[10, 100],
+    log10 jc ~ U[7, 9], a ramp to U[0.01, 0.2] T along a random direction.
+    Returns configuration dicts."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -159,6 +160,40 @@ def smooth_field(n, half_width, seed=0, n_modes=12, max_index=None, j_target=1.0
     jmax = float(np.sqrt(np.max(np.sum(cj * cj, axis=0))))
     scale = j_target / jmax if jmax > 0 else 1.0
     return dh * scale, cj * scale
+
+
+def synthetic_state_torch(cfg, seed=0, background=(0.0, 0.0, 0.0), n_modes=12, device="cuda"):
+    """synthetic_state evaluated with torch on a device (the same modes,
+    drawn from the same numpy generator; equal up to rounding): for large
+    grids, where the host evaluation takes seconds."""
+    import torch
+    nx, ny, nz = (int(v) for v in cfg["n"])
+    hw = cfg["half_width"]
+    rng = np.random.default_rng(seed)
+    max_index = (max(1, nx // 8), max(1, ny // 8), max(1, nz // 8))
+    f64 = dict(dtype=torch.float64, device=device)
+    ix = torch.arange(nx, **f64).view(1, 1, nx)
+    iy = torch.arange(ny, **f64).view(1, ny, 1)
+    iz = torch.arange(nz, **f64).view(nz, 1, 1)
+    dh = torch.zeros((3, nz, ny, nx), **f64)
+    cj = torch.zeros((3, nz, ny, nx), **f64)
+    for _ in range(n_modes):
+        m = [int(rng.integers(-mi, mi + 1)) for mi in max_index]
+        if m == [0, 0, 0]:
+            m[0] = 1
+        a = rng.normal(size=3)
+        p = rng.uniform(0.0, 2.0 * np.pi)
+        ph = 2.0 * np.pi * (m[0] * ix / nx + m[1] * iy / ny + m[2] * iz / nz) + p
+        c, sn = torch.cos(ph), torch.sin(ph)
+        k = np.array([np.pi * m[0] / hw[0], np.pi * m[1] / hw[1], np.pi * m[2] / hw[2]])
+        kxa = np.cross(k, a)
+        for comp in range(3):
+            dh[comp] += float(a[comp]) * c
+            cj[comp] -= float(kxa[comp]) * sn
+    jmax = float(torch.sqrt(torch.max(torch.sum(cj * cj, dim=0))))
+    scale = 1.05 / jmax if jmax > 0 else 1.0
+    b = torch.tensor(background, **f64).view(3, 1, 1, 1)
+    return dh * scale + b
 
 
 def synthetic_state(name_or_cfg, seed=0, background=(0.0, 0.0, 0.0), n=None, **kw):

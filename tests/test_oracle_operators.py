@@ -24,9 +24,15 @@ def _mode_field(g, m, amp, fn):
     return k, np.stack([a * fn(ph) for a in amp]), ph
 
 
+# grids of power-of-two and of 3 * 2^k lengths (the latter transformed by the
+# direct DFT along each axis)
+GRIDS = [(32, 16, 64), (48, 24, 96)]
+
+
+@pytest.mark.parametrize("n", GRIDS)
 @pytest.mark.parametrize("m", [(3, 0, 0), (0, 2, 0), (0, 0, 5), (1, -2, 3)])
-def test_curl_single_mode(m):
-    g = grid.Grid((32, 16, 64), (2.0, 1.0, 3.0))
+def test_curl_single_mode(m, n):
+    g = grid.Grid(n, (2.0, 1.0, 3.0))
     a = np.array([0.3, -1.1, 0.7])
     k, h, ph = _mode_field(g, m, a, np.sin)
     got = operators.curl_s(h, g)
@@ -47,10 +53,11 @@ def test_curl_x_mode_matches_paper_orientation():
     assert np.max(np.abs(got[1] + k0 * np.cos(k0 * x) * s)) < 1e-12
 
 
+@pytest.mark.parametrize("n", GRIDS)
 @pytest.mark.parametrize("m", [(3, 0, 0), (0, 2, 0), (0, 0, 5), (2, 1, -3)])
-def test_phi_single_mode(m):
+def test_phi_single_mode(m, n):
     # j = b cos(k.r) -> Phi[j] = -(k x b) sin(k.r) / |k|^2  (unsmoothed)
-    g = grid.Grid((32, 16, 64), (2.0, 1.0, 3.0))
+    g = grid.Grid(n, (2.0, 1.0, 3.0))
     b = np.array([1.0, 0.4, -0.6])
     k, j, ph = _mode_field(g, m, b, np.cos)
     got = operators.phi(j, g)
