@@ -313,7 +313,11 @@ scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, in
  * accepts no other call (SCFFT_ERR_STATE), h and the graph workspace must
  * stay allocated, and contexts on different streams run concurrently (the
  * batched use).  graph_ws: device buffer of scfft_graph_workspace_size bytes,
- * 256-byte aligned, owned by the caller. */
+ * 256-byte aligned, owned by the caller.  The captured graphs stay with the
+ * context and are replayed by the next call with the same graph_ws, steps and
+ * step size (a run continued chunk by chunk pays the capture once); any call
+ * that changes the mask, jc map, field law, drive, options or workspace
+ * forces a new capture. */
 scfft_status scfft_graph_workspace_size(const scfft_ctx* ctx, int32_t steps, size_t* bytes);
 scfft_status scfft_integrate_graph(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
                                    void* graph_ws, size_t graph_bytes, void* h_dev);

@@ -78,6 +78,17 @@ struct scfft_ctx {
   double field_hk_inv = 0.0, field_alpha = 0.0;  // e(j, h): 1/h_K (dimensionless), exponent
   bool graph_busy = false;          // an integration is enqueued; scfft_integrate_wait ends it
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  // Captured step graphs are kept for the next graph integration with the same
+  // workspace, step count and step size; every call that changes what the
+  // kernels are launched with (mask, jc map, field law, options, drive,
+  // workspace) bumps the epoch and so forces a new capture.
+  uint64_t epoch = 1;
+  struct {
+    const char* gws = nullptr;
+    int steps = 0;
+    double dt = 0.0;
+    uint64_t epoch = 0;
+  } graph_key;
   std::vector<double> graph_hedot;  // host copy of the rate table (alive until the wait)
   char* graph_ws = nullptr;
   int graph_steps = 0;
@@ -1178,47 +1189,64 @@ scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* 
   HIPCHK(c, hipMemcpyAsync(buf[B_Y], h, fb, hipMemcpyDeviceToDevice, c->stream));
   scfft_status st = rhs_impl<T>(c, t0, buf[B_Y], buf[B_K1], nullptr);
   if (st < 0) return st;
-  // capture one step for each parity of the buffer roles (accepting a step swaps Y/Y1, K1/K4)
-  hipStream_t cs = nullptr;
-  HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  const hipStream_t saved = c->stream;
-  const bool saved_prof = c->prof;
-  c->stream = cs;
-  c->prof = false;
-  c->graph_stop = &gs->stop;
-  c->g_hedot_tab = tab;
-  c->g_hedot_step = &gs->step;
-  T* r[6];
-  for (int k = 0; k < 6; ++k) r[k] = buf[k];
+  // capture one step for each parity of the buffer roles (accepting a step
+  // swaps Y/Y1, K1/K4), unless the graphs of the last integration still fit:
+  // chunks of equal length give step sizes equal up to the rounding of
+  // (t1 - t0) / steps, and the captured step size is kept
+  const bool cached = c->graph_exec[0] && c->graph_exec[1] && c->graph_key.gws == gws &&
+                      c->graph_key.steps == steps && c->graph_key.epoch == c->epoch &&
+                      std::fabs(c->graph_key.dt - dt) <= 1e-12 * std::fabs(dt);
   st = SCFFT_OK;
-  for (int par = 0; par < 2 && st == SCFFT_OK; ++par) {
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) {
-      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
-      break;
+  if (!cached) {
+    for (auto& x : c->graph_exec)
+      if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+    c->graph_key.epoch = 0;
+    hipStream_t cs = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const hipStream_t saved = c->stream;
+    const bool saved_prof = c->prof;
+    c->stream = cs;
+    c->prof = false;
+    c->graph_stop = &gs->stop;
+    c->g_hedot_tab = tab;
+    c->g_hedot_step = &gs->step;
+    T* r[6];
+    for (int k = 0; k < 6; ++k) r[k] = buf[k];
+    for (int par = 0; par < 2 && st == SCFFT_OK; ++par) {
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) {
+        st = fail(c, SCFFT_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        break;
+      }
+      const scfft_status sst = graph_step<T>(c, r, dt, gs, err, hist);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);
+      if (sst < 0) {
+        st = sst;
+      } else if (e != hipSuccess) {
+        st = fail(c, SCFFT_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      } else {
+        e = hipGraphInstantiate(&c->graph_exec[par], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = fail(c, SCFFT_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      if (g) (void)hipGraphDestroy(g);
+      std::swap(r[B_Y], r[B_Y1]);
+      std::swap(r[B_K1], r[B_K4]);
     }
-    const scfft_status sst = graph_step<T>(c, r, dt, gs, err, hist);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(cs, &g);
-    if (sst < 0) {
-      st = sst;
-    } else if (e != hipSuccess) {
-      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    } else {
-      e = hipGraphInstantiate(&c->graph_exec[par], g, nullptr, nullptr, 0);
-      if (e != hipSuccess) st = fail(c, SCFFT_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    c->stream = saved;
+    c->prof = saved_prof;
+    c->graph_stop = nullptr;
+    c->g_hedot_tab = nullptr;
+    c->g_hedot_step = nullptr;
+    c->g_hedot_stage = 0;
+    (void)hipStreamDestroy(cs);
+    if (st == SCFFT_OK) {
+      c->graph_key.gws = gws;
+      c->graph_key.steps = steps;
+      c->graph_key.dt = dt;
+      c->graph_key.epoch = c->epoch;
     }
-    if (g) (void)hipGraphDestroy(g);
-    std::swap(r[B_Y], r[B_Y1]);
-    std::swap(r[B_K1], r[B_K4]);
   }
-  c->stream = saved;
-  c->prof = saved_prof;
-  c->graph_stop = nullptr;
-  c->g_hedot_tab = nullptr;
-  c->g_hedot_step = nullptr;
-  c->g_hedot_stage = 0;
-  (void)hipStreamDestroy(cs);
   if (st == SCFFT_OK) {
     for (int s = 0; s < steps; ++s) {
       const hipError_t e = hipGraphLaunch(c->graph_exec[s & 1], c->stream);
@@ -1232,6 +1260,7 @@ scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* 
     (void)hipStreamSynchronize(c->stream);
     for (auto& x : c->graph_exec)
       if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+    c->graph_key.epoch = 0;
     return st;
   }
   c->graph_busy = true;
@@ -1249,8 +1278,6 @@ scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
   GraphState hs{0, 0, -1, 0};
   hipError_t e = hipMemcpyAsync(&hs, c->graph_ws + L.off_state, sizeof hs, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  for (auto& x : c->graph_exec)
-    if (x) (void)hipGraphExecDestroy(x), x = nullptr;
   c->graph_busy = false;
   if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "graph integration: %s", hipGetErrorString(e));
   // the last accepted state is in the Y buffer of the parity of the next (or failed) step
@@ -1332,6 +1359,7 @@ scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, dou
   HIPCHK(c, restore());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->opts.fuse_xy = pick;
+  ++c->epoch;
   if (choice) *choice = pick;
   if (ms_best) *ms_best = best;
   return SCFFT_OK;
@@ -1397,6 +1425,7 @@ scfft_status set_mask_host(scfft_ctx* c, const std::vector<uint8_t>& m) {
   c->n_out = (int64_t)c->nodes - in;
   c->has_mask = true;
   c->has_warm = false;
+  ++c->epoch;
   mask_betti(c->n, m.data(), c->betti);
   return c->betti[1] > 0 ? SCFFT_WARN_TOPOLOGY : SCFFT_OK;
 }
@@ -1556,6 +1585,7 @@ scfft_status scfft_workspace_size(const scfft_ctx* ctx, size_t* bytes) {
 scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
   if (!dev_ptr) return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace pointer is NULL");
   if (bytes < ctx->total)
     return fail(ctx, SCFFT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, ctx->total);
@@ -1595,6 +1625,7 @@ scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask) {
 scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!dev_kappa) {
@@ -1610,6 +1641,7 @@ scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
 scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
   if (!ctx || !d) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
   const char* why = nullptr;
   Drive dr;
   if (!dr.set(*d, ctx->u, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
@@ -1621,6 +1653,7 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
 scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
   if (!(b0_T >= 0.0) || !(alpha >= 0.0) || !std::isfinite(b0_T) || !std::isfinite(alpha))
     return fail(ctx, SCFFT_ERR_ARG, "field law needs b0_T >= 0 and alpha >= 0");
   // |B| / B0 = mu0 h_scale |h'| / B0 with h' the dimensionless field (Eq. 8)
@@ -1632,6 +1665,7 @@ scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   if (!ctx || !o) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
       !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2)
     return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");

@@ -142,3 +142,36 @@ def test_autotune_schedule(prec):
     s0 = sim(cfg, precision=prec)                 # adaptive iteration: refused
     with pytest.raises(scfft.ScfftError):
         scfft.scfft_autotune(s0.ctx, h)
+
+
+def test_graph_reuse_across_calls_and_state_changes():
+    """Consecutive graph integrations with the same workspace, step count and
+    step size replay the graphs of the first; after a state change (here the
+    rhs options: another exterior iteration count) the graphs are captured
+    again.  Every result equals the plain fixed-step integrator's."""
+    cfg = CUBE32
+    dt = torch.float64
+    h0 = to_dev(torch, state(cfg, seed=5, bg=(0.0, 0.01, 0.02)), dt)
+    steps, chunk = 3, 0.005
+    g = sim(cfg, fixed_iter=2)
+    p = sim(cfg, fixed_iter=2)
+    ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(g.ctx, steps))
+    hg, hp = h0.clone(), h0.clone()
+    o = scfft.default_ode_opts(fixed_steps=steps)
+    for k in range(3):                                    # the same chunk length three times
+        t0, t1 = k * chunk, (k + 1) * chunk
+        scfft.scfft_integrate_graph(g.ctx, t0, t1, steps, ws, hg)
+        scfft.scfft_integrate_wait(g.ctx, scfft.OdeStats())
+        scfft.scfft_integrate(p.ctx, t0, t1, hp, o)
+        torch.cuda.synchronize()
+        assert rel_max(hg.cpu().numpy(), hp.cpu().numpy()) < 1e-12, k
+    for s_ in (g, p):
+        scfft.scfft_set_rhs_opts(s_.ctx, scfft.default_rhs_opts(fixed_iter=3))
+    scfft.scfft_integrate_graph(g.ctx, 3 * chunk, 4 * chunk, steps, ws, hg)
+    st = scfft.OdeStats()
+    scfft.scfft_integrate_wait(g.ctx, st)
+    sp = scfft.OdeStats()
+    scfft.scfft_integrate(p.ctx, 3 * chunk, 4 * chunk, hp, o, stats=sp)
+    torch.cuda.synchronize()
+    assert rel_max(hg.cpu().numpy(), hp.cpu().numpy()) < 1e-12
+    assert st.iters_total == sp.iters_total == sp.rhs_calls * 3
