@@ -213,7 +213,8 @@ def graph_leg(count=64, steps=4):
     independent instances of mixed size (boxes of 48 to 192 nodes per edge,
     radix-3 lengths included), integrated with fixed steps (3 exterior
     iterations) either one after another with per-kernel launches or with
-    graph-replayed steps, one stream per instance, all in flight at once.
+    graph-replayed steps, one stream per instance, all in flight at once;
+    each instance's pass schedule is picked by the autotuner first.
     Aggregate right-hand-side evaluations per second."""
     import torch
     from paper_1803_01346_amd import scfft, workloads
@@ -226,7 +227,9 @@ def graph_leg(count=64, steps=4):
         hs = [workloads.synthetic_state_torch(c, seed=i) for i, c in enumerate(cfgs)]
         wss = [scfft.device_buffer(scfft.scfft_graph_workspace_size(s_.ctx, steps)) for s_ in sims]
         torch.cuda.synchronize()
-        return streams, sims, hs, wss
+        # the schedule autotuner picks row/column or fused plane passes per instance
+        picks = [scfft.scfft_autotune(s_.ctx, h, calls=3)[0] for s_, h in zip(sims, hs)]
+        return streams, sims, hs, wss, picks
 
     def plain(sims, hs):
         o = scfft.default_ode_opts(fixed_steps=steps)
@@ -255,19 +258,56 @@ def graph_leg(count=64, steps=4):
         return len(sims) * (1 + 3 * steps) / (time.perf_counter() - t)
 
     out = dict(steps=steps, exterior_iters=FIXED_ITER, dtype="f64", unit="RHS evals/s")
-    _, sims, hs, wss = setup([workloads.config("cube32")])
-    out["cube32"] = dict(plain=round(plain(sims, hs), 1), graph=round(graphs(sims, hs, wss), 1))
+    _, sims, hs, wss, picks = setup([workloads.config("cube32")])
+    out["cube32"] = dict(plain=round(plain(sims, hs), 1), graph=round(graphs(sims, hs, wss), 1),
+                         fuse_xy=picks[0])
     batch = workloads.batch_instances(count)
     t = time.perf_counter()
-    _, sims, hs, wss = setup(batch)
+    _, sims, hs, wss, picks = setup(batch)
     t_setup = time.perf_counter() - t
     edges = sorted({c["n"][0] for c in batch})
     out["batch"] = dict(instances=count, edges=edges,
                         per_edge={str(e): sum(c["n"][0] == e for c in batch) for e in edges},
-                        setup_s=round(t_setup, 1),
+                        setup_s=round(t_setup, 1), fused_plane_picks=int(sum(x == 2 for x in picks)),
                         plain=round(plain(sims, hs), 1), graph_streams=round(graphs(sims, hs, wss), 1))
     for s_ in sims:
         s_.close()
+    return out
+
+
+def lens_gain_leg(n_grid=128):
+    """The lens of Sec. 3 as the paper runs it (n = 30, rho_out = 100, field
+    along the axis h_e' = t', virgin start, adaptive steps and the stopping
+    rule of the exterior iteration) on the slit-lens stand-in geometry
+    (straight bore, FP64): the field-concentration factor, mean |B| over the
+    central region {r <= 0.2, |z| <= 0.33} over the applied B, at h_e' = 0.05
+    and 0.2 (the paper's biconical lens: about 2 and 1.6)."""
+    import numpy as np
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    mu0 = 4e-7 * np.pi
+    l, jc, e0 = 0.015, 5e8, 1e-4
+    t0 = mu0 * jc * l * l / e0
+    cfg = dict(n=(n_grid,) * 3, l_m=l, half_width=(2.0,) * 3, shapes=workloads.shape_lens(),
+               n_power=30.0, jc=jc, e0=e0, rho_out=100.0,
+               drive=dict(kind="ramp_hold", direction=(0.0, 0.0, 1.0), amp_T=0.2 * mu0 * jc * l,
+                          t_ramp_s=0.2 * t0))
+    s = scfft.Simulation(cfg, precision=scfft.F64)
+    x = -2.0 + (np.arange(n_grid) + 0.5) * (4.0 / n_grid)
+    r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2)
+    region = torch.from_numpy(((r <= 0.2) & (np.abs(x)[:, None, None] <= 0.33)).astype(np.uint8)).cuda()
+    h = s.empty_field()
+    scfft.scfft_init_state(s.ctx, 0.0, h)
+    out, t, steps, rhs = dict(grid=[n_grid] * 3, dtype="f64", n_power=30.0, rho_out=100.0), 0.0, 0, 0
+    wall = time.perf_counter()
+    for he in (0.05, 0.2):
+        st = scfft.OdeStats()
+        scfft.scfft_integrate(s.ctx, t, he * t0, h, scfft.default_ode_opts(), stats=st)
+        out["gain_%.2f" % he] = round(scfft.scfft_region_mean_abs_b(s.ctx, h, region) / (he * mu0 * jc * l), 3)
+        steps, rhs, t = steps + st.accepted, rhs + st.rhs_calls, he * t0
+    out.update(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2),
+               paper_biconical=dict(gain_0_05=2.0, gain_0_2=1.6))
+    s.close()
     return out
 
 
@@ -317,6 +357,7 @@ def main():
     ap.add_argument("--no-lens", action="store_true", help="skip the 256^3 FP32 lens leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
+    ap.add_argument("--no-lens-gain", action="store_true", help="skip the lens field-concentration run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -386,6 +427,7 @@ def main():
     lens = None if args.no_lens else lens256_leg()
     adj = None if args.no_adjoint else adjoint_leg(cfg)
     gleg = None if args.no_graph else graph_leg()
+    lgain = None if args.no_lens_gain else lens_gain_leg()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -415,6 +457,7 @@ def main():
         "lens256_f32": lens,
         "adjoint_cost": adj,
         "graphs": gleg,
+        "lens_gain": lgain,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,
