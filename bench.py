@@ -275,11 +275,11 @@ def graph_leg(count=64, steps=4):
     return out
 
 
-def lens_gain_leg(n_grid=128):
+def lens_gain_leg(n_grid=128, f32=False):
     """The lens of Sec. 3 as the paper runs it (n = 30, rho_out = 100, field
     along the axis h_e' = t', virgin start, adaptive steps and the stopping
     rule of the exterior iteration) on the slit-lens stand-in geometry
-    (straight bore, FP64): the field-concentration factor, mean |B| over the
+    (straight bore): the field-concentration factor, mean |B| over the
     central region {r <= 0.2, |z| <= 0.33} over the applied B, at h_e' = 0.05
     and 0.2 (the paper's biconical lens: about 2 and 1.6)."""
     import numpy as np
@@ -292,21 +292,20 @@ def lens_gain_leg(n_grid=128):
                n_power=30.0, jc=jc, e0=e0, rho_out=100.0,
                drive=dict(kind="ramp_hold", direction=(0.0, 0.0, 1.0), amp_T=0.2 * mu0 * jc * l,
                           t_ramp_s=0.2 * t0))
-    s = scfft.Simulation(cfg, precision=scfft.F64)
+    s = scfft.Simulation(cfg, precision=scfft.F32 if f32 else scfft.F64)
     x = -2.0 + (np.arange(n_grid) + 0.5) * (4.0 / n_grid)
     r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2)
     region = torch.from_numpy(((r <= 0.2) & (np.abs(x)[:, None, None] <= 0.33)).astype(np.uint8)).cuda()
     h = s.empty_field()
     scfft.scfft_init_state(s.ctx, 0.0, h)
-    out, t, steps, rhs = dict(grid=[n_grid] * 3, dtype="f64", n_power=30.0, rho_out=100.0), 0.0, 0, 0
+    out, t, steps, rhs = dict(dtype="f32" if f32 else "f64"), 0.0, 0, 0
     wall = time.perf_counter()
     for he in (0.05, 0.2):
         st = scfft.OdeStats()
         scfft.scfft_integrate(s.ctx, t, he * t0, h, scfft.default_ode_opts(), stats=st)
         out["gain_%.2f" % he] = round(scfft.scfft_region_mean_abs_b(s.ctx, h, region) / (he * mu0 * jc * l), 3)
         steps, rhs, t = steps + st.accepted, rhs + st.rhs_calls, he * t0
-    out.update(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2),
-               paper_biconical=dict(gain_0_05=2.0, gain_0_2=1.6))
+    out.update(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2))
     s.close()
     return out
 
@@ -427,7 +426,10 @@ def main():
     lens = None if args.no_lens else lens256_leg()
     adj = None if args.no_adjoint else adjoint_leg(cfg)
     gleg = None if args.no_graph else graph_leg()
-    lgain = None if args.no_lens_gain else lens_gain_leg()
+    lgain = None
+    if not args.no_lens_gain:
+        lgain = {"n_power": 30.0, "rho_out": 100.0, "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
+                 "128": lens_gain_leg(128), "256": lens_gain_leg(256, f32=True)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -388,6 +388,12 @@ scfft_status scfft_step_moment(scfft_ctx* ctx, int32_t omega_only, double m_Am2[
 /* Mean of |B| = mu0 |h| (tesla) over the nodes of a device region mask. */
 scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const uint8_t* dev_region,
                                      double* b_T);
+/* Stray-current fraction ||(1 - chi) j|| / ||chi j|| (Euclidean norms over
+ * all nodes and components) of j = C_s h (Eq. 4): the current left in
+ * Omega_out, which Sec. 2 suppresses through rho_out and iteration (5) rather
+ * than removes exactly.  0 when j vanishes in Omega.  Requires the mask;
+ * synchronous; overwrites the reverse-mode buffers of the workspace. */
+scfft_status scfft_stray_fraction(scfft_ctx* ctx, const void* h_dev, double* frac);
 /* B = mu0 h (tesla) at npts points (metres), trilinear between nodes with
  * periodic wrap; b_T[3*p + c]. */
 scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_m, int32_t npts,

@@ -191,6 +191,10 @@ hipError_t launch_max_partials(const double* partials, int n, double* out, hipSt
 template <typename T>
 hipError_t launch_region_abs(const T* h, const uint8_t* region, size_t nodes, double* partials,
                              int nblocks, hipStream_t s);
+// per-block sums of |j|^2 over Omega_out and over Omega nodes
+template <typename T>
+hipError_t launch_mask_sq(const T* j, const uint8_t* chi, size_t nodes, double* partials,
+                          int nblocks, hipStream_t s);
 // trilinear probe of h at npts dimensionless points
 template <typename T>
 hipError_t launch_probe(const T* h, int nx, int ny, int nz, const double* pts, int npts,

@@ -308,6 +308,36 @@ hipError_t launch_region_abs(const T* h, const uint8_t* region, size_t nodes, do
   return hipGetLastError();
 }
 
+// partials[2b] = sum of |j|^2 over Omega_out nodes, partials[2b+1] = over Omega.
+template <typename T>
+__global__ __launch_bounds__(kRB) void mask_sq_kernel(const T* __restrict__ j,
+                                                      const uint8_t* __restrict__ chi,
+                                                      size_t nodes, double* __restrict__ partials) {
+  __shared__ double sh[kRB];
+  double out = 0.0, in = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < nodes; i += (size_t)gridDim.x * kRB) {
+    const double a = j[i], b = j[nodes + i], c = j[2 * nodes + i];
+    const double q = a * a + b * b + c * c;
+    if (chi[i])
+      in += q;
+    else
+      out += q;
+  }
+  const double so = block_sum(out, sh);
+  const double si = block_sum(in, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = so;
+    partials[2 * blockIdx.x + 1] = si;
+  }
+}
+
+template <typename T>
+hipError_t launch_mask_sq(const T* j, const uint8_t* chi, size_t nodes, double* partials,
+                          int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((mask_sq_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, j, chi, nodes, partials);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kRB) void probe_kernel(const T* __restrict__ h, int nx, int ny, int nz,
                                                     const double* __restrict__ pts, int npts,
@@ -378,6 +408,8 @@ hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t n
                                         hipStream_t, const int*);                               \
   template hipError_t launch_region_abs<T>(const T*, const uint8_t*, size_t, double*, int,     \
                                            hipStream_t);                                        \
+  template hipError_t launch_mask_sq<T>(const T*, const uint8_t*, size_t, double*, int,         \
+                                        hipStream_t);                                           \
   template hipError_t launch_probe<T>(const T*, int, int, int, const double*, int, double,     \
                                       double, double, double, double, double, double*,         \
                                       hipStream_t);                                             \

@@ -1378,6 +1378,24 @@ scfft_status region_impl(scfft_ctx* c, const T* h, const uint8_t* region, double
   return SCFFT_OK;
 }
 
+// ||(1 - chi) j|| / ||chi j|| with j = C_s h (Eq. 4) formed in the reverse-mode
+// buffer (free outside reverse-mode calls).
+template <typename T>
+scfft_status stray_impl(scfft_ctx* c, const T* h, double* frac) {
+  T* j = wsp<T>(c, c->off_adj);
+  scfft_status st = apply_operator<T>(c, h, j, Z_CURL, 1.0);
+  if (st < 0) return st;
+  double* part = wsp<double>(c, c->off_part);
+  double* out = wsp<double>(c, c->off_scal);
+  HIPCHK(c, launch_mask_sq<T>(j, wsp<uint8_t>(c, c->off_chi), c->nodes, part, kReduceBlocks, c->stream));
+  HIPCHK(c, launch_sum_partials(part, kReduceBlocks, 2, 2, out, c->stream));
+  double r[2];
+  HIPCHK(c, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *frac = r[1] > 0.0 ? std::sqrt(r[0] / r[1]) : 0.0;
+  return SCFFT_OK;
+}
+
 template <typename T>
 scfft_status probe_impl(scfft_ctx* c, const T* h, const double* xyz, int npts, double* b) {
   double* dpts = wsp<double>(c, c->off_probe);
@@ -1916,6 +1934,15 @@ scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const ui
   if (!h_dev || !dev_region || !b_T) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
   return ctx->prec == SCFFT_F64 ? region_impl<double>(ctx, (const double*)h_dev, dev_region, b_T)
                                 : region_impl<float>(ctx, (const float*)h_dev, dev_region, b_T);
+}
+
+scfft_status scfft_stray_fraction(scfft_ctx* ctx, const void* h_dev, double* frac) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  scfft_status st;
+  if (!ready(ctx, true, &st)) return st;
+  if (!h_dev || !frac) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  return ctx->prec == SCFFT_F64 ? stray_impl<double>(ctx, (const double*)h_dev, frac)
+                                : stray_impl<float>(ctx, (const float*)h_dev, frac);
 }
 
 scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_m, int32_t npts,

@@ -100,6 +100,7 @@ _SIGS = {
     "scfft_voxelize": (C.c_int, [_P, C.POINTER(Shape), C.c_int32]),
     "scfft_set_mask": (C.c_int, [_P, _P]),
     "scfft_mask_betti": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "scfft_stray_fraction": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "scfft_mask_betti_host": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]),
     "scfft_set_jc_map": (C.c_int, [_P, _P]),
     "scfft_set_drive": (C.c_int, [_P, C.POINTER(Drive)]),
@@ -454,6 +455,12 @@ def scfft_region_mean_abs_b(ctx, h, dev_region):
     b = C.c_double()
     _check(load().scfft_region_mean_abs_b(ctx, _ptr(h), _ptr(dev_region), C.byref(b)), ctx)
     return b.value
+
+
+def scfft_stray_fraction(ctx, h):
+    f = C.c_double()
+    _check(load().scfft_stray_fraction(ctx, _ptr(h), C.byref(f)), ctx)
+    return f.value
 
 
 def scfft_probe_b(ctx, h, xyz_m):

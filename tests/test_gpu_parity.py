@@ -275,3 +275,24 @@ def test_box_pruning_is_exact(prec, fuse, fixed):
         outs.append(res)
     for a, b in zip(outs[0], outs[1]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("cfg", [CUBE32, NONCUBIC, small_cfg((48, 24, 32), (2.0, 1.0, 1.4), workloads.shape_cube(0.6))],
+                         ids=["32", "16x32x64", "48x24x32"])
+def test_stray_fraction(cfg, prec):
+    """||(1-chi) j|| / ||chi j|| of j = C_s h against the oracle (FP64 1e-10,
+    FP32 1e-5 relative), on a state and on the right-hand side's output."""
+    s = sim(cfg, precision=prec, fixed_iter=3)
+    prob, u = oracle_problem(cfg, fixed_iter=3)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    h = to_dev(torch, state(cfg, seed=7), dt)
+    hn = _np(h)
+    tol = 1e-10 if prec == scfft.F64 else 1e-5
+    got = scfft.scfft_stray_fraction(s.ctx, h)
+    want = readouts.stray_fraction(prob.grid, prob.chi, hn)
+    assert abs(got - want) <= tol * want
+    out, _ = s.rhs_eval(0.01, h)                     # a field with most current outside Omega
+    got = scfft.scfft_stray_fraction(s.ctx, out)
+    want = readouts.stray_fraction(prob.grid, prob.chi, _np(out))
+    assert abs(got - want) <= tol * want
