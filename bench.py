@@ -167,9 +167,10 @@ def lens256_leg(calls=10):
 def adjoint_leg(cfg, steps=2000, every=50):
     """Reverse-mode cost on the shield with a jc(x) map (kappa = 1 + 0.1 N(0,1),
     seed 5): 2000 fixed steps of 2e-5 s with checkpoints every 50 steps.  Time
-    of the checkpointed adjoint (forward with checkpoints, segment
-    recomputation, reverse steps) over the time of the plain forward
-    integration of the same steps."""
+    of the checkpointed adjoint giving the gradients in h0, the kappa map, n
+    and the drive vector (forward with checkpoints, segment recomputation,
+    reverse steps) over the time of the plain forward integration of the
+    same steps."""
     import numpy as np
     import torch
     from paper_1803_01346_amd import autograd as sag, scfft
@@ -190,11 +191,14 @@ def adjoint_leg(cfg, steps=2000, every=50):
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
+    kbar = torch.zeros_like(dk)
+
     def adj(k, ev):
         ws = sag.adjoint_workspace(sim, k, ev)
+        kbar.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        scfft.scfft_integrate_adjoint(sim.ctx, 0.0, k * 2e-5, k, ev, ws, h0, ybar, hT, h0b)
+        scfft.scfft_integrate_adjoint(sim.ctx, 0.0, k * 2e-5, k, ev, ws, h0, ybar, hT, h0b, kbar)
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
@@ -203,6 +207,7 @@ def adjoint_leg(cfg, steps=2000, every=50):
     ta = adj(steps, every)
     out = dict(ratio=round(ta / tf, 3), forward_s=round(tf, 3), adjoint_s=round(ta, 3), steps=steps,
                checkpoint_every=every, dt_s=2e-5, dtype="f64",
+               gradients="h0, kappa map, n, drive vector",
                note="ratio = (forward with checkpoints + recomputation + reverse) / forward")
     sim.close()
     return out

@@ -201,3 +201,78 @@ def test_autograd_gradcheck():
                                     atol=1e-6, rtol=1e-4, fast_mode=True)
     assert torch.autograd.gradcheck(lambda x: sag.Integrate.apply(x, s, 0.0, 1e-3 * u.t0, 3, 2), (h,),
                                     eps=1e-6, atol=1e-6, rtol=1e-4, fast_mode=True)
+
+
+def test_parameter_gradients_against_central_differences():
+    """The shield-type loss L = mean over the bore of |h(t1)|^2 after fixed
+    steps of a 45-degree field ramp that drives the cup wall to the critical
+    state (|j| near 1, so n and kappa matter), differentiated by one adjoint run
+    (IntegrateParams) with respect to a global jc (uniform scaling of the
+    kappa map), one kappa voxel, n and the field angle, against central
+    differences of the GPU forward path with relative step 1e-6: within
+    1e-4 relative."""
+    import math
+    from paper_1803_01346_amd import autograd as sag
+    theta = math.pi / 4
+    l, jc = 5e-3, 1e8
+    t0 = 4e-7 * math.pi * jc * l * l / 1e-4
+    h_end = 0.3                                           # ramp rate h_e' = 1 up to 0.3
+    base = small_cfg((32, 32, 32), (2.0, 2.0, 2.0), workloads.shape_cup(1.0, 0.6, 2.0, 0.3), n_power=20.0,
+                     l_m=l, jc=jc,
+                     drive=dict(kind="ramp_hold", direction=(math.sin(theta), 0.0, math.cos(theta)),
+                                amp_T=h_end * 4e-7 * math.pi * jc * l, t_ramp_s=h_end * t0))
+    steps, every, t1_s = 150, 30, h_end * t0              # dt' = 2e-3: stable for the explicit pair
+    prob, _ = oracle_problem(base)
+    g = prob.grid
+    x = -2.0 + (np.arange(32) + 0.5) * (4.0 / 32)
+    r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2) * np.ones((32, 32, 32))
+    bore = torch.from_numpy(((r < 0.5) & (np.abs(x)[:, None, None] < 0.6) & (prob.chi == 0))
+                            .astype(np.float64)).cuda()
+    nb = float(bore.sum())
+    kap0 = torch.from_numpy(_kappa(base, 9)).cuda()
+    h0 = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device="cuda")
+
+    def make(n_power):
+        return sim(dict(base, n_power=n_power), fixed_iter=2)
+
+    s = make(20.0)
+    p0 = sag.drive_vector(s)
+    amp = float(torch.linalg.norm(p0))
+
+    def loss(sim_, kap, p):
+        nt_ = torch.tensor(float(sim_.cfg["n_power"]), dtype=torch.float64)
+        hT = sag.IntegrateParams.apply(h0, kap, nt_, p, sim_, 0.0, t1_s, steps, every)
+        return (hT * hT).sum(dim=0).mul(bore).sum() / nb
+
+    kap = kap0.clone().requires_grad_(True)
+    nt = torch.tensor(20.0, dtype=torch.float64, requires_grad=True)
+    pt = p0.clone().requires_grad_(True)
+    L = sag.IntegrateParams.apply(h0, kap, nt, pt, s, 0.0, t1_s, steps, every)
+    L = (L * L).sum(dim=0).mul(bore).sum() / nb
+    L.backward()
+    kbar, n_bar, p_bar = kap.grad, float(nt.grad), pt.grad.double().cpu().numpy()
+    eps = 1e-6
+
+    def rel(a, b):
+        return abs(a - b) / max(abs(b), 1e-300)
+
+    with torch.no_grad():
+        # global jc: kappa -> (1 + e) kappa
+        fd = (float(loss(s, kap0 * (1 + eps), p0)) - float(loss(s, kap0 * (1 - eps), p0))) / (2 * eps)
+        assert rel(float((kbar * kap0).sum()), fd) < 1e-4
+        # the voxel of the map with the largest sensitivity
+        iz, iy, ix = np.unravel_index(int(torch.argmax(kbar.abs())), kbar.shape)
+        dk = torch.zeros_like(kap0)
+        dk[iz, iy, ix] = eps * float(kap0[iz, iy, ix])
+        fd = (float(loss(s, kap0 + dk, p0)) - float(loss(s, kap0 - dk, p0))) / (2 * float(dk[iz, iy, ix]))
+        assert rel(float(kbar[iz, iy, ix]), fd) < 1e-4
+        # n (a context per value of n)
+        fd = (float(loss(make(20.0 * (1 + eps)), kap0, p0)) -
+              float(loss(make(20.0 * (1 - eps)), kap0, p0))) / (2 * 20.0 * eps)
+        assert rel(n_bar, fd) < 1e-4
+        # field angle in the x-z plane
+        def p_of(th):
+            return torch.tensor([amp * math.sin(th), 0.0, amp * math.cos(th)], dtype=torch.float64)
+        fd = (float(loss(s, kap0, p_of(theta + eps))) - float(loss(s, kap0, p_of(theta - eps)))) / (2 * eps)
+        dth = float(np.dot(p_bar, [amp * math.cos(theta), 0.0, -amp * math.sin(theta)]))
+        assert rel(dth, fd) < 1e-4
