@@ -296,3 +296,51 @@ def test_stray_fraction(cfg, prec):
     got = scfft.scfft_stray_fraction(s.ctx, out)
     want = readouts.stray_fraction(prob.grid, prob.chi, _np(out))
     assert abs(got - want) <= tol * want
+
+
+def _fp32_vs_fp64(cfg, t0_s, steps, dt_s, start):
+    res = []
+    for prec, dt in ((scfft.F64, torch.float64), (scfft.F32, torch.float32)):
+        s = sim(cfg, precision=prec, fixed_iter=3)
+        h = start(s, dt)
+        ms = []
+        scfft.scfft_integrate(s.ctx, t0_s, t0_s + steps * dt_s, h, scfft.default_ode_opts(fixed_steps=steps),
+                              observer=lambda _u, t, _p: ms.append(scfft.scfft_step_moment(s.ctx)) or 0)
+        j = s.empty_field()
+        scfft.scfft_current(s.ctx, h, j)
+        torch.cuda.synchronize()
+        res.append((_np(h), _np(j), np.array(ms)))
+    return res
+
+
+def test_fp32_trajectory_against_fp64():
+    """FP32 bulk path against FP64 along trajectories of the shield (64^3 box,
+    n = 100, the 45-degree 50 Hz drive, 3 exterior iterations), within 1e-4
+    relative L2:
+      * from the virgin state, 60 fixed steps of 2e-5 s: h and j = C_s h at
+        the end and the moment of every accepted state;
+      * from a critical-state synthetic start at the peak field (|j| = 1.05
+        in Omega, where the law is steepest), 20 steps: h and j at the end
+        (the moment of that random current is a sum that cancels to 1e-3 of
+        its terms, so FP32 rounding of j shows in it at that ratio)."""
+    cfg = CUP64
+
+    def virgin(s, dt):
+        h = s.empty_field()
+        scfft.scfft_init_state(s.ctx, 0.0, h)
+        return h
+
+    (h64, j64, m64), (h32, j32, m32) = _fp32_vs_fp64(cfg, 0.0, 60, 2e-5, virgin)
+    assert m64.shape == (60, 3)
+    assert rel_l2(h32, h64) < 1e-4 and rel_l2(j32, j64) < 1e-4 and rel_l2(m32, m64) < 1e-4
+    print("virgin: FP32 vs FP64 rel L2 h %.2e j %.2e m %.2e" % (rel_l2(h32, h64), rel_l2(j32, j64),
+                                                                 rel_l2(m32, m64)))
+
+    def critical(s, dt):
+        he, _ = scfft.scfft_drive_eval(s.drive, s.material, 0.005)
+        return to_dev(torch, state(cfg, seed=0, bg=tuple(he)), dt)
+
+    (h64, j64, _), (h32, j32, _) = _fp32_vs_fp64(cfg, 0.005, 20, 2e-5, critical)
+    assert rel_l2(h32, h64) < 1e-4 and rel_l2(j32, j64) < 1e-4
+    print("critical: FP32 vs FP64 rel L2 h %.2e j %.2e (rel max h %.2e j %.2e)"
+          % (rel_l2(h32, h64), rel_l2(j32, j64), rel_max(h32, h64), rel_max(j32, j64)))
