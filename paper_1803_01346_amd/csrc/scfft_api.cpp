@@ -63,6 +63,7 @@ struct scfft_ctx {
   int64_t betti[3] = {0, 0, 0};                      // of the mask's voxel union
   std::string err;
   int64_t clamp_seen = 0;
+  int iter_guess = 0;  // exterior iterations of the last converged adaptive call
   // integrator: state whose moment partials the last power-law pass recorded,
   // and whether an observer callback is running (scfft_step_moment)
   const void* mom_state = nullptr;
@@ -369,7 +370,7 @@ double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) 
     case X_UPDATE: return inv_rows * spec + rows * mask + (a.track ? all + nout : nin) * frac * node +
                           rows * spec;
     case X_UPDATE_LAST: return inv_rows * spec + rows * mask +
-                               (a.track ? all + nout : (a.warm_out ? 2.0 : 1.0) * nout) * frac * node;
+                               ((a.track ? all : 0.0) + (a.warm_out ? 2.0 : 1.0) * nout) * frac * node;
     case X_STORE: return inv_rows * spec + rows * p.nx * node;
     case X_MOMENT: return inv_rows * spec + (a.omega_only ? rows * mask : 0.0);
     case X_ADJ_START: return rows * mask + rows * p.nx * node + (a.in2 ? nout * frac * node : 0.0) +
@@ -581,37 +582,62 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   } else {
     // Stopping rule on the device: after each update a one-block kernel sums
     // |delta| and sets a stop flag that makes every later pass of the loop
-    // return at once.  The host launches kIterChunk iterations at a time and
-    // reads the flag once per chunk instead of once per iteration.
+    // return at once.  The host first launches as many iterations as the
+    // previous call needed (the warm start makes consecutive calls alike),
+    // the last of them in the form that stores hdot and the next warm start
+    // without a forward transform, and reads the flag once; only if that
+    // was too few does it rebuild the spectrum and go on kIterChunk
+    // iterations at a time.
     IterState* ist = wsp<IterState>(c, c->off_delta);
     HIPCHK(c, launch_iter_reset(ist, s));
     Plan<T> pl = p;
     pl.stop = &ist->stop;
     const BoxPlans<T> bl = box_plans<T>(c, pl, c->opts.prune_box != 0);
     const int max_it = std::max(1, c->opts.max_iter);
-    int launched = 0;
+    const int guess = std::min(max_it, std::max({1, c->opts.min_iter, c->iter_guess > 0 ? c->iter_guess : kIterChunk}));
     IterState hst{0, 0, 0.0};
-    while (launched < max_it) {
-      const int chunk = std::min(kIterChunk, max_it - launched);
-      for (int k = 0; k < chunk; ++k) {
-        HIPCHK(c, iteration(pl, bl, X_UPDATE));
-        HIPCHK(c, launch_iter_decide(a.partials, xb, (double)c->n_out, tol, c->opts.min_iter, ist, s));
-      }
-      launched += chunk;
-      if (launched >= max_it)  // warm start of the next call, read on Omega_out only
-        HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
-                                 hipMemcpyDeviceToDevice, s));
-      HIPCHK(c, hipMemcpyAsync(&hst, ist, sizeof hst, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(&clamps_now, wsp<unsigned long long>(c, c->off_clamp),
-                               sizeof clamps_now, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      if (hst.stop) {
-        if (launched < max_it)
-          HIPCHK(c, hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T),
-                                   hipMemcpyDeviceToDevice, s));
-        break;
+    auto read_state = [&]() -> hipError_t {
+      hipError_t e;
+      if ((e = hipMemcpyAsync(&hst, ist, sizeof hst, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(&clamps_now, wsp<unsigned long long>(c, c->off_clamp), sizeof clamps_now,
+                              hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return e;
+      return hipStreamSynchronize(s);
+    };
+    auto copy_warm = [&]() {  // warm start of the next call, read on Omega_out only
+      return hipMemcpyAsync(wsp<T>(c, c->off_warm), hdot, 3 * c->nodes * sizeof(T), hipMemcpyDeviceToDevice, s);
+    };
+    for (int k = 0; k < guess; ++k) {
+      const bool lastk = k + 1 == guess;
+      a.warm_out = lastk ? wsp<T>(c, c->off_warm) : nullptr;
+      HIPCHK(c, iteration(pl, bl, lastk ? X_UPDATE_LAST : X_UPDATE));
+      HIPCHK(c, launch_iter_decide(a.partials, xb, (double)c->n_out, tol, c->opts.min_iter, ist, s));
+    }
+    a.warm_out = nullptr;
+    int launched = guess;
+    HIPCHK(c, read_state());
+    if (hst.stop) {
+      if (hst.iters < guess) HIPCHK(c, copy_warm());  // the storing update did not run
+    } else if (launched < max_it) {
+      // the spectrum of hdot for the next iteration (the storing update made none)
+      a.in = hdot;
+      a.in2 = nullptr;
+      HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+      while (launched < max_it) {
+        const int chunk = std::min(kIterChunk, max_it - launched);
+        for (int k = 0; k < chunk; ++k) {
+          HIPCHK(c, iteration(pl, bl, X_UPDATE));
+          HIPCHK(c, launch_iter_decide(a.partials, xb, (double)c->n_out, tol, c->opts.min_iter, ist, s));
+        }
+        launched += chunk;
+        HIPCHK(c, read_state());
+        if (hst.stop || launched >= max_it) {
+          HIPCHK(c, copy_warm());
+          break;
+        }
       }
     }
+    if (hst.stop) c->iter_guess = hst.iters;
     it = hst.iters;
     last = hst.last;
     converged = hst.stop != 0;

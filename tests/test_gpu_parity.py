@@ -344,3 +344,28 @@ def test_fp32_trajectory_against_fp64():
     assert rel_l2(h32, h64) < 1e-4 and rel_l2(j32, j64) < 1e-4
     print("critical: FP32 vs FP64 rel L2 h %.2e j %.2e (rel max h %.2e j %.2e)"
           % (rel_l2(h32, h64), rel_l2(j32, j64), rel_max(h32, h64), rel_max(j32, j64)))
+
+
+@pytest.mark.parametrize("cfg", [NONCUBIC, CUBE32], ids=["16x32x64", "32"])
+def test_rhs_adaptive_iteration_guess(cfg):
+    """The adaptive loop launches as many iterations as the previous call
+    needed: calls needing more (a start from Ohm's law after a warm call),
+    as many, and fewer than guessed all give the oracle's iteration count,
+    last delta and result."""
+    s = sim(cfg, delta_it=2e-5)
+    prob, u = oracle_problem(cfg, delta_it=2e-5)
+    h = state(cfg, seed=4)
+    dh = to_dev(torch, h, torch.float64)
+    seen = []
+    for t_s, reset in ((0.2, False), (0.21, False), (0.215, False), (0.22, True), (0.23, False)):
+        if reset:
+            scfft.scfft_reset_warm(s.ctx)
+            prob.warm = None
+        stats = scfft.RhsStats()
+        out, rc = s.rhs_eval(t_s, dh, stats=stats)
+        want = orhs.rhs_eval(prob, t_s / u.t0, h)
+        assert stats.iters == prob.last_iters, t_s
+        assert abs(stats.last_delta - prob.last_deltas[-1]) <= 1e-9 * prob.last_deltas[-1]
+        assert rel_max(_np(out), want) < 1e-10, t_s
+        seen.append(stats.iters)
+    assert seen[3] > seen[2]                              # the Ohm-law restart needed more than guessed
