@@ -315,6 +315,40 @@ def lens_gain_leg(n_grid=128, f32=False):
     return out
 
 
+def shield_leg(n_grid=128):
+    """The shield run of Sec. 3 (cases A and B, n = 30, rho_out = 20, virgin
+    start, adaptive steps, the stopping rule of the exterior iteration,
+    FP64) on the stand-in cup: the mean |B| over the shielded zone over the
+    applied |B| at the end of each field segment, steps and wall time (the
+    paper's own 128^3 run took about 2 h in Matlab on a Core i5-2400)."""
+    import numpy as np
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    out = dict(grid=[n_grid] * 3, dtype="f64", n_power=30.0, rho_out=20.0, tau=0.09,
+               paper_wall_clock="about 2 h at 128^3 (Matlab R2017a, Intel Core i5-2400)")
+    for case in ("A", "B"):
+        cfg, t0, zone = workloads.shield_case(case, n_grid)
+        s = scfft.Simulation(cfg, precision=scfft.F64)
+        sh, ns = scfft.make_shapes([zone], cfg["l_m"])
+        region = torch.from_numpy(scfft.scfft_voxelize_host(s.grid, s.material, sh, ns)).cuda()
+        h = s.empty_field()
+        scfft.scfft_init_state(s.ctx, 0.0, h)
+        bs = workloads.MU0 * cfg["jc"] * cfg["l_m"]
+        res, t, steps, rhs = {}, 0.0, 0, 0
+        torch.cuda.synchronize()
+        wall = time.perf_counter()
+        for k, (tt, be) in enumerate(((0.09 * t0, 0.09 * bs), (0.18 * t0, 0.09 * bs * np.sqrt(2.0)))):
+            st = scfft.OdeStats()
+            scfft.scfft_integrate(s.ctx, t, tt, h, scfft.default_ode_opts(), stats=st)
+            res["ratio_t%d" % (k + 1)] = round(scfft.scfft_region_mean_abs_b(s.ctx, h, region) / be, 4)
+            steps, rhs, t = steps + st.accepted, rhs + st.rhs_calls, tt
+        torch.cuda.synchronize()
+        res.update(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2))
+        out["case_" + case] = res
+        s.close()
+    return out
+
+
 def cpu_baseline(cfg, h_np):
     """The oracle's rhs_eval on the same 128^3 state with one exterior
     iteration (4 of the 8 spectral operator applications of a k = 3 call),
@@ -362,6 +396,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
     ap.add_argument("--no-lens-gain", action="store_true", help="skip the lens field-concentration run")
+    ap.add_argument("--no-shield", action="store_true", help="skip the shield cases A/B run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -431,6 +466,7 @@ def main():
     lens = None if args.no_lens else lens256_leg()
     adj = None if args.no_adjoint else adjoint_leg(cfg)
     gleg = None if args.no_graph else graph_leg()
+    shield = None if args.no_shield else shield_leg()
     lgain = None
     if not args.no_lens_gain:
         lgain = {"n_power": 30.0, "rho_out": 100.0, "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
@@ -465,6 +501,7 @@ def main():
         "adjoint_cost": adj,
         "graphs": gleg,
         "lens_gain": lgain,
+        "shield": shield,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,

@@ -93,6 +93,31 @@ CONFIGS = {
 }
 
 
+MU0 = 4e-7 * np.pi
+
+
+def shield_case(case="A", n_grid=128, tau=0.09, l_m=0.01, jc=1e8, e0=1e-4):
+    """The shield run of Sec. 3 on a stand-in body (the paper's sizes come
+    from a reference that is not available): a cup of outer radius 1, inner
+    radius 0.8, height 2 and cap 0.2 (units of l, open end up) centred in the
+    cube of side 3.2; n = 30, rho_out = 20; virgin start; the field grows
+    along the axis and then across it (case A: (0, 0, t') then
+    (t' - tau, 0, tau)) or in the opposite order (case B), t' up to 2 tau.
+    Returns (cfg, t0_s, zone) with zone the shielded-zone primitive: a
+    coaxial disk of radius 0.667 and thickness 0.143 whose middle plane is
+    0.452 below the top of the cup."""
+    t0 = MU0 * jc * l_m * l_m / e0
+    bs = MU0 * jc * l_m                                  # tesla per unit of h'
+    pts = {"A": [(0, 0, 0), (0, 0, tau), (tau, 0, tau)],
+           "B": [(0, 0, 0), (tau, 0, 0), (tau, 0, tau)]}[case]
+    cfg = dict(n=(n_grid,) * 3, l_m=l_m, half_width=(1.6, 1.6, 1.6),
+               shapes=shape_cup(1.0, 0.8, 2.0, 0.2, axis=2), n_power=30.0, jc=jc, e0=e0, rho_out=20.0,
+               drive=dict(kind="pwl", t_s=[0.0, tau * t0, 2 * tau * t0],
+                          b_T=[[bs * v for v in p] for p in pts]))
+    zone = prim("cylinder", "add", (0.0, 0.0, 1.0 - 0.452), (0.667, 0.0, 0.5 * 0.143), 2)
+    return cfg, t0, zone
+
+
 def config(name):
     return CONFIGS[name]
 
