@@ -670,9 +670,14 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
           a[cc][e] = nw;
         }
         if (valid && !in) {
-          if (A.track) acc0 += sqrt((double)d2);
-          if (A.track || OP == X_UPDATE_LAST) st_out |= 1u << e;
-          if constexpr (OP == X_UPDATE_LAST) {
+          if (A.track) {
+            acc0 += sqrt((double)d2);
+            st_out |= 1u << e;
+            if constexpr (OP == X_UPDATE_LAST) {
+              if (A.warm_out) st_warm |= 1u << e;
+            }
+          } else if constexpr (OP == X_UPDATE_LAST) {
+            st_out |= 1u << e;
             if (A.warm_out) st_warm |= 1u << e;
           }
         }
