@@ -211,7 +211,47 @@ struct ChiTable {
 
 }  // namespace
 
+namespace {
+void betti_of_box(const int n[3], const uint8_t* mask, int64_t betti[3]);
+}
+
+// The numbers depend only on the bounding box of Omega and one empty layer
+// around it (everything farther out is empty and joined to the unbounded
+// component), so the count runs on that crop of the grid.
 void mask_betti(const int n[3], const uint8_t* mask, int64_t betti[3]) {
+  int lo[3] = {n[0], n[1], n[2]}, hi[3] = {-1, -1, -1};
+  for (int z = 0; z < n[2]; ++z)
+    for (int y = 0; y < n[1]; ++y) {
+      const uint8_t* row = mask + ((size_t)z * n[1] + y) * n[0];
+      for (int x = 0; x < n[0]; ++x)
+        if (row[x]) {
+          const int id[3] = {x, y, z};
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], id[a]);
+            hi[a] = std::max(hi[a], id[a]);
+          }
+        }
+    }
+  if (hi[0] < 0) {
+    betti[0] = betti[1] = betti[2] = 0;
+    return;
+  }
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = std::max(0, lo[a] - 1);
+    hi[a] = std::min(n[a] - 1, hi[a] + 1);
+    c[a] = hi[a] - lo[a] + 1;
+  }
+  std::vector<uint8_t> crop((size_t)c[0] * c[1] * c[2]);
+  for (int z = 0; z < c[2]; ++z)
+    for (int y = 0; y < c[1]; ++y)
+      std::memcpy(&crop[((size_t)z * c[1] + y) * c[0]],
+                  mask + ((size_t)(z + lo[2]) * n[1] + (y + lo[1])) * n[0] + lo[0], (size_t)c[0]);
+  betti_of_box(c, crop.data(), betti);
+}
+
+namespace {
+void betti_of_box(const int n[3], const uint8_t* mask, int64_t betti[3]) {
   const int nx = n[0], ny = n[1], nz = n[2];
   const size_t nodes = (size_t)nx * ny * nz;
   if (nodes >= (size_t)INT32_MAX) {
@@ -265,5 +305,6 @@ void mask_betti(const int n[3], const uint8_t* mask, int64_t betti[3]) {
   betti[1] = b0 + b2 - chi;
   betti[2] = b2;
 }
+}  // namespace
 
 }  // namespace scfft
