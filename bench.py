@@ -122,6 +122,32 @@ def roofline_of(per_kind, traffic=None):
             "launches": d["launches"]}
 
 
+def rhs_bandwidth(sim, h, hd, rhs_ps, n, calls=10):
+    """The whole right-hand side against the HBM peak: its bytes per call
+    (the library's count for the launches of this schedule, and the counter
+    bytes of the committed traffic summary per launch of each kernel kind
+    when it matches the sources) times the calls per second of the timed
+    run; beside it the survey-style model of a plain R2C pencil schedule,
+    (3 + 2k) F + (17 + 16k) S + (2 + 2k) N^3 with F = 3 N^3 w and
+    S = 3 N^2 (N/2 + 1) 2w, at the same rate."""
+    pk = kernel_profile(sim, lambda: [sim.rhs_eval(T_STAR, h, hd) for _ in range(calls)])
+    b = sum(v["bytes_per_launch"] * v["launches"] for v in pk.values()) / calls
+    tr = {k: measured_traffic(k) for k in pk}
+    cb = (sum(tr[k] * pk[k]["launches"] for k in pk) / calls) if all(v is not None for v in tr.values()) else None
+    w, k = 8.0, FIXED_ITER
+    nodes = float(n[0] * n[1] * n[2])
+    F = 3.0 * nodes * w
+    S = 3.0 * n[2] * n[1] * (n[0] // 2 + 1) * 2.0 * w
+    model = (3 + 2 * k) * F + (17 + 16 * k) * S + (2 + 2 * k) * nodes
+    out = dict(bytes_per_rhs=int(b), achieved_GBs=round(b * rhs_ps / 1e9, 1),
+               frac=round(b * rhs_ps / (HBM_PEAK_GBS * 1e9), 4),
+               counter_bytes_per_rhs=int(cb) if cb is not None else None,
+               counter_frac=round(cb * rhs_ps / (HBM_PEAK_GBS * 1e9), 4) if cb is not None else None,
+               model_bytes_per_rhs=int(model),
+               model_equivalent_frac=round(model * rhs_ps / (HBM_PEAK_GBS * 1e9), 4))
+    return out
+
+
 def converged_leg(cfg, h, calls=20):
     """rhs_eval with the paper's stopping rule (delta_it = 2e-5) instead of a
     fixed count, on consecutive stage times so each call starts from the
@@ -440,6 +466,7 @@ def main():
 
     # right-hand side alone (no integrator work)
     rhs_ps, hd64 = time_rhs_only(sim, h, 50)
+    rhs_hbm = None if args.no_events else rhs_bandwidth(sim, h, hd64, rhs_ps, n)
 
     fp32 = None
     if not args.no_fp32:
@@ -495,6 +522,7 @@ def main():
                                "iterations per RHS, moment readout per step" % (args.config, FIXED_ITER),
                    "grid": list(n), "exterior_iters": FIXED_ITER, "rhs_per_step": 3},
         "rhs_only": round(rhs_ps, 2),
+        "rhs_hbm": rhs_hbm,
         "fp32": fp32,
         "converged": converged,
         "lens256_f32": lens,
