@@ -378,22 +378,41 @@ def shield_leg(n_grid=128):
 def cpu_baseline(cfg, h_np):
     """The oracle's rhs_eval on the same 128^3 state with one exterior
     iteration (4 of the 8 spectral operator applications of a k = 3 call),
-    timed once and scaled by the operator count to a k = 3 call."""
+    timed once and scaled by the operator count to a k = 3 call; beside it
+    full k = 3 calls on the same body at 32^3 and 64^3 (median of 3)."""
+    import numpy as np
     from oracle import geometry, grid, rhs, units
-    g = grid.Grid(cfg["n"], cfg["half_width"])
-    chi = geometry.voxelize(g, cfg["shapes"])
-    u = units.Units(cfg["jc"], cfg["l_m"])
-    d = dict(cfg["drive"])
-    prob = rhs.Problem(g, chi, cfg["n_power"], cfg["rho_out"], units.Drive(u, d.pop("kind"), **d),
-                       rhs.RhsOptions(fixed_iter=1))
+    from paper_1803_01346_amd import workloads
+
+    def problem(c, k):
+        g = grid.Grid(c["n"], c["half_width"])
+        chi = geometry.voxelize(g, c["shapes"])
+        u = units.Units(c["jc"], c["l_m"])
+        d = dict(c["drive"])
+        return rhs.Problem(g, chi, c["n_power"], c["rho_out"], units.Drive(u, d.pop("kind"), **d),
+                           rhs.RhsOptions(fixed_iter=k)), u
+
+    prob, u = problem(cfg, 1)
     t = time.perf_counter()
     rhs.rhs_eval(prob, T_STAR / u.t0, h_np)
     dt = time.perf_counter() - t
     ops_k1, ops_k3 = 2 + 2 * 1, 2 + 2 * FIXED_ITER
+    small = {}
+    for n in (32, 64):
+        c = dict(cfg, n=(n, n, n))
+        p, uu = problem(c, FIXED_ITER)
+        hs = workloads.synthetic_state(c, seed=0)
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            rhs.rhs_eval(p, T_STAR / uu.t0, hs)
+            ts.append(time.perf_counter() - t1)
+        small["%d^3" % n] = round(1.0 / float(np.median(ts)), 3)
     return dict(value=1.0 / (dt * ops_k3 / ops_k1), unit="RHS evals/s", cores=1, kind="oracle",
                 sample="one oracle rhs_eval at 128^3 (cup shield, FP64, own radix-2 FFT) with 1 "
                        "exterior iteration: %.1f s for 4 operator applications, scaled x2 to the "
-                       "8 of a 3-iteration call" % dt)
+                       "8 of a 3-iteration call" % dt,
+                smaller_boxes_rhs_per_s=small)
 
 
 def copy_calibration(nbytes=256 << 20, reps=5):
