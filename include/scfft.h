@@ -322,6 +322,14 @@ scfft_status scfft_graph_workspace_size(const scfft_ctx* ctx, int32_t steps, siz
 scfft_status scfft_integrate_graph(scfft_ctx* ctx, double t0_s, double t1_s, int32_t steps,
                                    void* graph_ws, size_t graph_bytes, void* h_dev);
 scfft_status scfft_integrate_wait(scfft_ctx* ctx, scfft_ode_stats* stats);
+/* The magnetic moment (as scfft_moment: all nodes, or Omega only) of every
+ * state accepted by the last graph integration, summed on the device by the
+ * power-law pass of each step's last evaluation; valid after
+ * scfft_integrate_wait while that integration's graph workspace is still
+ * allocated.  Writes min(max_steps, accepted) rows m_Am2[3*k + c] (A m^2)
+ * and the accepted count to *n_steps. */
+scfft_status scfft_graph_moments(scfft_ctx* ctx, int32_t omega_only, int32_t max_steps, double* m_Am2,
+                                 int32_t* n_steps);
 
 /* ---- reverse mode (gradients) ----
  *

@@ -168,6 +168,9 @@ struct GraphState {
 hipError_t launch_graph_reset(GraphState* g, hipStream_t s);
 // records err[0] as hist[step]; step += 1 if finite, else sets stop and bad
 hipError_t launch_graph_step_end(const double* err, GraphState* g, double* hist, hipStream_t s);
+// moment partials of the accepted state into its row of the history
+hipError_t launch_graph_moment(const double* partials, int n, const GraphState* g, double* hist,
+                               hipStream_t s);
 hipError_t launch_iter_decide(const double* partials, int n, double n_out, double tol, int min_iter,
                               IterState* st, hipStream_t s);
 template <typename T>

@@ -128,6 +128,29 @@ hipError_t launch_graph_step_end(const double* err, GraphState* g, double* hist,
   return hipGetLastError();
 }
 
+// Graph replay: hist[6 * step + c] = sum_b partials[6 b + c] (the moment
+// partials of the state just accepted, all nodes then Omega), summed in the
+// order of sum_partials_kernel; nothing once the stop flag is set.
+__global__ __launch_bounds__(kRB) void graph_moment_kernel(const double* __restrict__ p, int n,
+                                                           const GraphState* g,
+                                                           double* __restrict__ hist) {
+  __shared__ double sh[kRB];
+  if (g->stop) return;  // uniform across the block
+  const int step = g->step;
+  for (int c = 0; c < 6; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRB) acc += p[(size_t)i * 6 + c];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) hist[6 * (size_t)step + c] = r;
+  }
+}
+
+hipError_t launch_graph_moment(const double* partials, int n, const GraphState* g, double* hist,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(graph_moment_kernel, dim3(1), dim3(kRB), 0, s, partials, n, g, hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_iter_reset(IterState* st, hipStream_t s) {
   hipLaunchKernelGGL(iter_reset_kernel, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();

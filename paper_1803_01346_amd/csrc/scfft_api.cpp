@@ -93,6 +93,7 @@ struct scfft_ctx {
   std::vector<double> graph_hedot;  // host copy of the rate table (alive until the wait)
   char* graph_ws = nullptr;
   int graph_steps = 0;
+  int graph_accepted = -1;  // steps accepted by the last waited graph integration
   double graph_t0 = 0.0, graph_dt = 0.0;
   void* graph_h = nullptr;
 
@@ -1148,7 +1149,7 @@ scfft_status integrate_adjoint_impl(scfft_ctx* c, double t0, double t1, int step
 // Caller workspace: the device state of the replays, the error norm of each
 // step and the table of applied-field rates (3 stages x 3 components per step).
 struct GraphLayout {
-  size_t off_state = 0, off_err = 0, off_hist = 0, off_tab = 0, total = 0;
+  size_t off_state = 0, off_err = 0, off_hist = 0, off_tab = 0, off_mhist = 0, total = 0;
 };
 
 GraphLayout graph_layout(int steps) {
@@ -1158,6 +1159,7 @@ GraphLayout graph_layout(int steps) {
   L.off_err = o;    o = align_up(o + sizeof(double));
   L.off_hist = o;   o = align_up(o + (size_t)steps * sizeof(double));
   L.off_tab = o;    o = align_up(o + (size_t)steps * 9 * sizeof(double));
+  L.off_mhist = o;  o = align_up(o + (size_t)steps * 6 * sizeof(double));
   L.total = o;
   return L;
 }
@@ -1167,7 +1169,7 @@ GraphLayout graph_layout(int steps) {
 // table, and every kernel returns at once after the stop flag is set.
 template <typename T>
 scfft_status graph_step(scfft_ctx* c, T* const r[6], double dt, GraphState* gs, double* err,
-                        double* hist) {
+                        double* hist, double* mhist) {
   const double thr = 1e-6 / 2e-4;  // atol / rtol of the default controller
   scfft_status st;
   c->g_hedot_stage = 0;
@@ -1177,7 +1179,11 @@ scfft_status graph_step(scfft_ctx* c, T* const r[6], double dt, GraphState* gs, 
   HIPCHK(c, launch_combo<T>(r[B_Y1], r[B_Y], r[B_K1], dt * (2.0 / 9.0), r[B_K2], dt * (1.0 / 3.0),
                             r[B_K3], dt * (4.0 / 9.0), 3 * c->nodes, c->stream, &gs->stop));
   c->g_hedot_stage = 2;
-  if ((st = rhs_impl<T>(c, 0.0, r[B_Y1], r[B_K4], nullptr)) < 0) return st;
+  // the FSAL evaluation at the new state also sums its moment (power-law pass)
+  double* mom = wsp<double>(c, c->off_mom);
+  if ((st = rhs_impl<T>(c, 0.0, r[B_Y1], r[B_K4], nullptr, nullptr, 0.0, mom)) < 0) return st;
+  const int xbm = xpass_blocks<T>(make_plan<T>(c));
+  HIPCHK(c, launch_graph_moment(mom, xbm, gs, mhist, c->stream));
   double* part = wsp<double>(c, c->off_part);
   HIPCHK(c, launch_errnorm<T>(r[B_Y], r[B_Y1], r[B_K1], r[B_K2], r[B_K3], r[B_K4], dt, thr,
                               3 * c->nodes, part, kReduceBlocks, c->stream, &gs->stop));
@@ -1197,6 +1203,7 @@ scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* 
   double* err = reinterpret_cast<double*>(gws + L.off_err);
   double* hist = reinterpret_cast<double*>(gws + L.off_hist);
   double* tab = reinterpret_cast<double*>(gws + L.off_tab);
+  double* mhist = reinterpret_cast<double*>(gws + L.off_mhist);
   // applied-field rates at the stage times of every step, evaluated on the host
   c->graph_hedot.assign((size_t)steps * 9, 0.0);
   const double frac[3] = {0.5, 0.75, 1.0};
@@ -1208,6 +1215,7 @@ scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* 
       for (int d = 0; d < 3; ++d) c->graph_hedot[(size_t)s * 9 + q * 3 + d] = hd[d];
     }
   }
+  c->graph_accepted = -1;
   HIPCHK(c, hipMemcpyAsync(tab, c->graph_hedot.data(), c->graph_hedot.size() * sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_graph_reset(gs, c->stream));
@@ -1244,7 +1252,7 @@ scfft_status graph_begin_impl(scfft_ctx* c, double t0, double t1, int steps, T* 
         st = fail(c, SCFFT_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
         break;
       }
-      const scfft_status sst = graph_step<T>(c, r, dt, gs, err, hist);
+      const scfft_status sst = graph_step<T>(c, r, dt, gs, err, hist, mhist);
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(cs, &g);
       if (sst < 0) {
@@ -1318,6 +1326,7 @@ scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
     HIPCHK(c, hipMemcpyAsync(&err_last, c->graph_ws + L.off_hist + (size_t)last * sizeof(double),
                              sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->graph_accepted = hs.step;
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
     stats->accepted = hs.step;
@@ -1896,6 +1905,28 @@ scfft_status scfft_integrate_wait(scfft_ctx* ctx, scfft_ode_stats* stats) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (!ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "no graph integration is enqueued");
   return ctx->prec == SCFFT_F64 ? graph_wait_impl<double>(ctx, stats) : graph_wait_impl<float>(ctx, stats);
+}
+
+scfft_status scfft_graph_moments(scfft_ctx* ctx, int32_t omega_only, int32_t max_steps, double* m_Am2,
+                                 int32_t* n_steps) {
+  if (!ctx || !n_steps || max_steps < 0 || (max_steps > 0 && !m_Am2)) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "call scfft_integrate_wait first");
+  if (ctx->graph_accepted < 0 || !ctx->graph_ws)
+    return fail(ctx, SCFFT_ERR_STATE, "no graph integration has been waited for");
+  const int n = std::min(max_steps, ctx->graph_accepted);
+  *n_steps = ctx->graph_accepted;
+  if (n == 0) return SCFFT_OK;
+  const GraphLayout L = graph_layout(ctx->graph_steps);
+  std::vector<double> h((size_t)n * 6);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->graph_ws + L.off_mhist, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const double dv = ctx->h[0] * ctx->h[1] * ctx->h[2];
+  const double scale = ctx->u.jc * std::pow(ctx->u.l, 4.0);  // m' -> A m^2
+  const int first = omega_only ? 3 : 0;
+  for (int k = 0; k < n; ++k)
+    for (int d = 0; d < 3; ++d) m_Am2[3 * (size_t)k + d] = 0.5 * h[6 * (size_t)k + first + d] * dv * scale;
+  return SCFFT_OK;
 }
 
 scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev) {

@@ -101,6 +101,8 @@ _SIGS = {
     "scfft_set_mask": (C.c_int, [_P, _P]),
     "scfft_mask_betti": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "scfft_stray_fraction": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "scfft_graph_moments": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int32)]),
     "scfft_mask_betti_host": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]),
     "scfft_set_jc_map": (C.c_int, [_P, _P]),
     "scfft_set_drive": (C.c_int, [_P, C.POINTER(Drive)]),
@@ -396,6 +398,16 @@ def scfft_autotune(ctx, h, calls=5):
     ms = C.c_double()
     _check(load().scfft_autotune(ctx, _ptr(h), int(calls), C.byref(fx), C.byref(ms)), ctx)
     return fx.value, ms.value
+
+
+def scfft_graph_moments(ctx, max_steps, omega_only=0):
+    """Moments (A m^2) of the states accepted by the last waited graph
+    integration: array [accepted][3]."""
+    m = np.zeros((max(1, int(max_steps)), 3))
+    n = C.c_int32()
+    _check(load().scfft_graph_moments(ctx, int(omega_only), int(max_steps),
+                                      m.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)), ctx)
+    return m[:min(int(max_steps), n.value)]
 
 
 def scfft_graph_workspace_size(ctx, steps):

@@ -175,3 +175,32 @@ def test_graph_reuse_across_calls_and_state_changes():
     torch.cuda.synchronize()
     assert rel_max(hg.cpu().numpy(), hp.cpu().numpy()) < 1e-12
     assert st.iters_total == sp.iters_total == sp.rhs_calls * 3
+
+
+@pytest.mark.parametrize("prec,fuse", [(scfft.F64, 0), (scfft.F64, 2), (scfft.F32, 1)])
+def test_graph_moment_history(prec, fuse):
+    """The moment of every accepted state, summed on the device during graph
+    replay, equals what an observer of the plain fixed-step integrator reads
+    with scfft_step_moment (all nodes and Omega only)."""
+    cfg = CUBE32
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    _, u = oracle_problem(cfg)
+    x = np.arange(32) - 15.5
+    win = np.exp(-(x[None, None, :] ** 2 + x[None, :, None] ** 2 + x[:, None, None] ** 2) / 60.0)
+    h0 = to_dev(torch, state(cfg, seed=7) * win, dt)
+    t1_s, steps = 0.02, 5
+    a = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=fuse)
+    ms = []
+    scfft.scfft_integrate(a.ctx, 0.0, t1_s, h0.clone(), scfft.default_ode_opts(fixed_steps=steps),
+                          observer=lambda _u, t, _p: ms.append((scfft.scfft_step_moment(a.ctx, 0),
+                                                                scfft.scfft_step_moment(a.ctx, 1))) or 0)
+    b = sim(cfg, precision=prec, fixed_iter=2, fuse_xy=fuse)
+    _graph_run(b, h0.clone(), t1_s, steps)
+    m_all = scfft.scfft_graph_moments(b.ctx, steps + 3)
+    m_in = scfft.scfft_graph_moments(b.ctx, steps, omega_only=1)
+    assert m_all.shape == (steps, 3) and m_in.shape == (steps, 3)
+    ref_all = np.array([m[0] for m in ms])
+    ref_in = np.array([m[1] for m in ms])
+    tol = 1e-12 if prec == scfft.F64 else 1e-5
+    assert np.max(np.abs(m_all - ref_all)) <= tol * np.max(np.abs(ref_all))
+    assert np.max(np.abs(m_in - ref_in)) <= tol * np.max(np.abs(ref_in))
