@@ -120,3 +120,27 @@ def test_create_rejects_bad_shapes():
         scfft.scfft_create(scfft.make_grid((16, 16, 16), (0.01, 0.01, 0.01)),
                            scfft.make_material(0.5, 1e8, 1e-4, 20, 1e-2))
     assert e.value.status == scfft.ERR_ARG
+
+
+def _build_c_client(out):
+    """Compile tests/c/cube_ramp.c, a plain C client of include/scfft.h,
+    against the in-tree library with the system C compiler."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pkg = os.path.join(ROOT, "paper_1803_01346_amd")
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c", "cube_ramp.c"), "-L" + pkg, "-lscfft",
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath," + pkg, "-Wl,-rpath,/opt/rocm/lib", "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return out
+
+
+def test_c_client_compiles_and_links(tmp_path):
+    """The header is plain C11 and the library links into a C program."""
+    scfft.load()                                       # the library is built
+    assert os.path.exists(_build_c_client(str(tmp_path / "cube_ramp")))
