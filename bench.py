@@ -341,6 +341,36 @@ def lens_gain_leg(n_grid=128, f32=False):
     return out
 
 
+def lens_config_leg():
+    """The slit lens of the 256^3 FP32 configuration run to the end of its
+    field ramp (n = 50, jc = 2e8 A/m^2, rho_out = 100, 0 -> 1 T along the
+    axis over 150 s, virgin start, adaptive steps with the stopping rule):
+    the field-concentration factor at the bore centre, |B(0)| / B_applied,
+    at 0.25, 0.5 and 1 T."""
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    cfg = workloads.config("lens256")
+    s = scfft.Simulation(cfg, precision=scfft.F32)
+    h = s.empty_field()
+    scfft.scfft_init_state(s.ctx, 0.0, h)
+    d = cfg["drive"]
+    out, t, steps, rhs = dict(grid=list(cfg["n"]), dtype="f32", n_power=cfg["n_power"],
+                              rho_out=cfg["rho_out"]), 0.0, 0, 0
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    for frac in (0.25, 0.5, 1.0):
+        tt = frac * d["t_ramp_s"]
+        st = scfft.OdeStats()
+        scfft.scfft_integrate(s.ctx, t, tt, h, scfft.default_ode_opts(), stats=st)
+        b = scfft.scfft_probe_b(s.ctx, h, [[0.0, 0.0, 0.0]])[0]
+        out["factor_%gT" % (frac * d["amp_T"])] = round(float((b @ b) ** 0.5) / (frac * d["amp_T"]), 4)
+        steps, rhs, t = steps + st.accepted, rhs + st.rhs_calls, tt
+    torch.cuda.synchronize()
+    out.update(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2))
+    s.close()
+    return out
+
+
 def shield_leg(n_grid=128):
     """The shield run of Sec. 3 (cases A and B, n = 30, rho_out = 20, virgin
     start, adaptive steps, the stopping rule of the exterior iteration,
@@ -442,6 +472,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
     ap.add_argument("--no-lens-gain", action="store_true", help="skip the lens field-concentration run")
     ap.add_argument("--no-shield", action="store_true", help="skip the shield cases A/B run")
+    ap.add_argument("--no-lens-config", action="store_true",
+                    help="skip the 256^3 lens ramp (field-concentration factor at the bore centre)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -513,6 +545,7 @@ def main():
     adj = None if args.no_adjoint else adjoint_leg(cfg)
     gleg = None if args.no_graph else graph_leg()
     shield = None if args.no_shield else shield_leg()
+    lens_cfg = None if args.no_lens_config else lens_config_leg()
     lgain = None
     if not args.no_lens_gain:
         lgain = {"n_power": 30.0, "rho_out": 100.0, "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
@@ -549,6 +582,7 @@ def main():
         "graphs": gleg,
         "lens_gain": lgain,
         "shield": shield,
+        "lens_config": lens_cfg,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,
