@@ -341,6 +341,47 @@ def lens_gain_leg(n_grid=128, f32=False):
     return out
 
 
+def shield_config_leg(outputs=40):
+    """The shield configuration run over its two periods (n = 100, jc = 1e8,
+    0.05 T at 50 Hz and 45 degrees, virgin start, adaptive steps with the
+    stopping rule) in FP64 and FP32: B on the bore axis (z = -1, 0, 1 cm)
+    at evenly spaced output times, its largest magnitude relative to the
+    applied amplitude, and the FP32 / FP64 difference of the probe
+    histories."""
+    import numpy as np
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    cfg = workloads.config("cup128")
+    l = cfg["l_m"]
+    pts = [[0.0, 0.0, -l], [0.0, 0.0, 0.0], [0.0, 0.0, l]]
+    t_end = cfg["t_end_s"]
+    res = {}
+    out = dict(grid=list(cfg["n"]), outputs=outputs, probe_z_m=[p[2] for p in pts])
+    for prec, name in ((scfft.F64, "f64"), (scfft.F32, "f32")):
+        s = scfft.Simulation(cfg, precision=prec)
+        h = s.empty_field()
+        scfft.scfft_init_state(s.ctx, 0.0, h)
+        hist, t, steps, rhs = [], 0.0, 0, 0
+        torch.cuda.synchronize()
+        wall = time.perf_counter()
+        for k in range(1, outputs + 1):
+            tt = t_end * k / outputs
+            st = scfft.OdeStats()
+            scfft.scfft_integrate(s.ctx, t, tt, h, scfft.default_ode_opts(), stats=st)
+            hist.append(scfft.scfft_probe_b(s.ctx, h, pts))
+            steps, rhs, t = steps + st.accepted, rhs + st.rhs_calls, tt
+        torch.cuda.synchronize()
+        res[name] = np.array(hist)
+        mags = np.sqrt(np.sum(res[name] ** 2, axis=2))
+        out[name] = dict(steps=steps, rhs_calls=rhs, wall_s=round(time.perf_counter() - wall, 2),
+                         max_abs_B_over_applied=[round(float(v) / cfg["drive"]["amp_T"], 4)
+                                                 for v in mags.max(axis=0)])
+        s.close()
+    d = res["f32"] - res["f64"]
+    out["f32_vs_f64_rel_l2"] = float(np.sqrt(np.sum(d ** 2) / np.sum(res["f64"] ** 2)))
+    return out
+
+
 def lens_config_leg():
     """The slit lens of the 256^3 FP32 configuration run to the end of its
     field ramp (n = 50, jc = 2e8 A/m^2, rho_out = 100, 0 -> 1 T along the
@@ -472,6 +513,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
     ap.add_argument("--no-lens-gain", action="store_true", help="skip the lens field-concentration run")
     ap.add_argument("--no-shield", action="store_true", help="skip the shield cases A/B run")
+    ap.add_argument("--no-shield-config", action="store_true",
+                    help="skip the two-period shield run (bore-axis probe, FP64 and FP32)")
     ap.add_argument("--no-lens-config", action="store_true",
                     help="skip the 256^3 lens ramp (field-concentration factor at the bore centre)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -546,6 +589,7 @@ def main():
     gleg = None if args.no_graph else graph_leg()
     shield = None if args.no_shield else shield_leg()
     lens_cfg = None if args.no_lens_config else lens_config_leg()
+    shield_cfg = None if args.no_shield_config else shield_config_leg()
     lgain = None
     if not args.no_lens_gain:
         lgain = {"n_power": 30.0, "rho_out": 100.0, "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
@@ -583,6 +627,7 @@ def main():
         "lens_gain": lgain,
         "shield": shield,
         "lens_config": lens_cfg,
+        "shield_config": shield_cfg,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,
