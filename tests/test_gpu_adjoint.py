@@ -276,3 +276,51 @@ def test_parameter_gradients_against_central_differences():
         fd = (float(loss(s, kap0, p_of(theta + eps))) - float(loss(s, kap0, p_of(theta - eps)))) / (2 * eps)
         dth = float(np.dot(p_bar, [amp * math.cos(theta), 0.0, -amp * math.sin(theta)]))
         assert rel(dth, fd) < 1e-4
+
+
+def test_config5_gradients_against_central_differences():
+    """The adjoint configuration at full size: the 128^3 shield with a jc map
+    kappa = 1 + 0.1 N(0,1) (seed 5), a critical-state start, 2000 fixed
+    steps of 2e-5 s (checkpoints every 50), loss = mean over the bore of
+    |h(t_end)|^2.  The gradients in n and in a global jc (a uniform scaling
+    of kappa) from one adjoint run agree with central differences of the
+    forward path (relative step 1e-6) within 1e-4."""
+    import math
+    from paper_1803_01346_amd import autograd as sag
+    cfg = workloads.config("cup128")
+    steps, every, t1_s = 2000, 50, 2000 * 2e-5
+    n = cfg["n"]
+    kap0 = torch.from_numpy(1.0 + 0.1 * np.random.default_rng(5).normal(size=(n[2], n[1], n[0]))).cuda()
+    x = -4.0 + (np.arange(n[0]) + 0.5) * (8.0 / n[0])
+    r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2) * np.ones((n[2], n[1], n[0]))
+    bore = torch.from_numpy(((r < 0.7) & (np.abs(x)[:, None, None] < 1.5)).astype(np.float64)).cuda()
+    nb = float(bore.sum())
+
+    def make(n_power):
+        return sim(dict(cfg, n_power=n_power), fixed_iter=3)
+
+    s = make(cfg["n_power"])
+    he, _ = scfft.scfft_drive_eval(s.drive, s.material, 0.005)
+    h0 = to_dev(torch, state(cfg, seed=0, bg=tuple(he)), torch.float64)
+    p0 = sag.drive_vector(s)
+
+    def loss(sim_, kap):
+        nt = torch.tensor(float(sim_.cfg["n_power"]), dtype=torch.float64)
+        hT = sag.IntegrateParams.apply(h0, kap, nt, p0, sim_, 0.0, t1_s, steps, every)
+        return (hT * hT).sum(dim=0).mul(bore).sum() / nb
+
+    kap = kap0.clone().requires_grad_(True)
+    nt = torch.tensor(float(cfg["n_power"]), dtype=torch.float64, requires_grad=True)
+    hT = sag.IntegrateParams.apply(h0, kap, nt, p0, s, 0.0, t1_s, steps, every)
+    L = (hT * hT).sum(dim=0).mul(bore).sum() / nb
+    L.backward()
+    g_jc, g_n = float((kap.grad * kap0).sum()), float(nt.grad)
+    eps = 1e-6
+    with torch.no_grad():
+        fd_jc = (float(loss(s, kap0 * (1 + eps))) - float(loss(s, kap0 * (1 - eps)))) / (2 * eps)
+        n0 = cfg["n_power"]
+        fd_n = (float(loss(make(n0 * (1 + eps)), kap0)) - float(loss(make(n0 * (1 - eps)), kap0))) / (2 * n0 * eps)
+    print("dL/dln(jc) adjoint %.9e fd %.9e; dL/dn adjoint %.9e fd %.9e" % (g_jc, fd_jc, g_n, fd_n))
+    assert abs(g_jc - fd_jc) <= 1e-4 * abs(fd_jc)
+    assert abs(g_n - fd_n) <= 1e-4 * abs(fd_n)
+    assert math.isfinite(float(L.detach()))
