@@ -122,6 +122,22 @@ def roofline_of(per_kind, traffic=None):
             "launches": d["launches"]}
 
 
+def rhs_event_median(sim, h, hd, calls=100, warm=10):
+    """Median duration (ms) of single rhs_eval calls, each bracketed by HIP
+    events on the context's stream (torch's current stream here)."""
+    import torch
+    for _ in range(warm):
+        sim.rhs_eval(T_STAR, h, hd)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, b in ev:
+        a.record()
+        sim.rhs_eval(T_STAR, h, hd)
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    return ts[len(ts) // 2]
+
+
 def rhs_bandwidth(sim, h, hd, rhs_ps, n, calls=10):
     """The whole right-hand side against the HBM peak: its bytes per call
     (the library's count for the launches of this schedule, and the counter
@@ -560,6 +576,7 @@ def main():
 
     # right-hand side alone (no integrator work)
     rhs_ps, hd64 = time_rhs_only(sim, h, 50)
+    rhs_med_ms = rhs_event_median(sim, h, hd64)
     rhs_hbm = None if args.no_events else rhs_bandwidth(sim, h, hd64, rhs_ps, n)
 
     fp32 = None
@@ -618,6 +635,7 @@ def main():
                                "iterations per RHS, moment readout per step" % (args.config, FIXED_ITER),
                    "grid": list(n), "exterior_iters": FIXED_ITER, "rhs_per_step": 3},
         "rhs_only": round(rhs_ps, 2),
+        "rhs_median_ms": round(rhs_med_ms, 4),
         "rhs_hbm": rhs_hbm,
         "fp32": fp32,
         "converged": converged,
