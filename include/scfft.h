@@ -128,12 +128,17 @@ typedef struct {
  *   fuse_xy      per-component steps (warm start, masks, exterior update with
  *                fixed_iter) as one fused xy-plane pass instead of y inverse,
  *                x pass, y forward, where the plane fits on chip (Nx = Ny <=
- *                128): 0 never, 1 (default) where measured faster (FP32),
- *                2 always.  Results agree to rounding.
+ *                128): 0 never, 1 (default) where measured faster (Nx = Ny
+ *                <= 64), 2 always.  Results agree to rounding.
  *   prune_box    1 (default): skip the parts of the transforms that only touch
  *                zeros or unused values outside the bounding box of Omega
  *                (fields masked to Omega, rates needed on Omega); 0: full
- *                transforms.  Results are identical. */
+ *                transforms.  Results are identical.
+ *   x_alt        0 (default) or 1: the per-component x passes (input, warm
+ *                start, masks, exterior update with fixed_iter, store) hold
+ *                the alternate number of elements per thread (4 instead of 8,
+ *                or 8 instead of 4: other radices and rows per block).
+ *                Results agree to rounding; scfft_autotune picks it. */
 typedef struct {
   double delta_it;
   int32_t min_iter;
@@ -143,6 +148,7 @@ typedef struct {
   double sigma_scale;
   int32_t fuse_xy;
   int32_t prune_box;
+  int32_t x_alt;
 } scfft_rhs_opts;
 
 typedef struct {
@@ -264,6 +270,8 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d);
  * default); alpha >= 0.  The reverse mode rejects it (SCFFT_ERR_ARG). */
 scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha);
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o);
+/* The options in force (after scfft_autotune: its choice). */
+scfft_status scfft_get_rhs_opts(const scfft_ctx* ctx, scfft_rhs_opts* o);
 /* Forget the warm start of iteration (5): the next RHS starts from Ohm's law. */
 scfft_status scfft_reset_warm(scfft_ctx* ctx);
 
@@ -289,11 +297,13 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
                              scfft_ode_stats* stats);
 
 /* Autotuner: times one right-hand-side call (fixed_iter > 0) under each pass
- * schedule this grid supports (row/column passes; fused xy-plane passes where
- * a z plane fits in LDS) on the caller's state h, calls times each after a
- * warm-up call, and keeps the faster one as the rhs option fuse_xy (0 or 2).
- * The warm start is restored afterwards.  fuse_xy and ms_per_call (may be
- * NULL) receive the choice and its mean time per call.  Synchronous. */
+ * schedule this grid supports (row/column passes with either element count
+ * of the per-component x passes, rhs option x_alt 0 or 1; fused xy-plane
+ * passes where a z plane fits in LDS) on the caller's state h, calls times
+ * each after a warm-up call, and keeps the fastest as the rhs options fuse_xy
+ * (0 or 2) and x_alt.  The warm start is restored afterwards.  fuse_xy and
+ * ms_per_call (may be NULL) receive the schedule and its mean time per call;
+ * scfft_get_rhs_opts returns all options.  Synchronous. */
 scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, int32_t* fuse_xy,
                             double* ms_per_call);
 

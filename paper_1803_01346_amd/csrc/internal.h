@@ -45,6 +45,7 @@ struct Plan {
   AxisTab<T> ax, ay, az;
   Ranges r;
   const int* stop = nullptr;  // device flag: once nonzero, the passes of this plan return at once
+  int xalt = 0;  // per-component X passes with the alternate element count per thread
   void full_ranges() {
     r = Ranges{0, nz, 0, ny, 0, ny, 0, nz, 0, ny, 0, nz, 0, ny, 0, nz};
   }

@@ -400,14 +400,16 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
 // NC = 3: all three components per row (the power law, the moment, the
 // exterior update with convergence sums); NC = 1: one component per block
 // (blockIdx.y), for the steps that act on each component alone.
-template <typename T, int NX, int OP, int NC>
+// EV: elements-per-thread bound of the row transform (0: the default of the
+// op, ex_max); the schedule autotuner may pick the alternate one.
+template <typename T, int NX, int OP, int NC, int EV = 0>
 __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   if (P.stop && *P.stop) return;  // uniform: the iteration has stopped
   static_assert(NC == 3 || NC == 1, "components per block");
   static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT && OP != X_ADJ_LAST && OP != X_ADJ_LAW),
                 "needs all components");
   constexpr int M = NX / 2;
-  constexpr int E = elems_per_thread(M, ex_max<T, NC, OP>());
+  constexpr int E = elems_per_thread(M, EV ? EV : ex_max<T, NC, OP>());
   constexpr int TPT = M / E;
   constexpr int ROWS = kBlock / TPT;
   static_assert(2 * E <= 32, "store masks hold one bit per node");
@@ -860,9 +862,9 @@ constexpr int tpt_of() {
   return N / elems_per_thread(N, EMAX);
 }
 
-template <typename T, int NX, int NC = 3, int OP = -1>
+template <typename T, int NX, int NC = 3, int OP = -1, int EV = 0>
 static int xblocks_n(const Plan<T>& p) {
-  constexpr int ROWS = kBlock / tpt_of<NX / 2, ex_max<T, NC, OP>()>();
+  constexpr int ROWS = kBlock / tpt_of<NX / 2, EV ? EV : ex_max<T, NC, OP>()>();
   const int rows = (p.r.xyhi - p.r.xylo) * (p.r.xzhi - p.r.xzlo);
   return (rows + ROWS - 1) / ROWS;
 }
@@ -885,11 +887,27 @@ int xpass_blocks(const Plan<T>& p) {
   return -1;
 }
 
+// the alternate bound of a per-component op: 4 where the default is 8 and
+// the other way round
+template <typename T, int OP>
+constexpr int ex_alt() { return ex_max<T, 1, OP>() >= 8 ? 4 : 8; }
+
+template <typename T, int NX, int OP, int NC, int EV = 0>
+static void xlaunch_ev(const Plan<T>& p, const XArgs<T>& a, hipStream_t s, KTime t) {
+  const int nb = xblocks_n<T, NX, NC, OP, EV>(p);
+  if (nb <= 0) return;  // empty row range
+  launch(xpass_kernel<T, NX, OP, NC, EV>, dim3(nb, NC == 3 ? 1 : 3), dim3(kBlock), s, t, p, a);
+}
+
 template <typename T, int NX, int OP, int NC>
 static void xlaunch_op(const Plan<T>& p, const XArgs<T>& a, hipStream_t s, KTime t) {
-  const int nb = xblocks_n<T, NX, NC, OP>(p);
-  if (nb <= 0) return;  // empty row range
-  launch(xpass_kernel<T, NX, OP, NC>, dim3(nb, NC == 3 ? 1 : 3), dim3(kBlock), s, t, p, a);
+  if constexpr (NC == 1) {
+    if (p.xalt) {
+      xlaunch_ev<T, NX, OP, 1, ex_alt<T, OP>()>(p, a, s, t);
+      return;
+    }
+  }
+  xlaunch_ev<T, NX, OP, NC>(p, a, s, t);
 }
 
 template <typename T, int NX, int NC>

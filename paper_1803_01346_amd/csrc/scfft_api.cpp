@@ -178,6 +178,7 @@ Plan<T> make_plan(scfft_ctx* c) {
   }
   p.full_ranges();
   p.stop = c->graph_stop;
+  p.xalt = c->opts.x_alt;
   return p;
 }
 
@@ -450,12 +451,14 @@ hipError_t spectral_middle(scfft_ctx* c, const Plan<T>& p, int sym, double coef)
   return run_y<T>(c, p, true);
 }
 
-// fuse_xy: 0 never, 1 where the fused plane pass measured faster (FP32; in
-// FP64 one 133 KB plane per CU leaves too few waves), 2 always (if it fits).
+// fuse_xy: 0 never, 1 where the fused plane pass measured faster (planes of
+// up to 64 x 64 nodes, both precisions; at 128 x 128 the row/column passes
+// win: one 133 KB FP64 or 67 KB FP32 plane per block leaves too few waves per
+// CU), 2 always (if it fits).
 template <typename T>
 bool use_xy(const scfft_ctx* c, const Plan<T>& p) {
   if (!xypass_supported<T>(p)) return false;
-  return c->opts.fuse_xy >= 2 || (c->opts.fuse_xy == 1 && sizeof(T) == 4);
+  return c->opts.fuse_xy >= 2 || (c->opts.fuse_xy == 1 && p.nx <= 64);
 }
 
 // Fixed iteration count with fused xy-plane passes: the per-component steps
@@ -701,8 +704,14 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
     a.in = h;
     a.in2 = in2;
     a.in2_coef = (T)in2_coef;
-    HIPCHK(c, run_x<T>(c, p, X_FWD, a));
-    HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+    if (use_xy<T>(c, p)) {  // the forward call's fused schedule (fixed count)
+      HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));
+      HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));
+      HIPCHK(c, run_y<T>(c, p, true));
+    } else {
+      HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+      HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+    }
     XArgs<T> al = a;
     al.j_out = jbuf;
     al.clamps = reinterpret_cast<unsigned long long*>(wsp<double>(c, c->off_adjs) + 8);
@@ -1347,8 +1356,11 @@ scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
 template <typename T>
 scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, double* ms_best) {
   const Plan<T> p = make_plan<T>(c);
-  std::vector<int> cand = {0};
-  if (xypass_supported<T>(p)) cand.push_back(2);
+  // (fuse_xy, x_alt): row/column passes with either element count of the
+  // per-component x passes, and the fused plane pass where it fits (which
+  // has no per-component x pass to vary)
+  std::vector<std::pair<int, int>> cand = {{0, 0}, {0, 1}};
+  if (xypass_supported<T>(p)) cand.push_back({2, 0});
   const size_t fb = 3 * c->nodes * sizeof(T);
   T* out = wsp<T>(c, c->off_ode + 4 * fb);
   T* saved = wsp<T>(c, c->off_ode + 5 * fb);
@@ -1366,12 +1378,13 @@ scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, dou
     (void)hipEventDestroy(e0);
     return fail(c, SCFFT_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(he));
   }
-  const int keep = c->opts.fuse_xy;
+  const int keep = c->opts.fuse_xy, keep_alt = c->opts.x_alt;
   scfft_status st = SCFFT_OK;
   double best = INFINITY;
-  int pick = keep;
-  for (int fx : cand) {
-    c->opts.fuse_xy = fx;
+  int pick = keep, pick_alt = keep_alt;
+  for (const auto& fa : cand) {
+    c->opts.fuse_xy = fa.first;
+    c->opts.x_alt = fa.second;
     if ((he = restore()) != hipSuccess) break;
     if ((st = rhs_impl<T>(c, 0.0, h, out, nullptr)) < 0) break;          // warm-up
     if ((he = hipEventRecord(e0, c->stream)) != hipSuccess) break;
@@ -1383,17 +1396,20 @@ scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, dou
     if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
     if (ms / calls < best) {
       best = ms / calls;
-      pick = fx;
+      pick = fa.first;
+      pick_alt = fa.second;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->opts.fuse_xy = keep;
+  c->opts.x_alt = keep_alt;
   if (st < 0) return st;
   if (he != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "autotune: %s", hipGetErrorString(he));
   HIPCHK(c, restore());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->opts.fuse_xy = pick;
+  c->opts.x_alt = pick_alt;
   ++c->epoch;
   if (choice) *choice = pick;
   if (ms_best) *ms_best = best;
@@ -1518,6 +1534,7 @@ void scfft_default_rhs_opts(scfft_rhs_opts* o) {
   o->sigma_scale = 1.0;
   o->fuse_xy = 1;
   o->prune_box = 1;
+  o->x_alt = 0;
 }
 
 void scfft_default_ode_opts(scfft_ode_opts* o) {
@@ -1720,7 +1737,8 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ++ctx->epoch;
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
-      !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2)
+      !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2 ||
+      o->x_alt < 0 || o->x_alt > 1)
     return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");
   const bool resigma = o->sigma_scale != ctx->opts.sigma_scale;
   ctx->opts = *o;
@@ -1729,6 +1747,12 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
                  std::sqrt(ctx->h[0] * ctx->h[0] + ctx->h[1] * ctx->h[1] + ctx->h[2] * ctx->h[2]);
     if (ctx->ws) return ctx->prec == SCFFT_F64 ? upload_tables<double>(ctx) : upload_tables<float>(ctx);
   }
+  return SCFFT_OK;
+}
+
+scfft_status scfft_get_rhs_opts(const scfft_ctx* ctx, scfft_rhs_opts* o) {
+  if (!ctx || !o) return SCFFT_ERR_ARG;
+  *o = ctx->opts;
   return SCFFT_OK;
 }
 

@@ -58,7 +58,7 @@ class Shape(C.Structure):
 class RhsOpts(C.Structure):
     _fields_ = [("delta_it", C.c_double), ("min_iter", C.c_int32), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("smooth_phi", C.c_int32), ("sigma_scale", C.c_double),
-                ("fuse_xy", C.c_int32), ("prune_box", C.c_int32)]
+                ("fuse_xy", C.c_int32), ("prune_box", C.c_int32), ("x_alt", C.c_int32)]
 
 
 class RhsStats(C.Structure):
@@ -101,6 +101,7 @@ _SIGS = {
     "scfft_set_mask": (C.c_int, [_P, _P]),
     "scfft_mask_betti": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "scfft_stray_fraction": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "scfft_get_rhs_opts": (C.c_int, [_P, _P]),
     "scfft_graph_moments": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int32)]),
     "scfft_mask_betti_host": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]),
@@ -390,6 +391,12 @@ def scfft_step_moment(ctx, omega_only=0):
     m = (C.c_double * 3)()
     _check(load().scfft_step_moment(ctx, int(omega_only), m), ctx)
     return np.array(m[:])
+
+
+def scfft_get_rhs_opts(ctx):
+    o = RhsOpts()
+    _check(load().scfft_get_rhs_opts(ctx, C.byref(o)), ctx)
+    return o
 
 
 def scfft_autotune(ctx, h, calls=5):

@@ -138,13 +138,16 @@ def test_integrate_adjoint_fp64(cfg):
     assert np.max(np.abs(pb - g["p_bar"])) <= 1e-10 * np.max(np.abs(g["p_bar"]))
 
 
-def test_integrate_adjoint_checkpoint_interval_and_forward_agree():
+@pytest.mark.parametrize("fuse", [0, 2])
+def test_integrate_adjoint_checkpoint_interval_and_forward_agree(fuse):
     """Any checkpoint interval gives bitwise the same gradient (the recomputed
-    segments repeat the forward arithmetic), and the forward result is that of
-    scfft_integrate's fixed-step mode after a warm-start reset."""
+    segments repeat the forward arithmetic, and where the tape holds no j the
+    reverse call recomputes it with the forward call's pass schedule), and the
+    forward result is that of scfft_integrate's fixed-step mode after a
+    warm-start reset."""
     cfg = SQZ
     prob, u = oracle_problem(cfg, fixed_iter=2)
-    s = sim(cfg, fixed_iter=2)
+    s = sim(cfg, fixed_iter=2, fuse_xy=fuse)
     h0 = _scaled_state(cfg, prob, 13)
     ybar = state(cfg, seed=14, bg=(0.0, 0.0, 0.0))
     t1_s, steps = 2e-3 * u.t0, 6
