@@ -76,6 +76,7 @@ def rhs_vjp(prob, t, h, warm_used, lam, mu=None):
     K = prob.opts.fixed_iter
     assert K > 0
     assert prob.field_law is None, "reverse mode of the field-dependent law is not written"
+    assert getattr(prob, "aniso", None) is None, "reverse mode of the anisotropic law is not written"
     inside = prob.chi.astype(np.float64)
     outside = 1.0 - inside
     # forward quantities the adjoint needs: j = C h (Eq. 4)

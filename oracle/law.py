@@ -13,17 +13,25 @@ definition with a power; the GPU path uses a log form, and tests compare.
 import numpy as np
 
 
-def power_law(j, n, kappa=None):
-    """e' = (|j'|/kappa)^(n-1) j'/kappa, pointwise, e'(0) = 0."""
+def power_law(j, n, kappa=None, aniso=None):
+    """e' = (|j'|/kappa)^(n-1) j'/kappa, pointwise, e'(0) = 0.
+
+    aniso = (a_x, a_y, a_z), all > 0: an anisotropic law (the paper allows
+    other relations after Eq. 1 and fixes none; this form is user-chosen),
+    the gradient in j' of the dissipation potential
+        U(j') = kappa/(n+1) (|j'|_A/kappa)^(n+1),  |j'|_A^2 = sum_c a_c j'_c^2,
+    that is e' = (|j'|_A/kappa)^(n-1) A j'/kappa with A = diag(a).  A = I is
+    the isotropic law."""
     j = np.asarray(j, dtype=np.float64)
-    a = np.sqrt(j[0] ** 2 + j[1] ** 2 + j[2] ** 2)
+    w = np.ones(3) if aniso is None else np.asarray(aniso, dtype=np.float64)
+    a = np.sqrt(w[0] * j[0] ** 2 + w[1] * j[1] ** 2 + w[2] * j[2] ** 2)
     if kappa is None:
         kappa = np.ones_like(a)
     r = a / kappa
     with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
         rho = np.power(r, n - 1.0) / kappa
     rho = np.where(a > 0.0, rho, 0.0)
-    return j * rho
+    return w.reshape((3,) + (1,) * (j.ndim - 1)) * j * rho
 
 
 def field_kappa(kappa, h, field_law):
@@ -38,11 +46,12 @@ def field_kappa(kappa, h, field_law):
     return base / np.power(1.0 + mag / hk, alpha)
 
 
-def constitutive(j, chi, n, rho_out, kappa=None, h=None, field_law=None):
+def constitutive(j, chi, n, rho_out, kappa=None, h=None, field_law=None, aniso=None):
     """e = rho(|j|) j in the superconductor (chi = 1), rho_out j outside; with
-    field_law the critical density depends on the local field h."""
+    field_law the critical density depends on the local field h; with aniso
+    the anisotropic law of power_law."""
     j = np.asarray(j, dtype=np.float64)
     inside = np.asarray(chi) != 0
     if field_law is not None:
         kappa = field_kappa(kappa, h, field_law)
-    return np.where(inside, power_law(j, n, kappa), rho_out * j)
+    return np.where(inside, power_law(j, n, kappa, aniso), rho_out * j)

@@ -42,7 +42,8 @@ class Problem:
     """Everything rhs_eval needs besides the state: grid, mask, material,
     drive and options, plus the warm-start memory (hdot_out of the last call)."""
 
-    def __init__(self, grid, chi, n_power, rho_out, drive, opts=None, kappa=None, field_law=None):
+    def __init__(self, grid, chi, n_power, rho_out, drive, opts=None, kappa=None, field_law=None,
+                 aniso=None):
         self.grid = grid
         self.chi = np.asarray(chi, dtype=np.uint8)
         self.n = float(n_power)
@@ -51,6 +52,7 @@ class Problem:
         self.opts = opts if opts is not None else RhsOptions()
         self.kappa = kappa
         self.field_law = field_law  # (h_K, alpha): field-dependent critical density, or None
+        self.aniso = aniso          # (a_x, a_y, a_z): anisotropic law, or None (isotropic)
         self.warm = None            # hdot on Omega_out from the most recent call
         self.last_iters = 0
         self.last_deltas = []
@@ -66,7 +68,8 @@ def rhs_eval(prob, t, h):
     o = prob.opts
 
     j = operators.curl_s(h, g)                                   # Eq. 4
-    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out, prob.kappa, h, prob.field_law)  # Eq. 1
+    e = law.constitutive(j, prob.chi, prob.n, prob.rho_out, prob.kappa, h, prob.field_law,
+                         prob.aniso)                             # Eq. 1
     hdot_in = -operators.curl_s(e, g) * inside                   # Eq. 3 on Omega
     if prob.warm is None:
         hdot_out = -operators.curl_s(e, g) * outside             # Ohm-law start

@@ -86,3 +86,56 @@ def test_field_dependent_critical_density():
     # outside the superconductor the field law does not enter
     chi0 = np.zeros((4, 5, 6), dtype=np.uint8)
     assert np.array_equal(law.constitutive(j, chi0, 25.0, 20.0, kap, h, (hk, 1.0)), 20.0 * j)
+
+
+def _potential(j, n, kappa, a):
+    # U(j) = kappa/(n+1) (|j|_A/kappa)^(n+1), |j|_A^2 = sum_c a_c j_c^2
+    ja = np.sqrt(np.sum(np.asarray(a).reshape(3, 1) * j * j, axis=0))
+    return kappa / (n + 1.0) * (ja / kappa) ** (n + 1.0)
+
+
+@pytest.mark.parametrize("n", [1.0, 5.0, 30.0])
+def test_anisotropic_law_is_the_gradient_of_its_potential(n):
+    # e = grad_j U by central differences of U (a written-out potential, not
+    # the law's formula): a dropped weight or a wrong exponent fails here
+    rng = np.random.default_rng(11)
+    a = (1.0, 0.4, 2.5)
+    kap = 1.3
+    j = rng.uniform(0.6, 1.2, size=(3, 8)) * rng.choice([-1.0, 1.0], size=(3, 8))
+    e = law.power_law(j, n, np.full(8, kap), a)
+    step = 1e-6
+    for c in range(3):
+        d = np.zeros((3, 1))
+        d[c] = step
+        fd = (_potential(j + d, n, kap, a) - _potential(j - d, n, kap, a)) / (2 * step)
+        assert np.allclose(e[c], fd, rtol=1e-6, atol=1e-9)
+
+
+def test_anisotropic_law_special_cases():
+    rng = np.random.default_rng(12)
+    j = rng.normal(size=(3, 40))
+    kap = 1.0 + 0.2 * rng.random(40)
+    # A = I: the isotropic law exactly
+    assert np.array_equal(law.power_law(j, 25.0, kap, (1.0, 1.0, 1.0)), law.power_law(j, 25.0, kap))
+    # A = lambda I: |j|_A = sqrt(lambda)|j|, so e scales by lambda^((n+1)/2)
+    lam, n = 1.7, 9.0
+    assert np.allclose(law.power_law(j, n, kap, (lam,) * 3), lam ** ((n + 1) / 2) * law.power_law(j, n, kap),
+                       rtol=1e-12)
+    # current along one axis: the one-dimensional law with critical density
+    # kappa / sqrt(a_c), scaled by sqrt(a_c): e_c = a_c^((n+1)/2) (|j|/kappa)^(n-1) j/kappa
+    a = (0.5, 2.0, 3.0)
+    for c in range(3):
+        jc = np.zeros((3, 40))
+        jc[c] = j[c]
+        e = law.power_law(jc, n, kap, a)
+        want = a[c] ** ((n + 1) / 2) * (np.abs(j[c]) / kap) ** (n - 1) * j[c] / kap
+        assert np.allclose(e[c], want, rtol=1e-12)
+        assert np.all(e[[k for k in range(3) if k != c]] == 0.0)
+    # odd, and dissipative: e . j = (|j|_A/kappa)^(n+1) kappa >= 0
+    e = law.power_law(j, n, kap, a)
+    assert np.array_equal(law.power_law(-j, n, kap, a), -e)
+    ja = np.sqrt(np.sum(np.reshape(a, (3, 1)) * j * j, axis=0))
+    assert np.allclose(np.sum(e * j, axis=0), (ja / kap) ** (n + 1) * kap, rtol=1e-12)
+    # outside the superconductor the anisotropy does not enter
+    chi0 = np.zeros(40, dtype=np.uint8)
+    assert np.array_equal(law.constitutive(j, chi0, n, 20.0, kap, aniso=a), 20.0 * j)
