@@ -269,6 +269,16 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d);
  * used in Eq. 1 in place of jc kappa(x).  b0_T = 0 switches it off (the
  * default); alpha >= 0.  The reverse mode rejects it (SCFFT_ERR_ARG). */
 scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha);
+/* Anisotropic current-voltage relation, another relation that Sec. 2 allows
+ * in place of Eq. 1 (the paper fixes no form): in Omega
+ *   e = e0 (|j|_A / jc_loc)^(n-1) A j / jc_loc,  A = diag(a[0], a[1], a[2]),
+ *   |j|_A^2 = a[0] jx^2 + a[1] jy^2 + a[2] jz^2,
+ * the gradient of the dissipation potential jc_loc e0/(n+1) (|j|_A/jc_loc)^(n+1),
+ * with jc_loc = jc kappa(x) (and the field law's factor, if set); a current
+ * along axis c alone meets e0 at jc_loc / sqrt(a[c])^((n+1)/n).  Weights in
+ * x, y, z order, finite and > 0; NULL or (1, 1, 1) restores the isotropic
+ * law (the default).  The reverse mode rejects it (SCFFT_ERR_ARG). */
+scfft_status scfft_set_anisotropy(scfft_ctx* ctx, const double a[3]);
 scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o);
 /* The options in force (after scfft_autotune: its choice). */
 scfft_status scfft_get_rhs_opts(const scfft_ctx* ctx, scfft_rhs_opts* o);

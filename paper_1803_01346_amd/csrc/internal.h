@@ -100,6 +100,10 @@ struct XArgs {
   // X_LAW: field-dependent critical density kappa / (1 + |h| hk_inv)^kim_alpha,
   // h = in + in2_coef in2 read at Omega nodes; hk_inv = 0: independent of h
   T hk_inv, kim_alpha;
+  // X_LAW: anisotropic law e = (|j|_A / kappa)^(n-1) A j / kappa, A = diag(aniso_w),
+  // |j|_A^2 = sum_c aniso_w[c] j_c^2; aniso = 0: the isotropic law
+  T aniso_w[3];
+  int aniso;
   T hedot[3];
   int omega_only;        // X_MOMENT: 1 = chi nodes only
   int track;             // X_HIN, X_UPDATE*: 1 = keep every iterate in `out` and sum

@@ -397,6 +397,30 @@ __device__ __forceinline__ void power_law(T& a, T& b, T& c, T npow, T lnk, T exp
   }
 }
 
+// Anisotropic law (a user-chosen relation in place of Eq. 1, which the paper
+// allows): the gradient in j of kappa/(n+1) (|j|_A/kappa)^(n+1), with
+// |j|_A^2 = wx jx^2 + wy jy^2 + wz jz^2, that is e = (|j|_A/kappa)^(n-1) A j/kappa.
+template <typename T>
+__device__ __forceinline__ void power_law_aniso(T& a, T& b, T& c, T wx, T wy, T wz, T npow, T lnk,
+                                                T expmax, unsigned& clamps) {
+  const T s = wx * a * a + wy * b * b + wz * c * c;
+  if (s > T(0)) {
+    T ex = (npow - T(1)) * (T(0.5) * dev_log<T>(s) - lnk) - lnk;
+    if (ex > expmax) {
+      ex = expmax;
+      ++clamps;
+    }
+    const T f = dev_exp<T>(ex);
+    a *= wx * f;
+    b *= wy * f;
+    c *= wz * f;
+  } else {
+    a = T(0);
+    b = T(0);
+    c = T(0);
+  }
+}
+
 // NC = 3: all three components per row (the power law, the moment, the
 // exterior update with convergence sums); NC = 1: one component per block
 // (blockIdx.y), for the steps that act on each component alone.
@@ -638,7 +662,11 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
             }
             lnk -= A.kim_alpha * dev_log1p<T>(sqrt(hs) * A.hk_inv);
           }
-          power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
+          if (A.aniso)
+            power_law_aniso<T>(a[0][e], a[1][e], a[2][e], A.aniso_w[0], A.aniso_w[1], A.aniso_w[2],
+                               A.npow, lnk, A.expmax, clamps);
+          else
+            power_law<T>(a[0][e], a[1][e], a[2][e], A.npow, lnk, A.expmax, clamps);
         } else {
 #pragma unroll
           for (int c = 0; c < 3; ++c) a[c][e] *= A.rho_out;

@@ -77,6 +77,8 @@ struct scfft_ctx {
   const int* g_hedot_step = nullptr;
   int g_hedot_stage = 0;
   double field_hk_inv = 0.0, field_alpha = 0.0;  // e(j, h): 1/h_K (dimensionless), exponent
+  double aniso_w[3] = {1.0, 1.0, 1.0};             // anisotropic law weights
+  bool has_aniso = false;
   bool graph_busy = false;          // an integration is enqueued; scfft_integrate_wait ends it
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   // Captured step graphs are kept for the next graph integration with the same
@@ -290,6 +292,8 @@ XArgs<T> base_args(scfft_ctx* c) {
   a.hedot_stage = c->g_hedot_stage;
   a.hk_inv = (T)c->field_hk_inv;
   a.kim_alpha = (T)c->field_alpha;
+  a.aniso = c->has_aniso ? 1 : 0;
+  for (int d = 0; d < 3; ++d) a.aniso_w[d] = (T)c->aniso_w[d];
   a.npow = (T)c->mat.n_power;
   a.rho_out = (T)c->mat.rho_out;
   a.expmax = sizeof(T) == 4 ? (T)80.0 : (T)700.0;
@@ -689,6 +693,8 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
   if (K <= 0) return fail(c, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
   if (c->field_hk_inv > 0.0)
     return fail(c, SCFFT_ERR_ARG, "reverse mode of the field-dependent law is not implemented");
+  if (c->has_aniso)
+    return fail(c, SCFFT_ERR_ARG, "reverse mode of the anisotropic law is not implemented");
   const Plan<T> p = make_plan<T>(c);
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
   const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
@@ -1729,6 +1735,21 @@ scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
   // |B| / B0 = mu0 h_scale |h'| / B0 with h' the dimensionless field (Eq. 8)
   ctx->field_hk_inv = b0_T > 0.0 ? kMu0 * ctx->u.h_scale / b0_T : 0.0;
   ctx->field_alpha = b0_T > 0.0 ? alpha : 0.0;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_set_anisotropy(scfft_ctx* ctx, const double a[3]) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  ++ctx->epoch;
+  if (a) {
+    for (int d = 0; d < 3; ++d)
+      if (!(a[d] > 0.0) || !std::isfinite(a[d]))
+        return fail(ctx, SCFFT_ERR_ARG, "anisotropy weights must be finite and > 0");
+  }
+  const bool iso = !a || (a[0] == 1.0 && a[1] == 1.0 && a[2] == 1.0);
+  for (int d = 0; d < 3; ++d) ctx->aniso_w[d] = iso ? 1.0 : a[d];
+  ctx->has_aniso = !iso;
   return SCFFT_OK;
 }
 

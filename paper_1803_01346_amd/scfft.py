@@ -108,6 +108,7 @@ _SIGS = {
     "scfft_set_jc_map": (C.c_int, [_P, _P]),
     "scfft_set_drive": (C.c_int, [_P, C.POINTER(Drive)]),
     "scfft_set_field_law": (C.c_int, [_P, C.c_double, C.c_double]),
+    "scfft_set_anisotropy": (C.c_int, [_P, _P]),
     "scfft_set_rhs_opts": (C.c_int, [_P, C.POINTER(RhsOpts)]),
     "scfft_reset_warm": (C.c_int, [_P]),
     "scfft_init_state": (C.c_int, [_P, C.c_double, _P]),
@@ -343,6 +344,14 @@ def scfft_set_drive(ctx, drive):
 
 def scfft_set_field_law(ctx, b0_T, alpha=1.0):
     return _check(load().scfft_set_field_law(ctx, float(b0_T), float(alpha)), ctx)
+
+
+def scfft_set_anisotropy(ctx, weights=None):
+    """Anisotropic law weights (a_x, a_y, a_z); None restores the isotropic law."""
+    if weights is None:
+        return _check(load().scfft_set_anisotropy(ctx, None), ctx)
+    w = (C.c_double * 3)(*[float(v) for v in weights])
+    return _check(load().scfft_set_anisotropy(ctx, w), ctx)
 
 
 def scfft_set_rhs_opts(ctx, opts):
