@@ -68,6 +68,10 @@ struct scfft_ctx {
   // and whether an observer callback is running (scfft_step_moment)
   const void* mom_state = nullptr;
   const void* obs_state = nullptr;  // state shown to the running observer, else null
+  // moment sums (all nodes, Omega) of mom_state, read back with the step's
+  // error norm in one transfer; valid while mom_sums_for == mom_state
+  double mom_sums[6] = {0, 0, 0, 0, 0, 0};
+  const void* mom_sums_for = nullptr;
 
   // graph-replayed fixed-step integration (scfft_integrate_graph): while a
   // step is captured, passes take their stop flag and applied-field rates
@@ -819,7 +823,10 @@ struct DeviceOps {
     scfft_status s = rhs_impl<T>(c, t, buf[y], buf[dst], c->opts.fixed_iter > 0 ? nullptr : &rs,
                                  state ? nullptr : buf[k], state ? 0.0 : coef, mom);
     if (s < 0) return s;
-    if (mom) c->mom_state = buf[y];
+    if (mom) {
+      c->mom_state = buf[y];
+      c->mom_sums_for = nullptr;  // the sums read so far belong to another state
+    }
     if (c->opts.fixed_iter > 0) {
       st->iters_total += c->opts.fixed_iter;
     } else {
@@ -838,15 +845,30 @@ struct DeviceOps {
                                    3 * c->nodes, c->stream);
     return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "combo: %s", hipGetErrorString(e));
   }
+  // The error norm of the step; where the new state y1 recorded moment
+  // partials (an observer is set), their sums come back in the same
+  // transfer, so the observer's scfft_step_moment costs no second wait.
   int errnorm(Buf y, Buf y1, double dt, double thr, double* err) {
     double* part = wsp<double>(c, c->off_part);
     double* out = wsp<double>(c, c->off_scal);
+    const bool with_mom = obs && c->mom_state == buf[y1];
     hipError_t e = launch_errnorm<T>(buf[y], buf[y1], buf[B_K1], buf[B_K2], buf[B_K3], buf[B_K4],
                                      dt, thr, 3 * c->nodes, part, kReduceBlocks, c->stream);
     if (e == hipSuccess) e = launch_max_partials(part, kReduceBlocks, out, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(err, out, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && with_mom)
+      e = launch_sum_partials(wsp<double>(c, c->off_mom), xpass_blocks<T>(make_plan<T>(c)), 6, 6,
+                              out + 1, c->stream);
+    double r[7];
+    const size_t nb = (with_mom ? 7 : 1) * sizeof(double);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, out, nb, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    return e == hipSuccess ? 0 : fail(c, SCFFT_ERR_DEVICE, "errnorm: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "errnorm: %s", hipGetErrorString(e));
+    *err = r[0];
+    if (with_mom) {
+      for (int k = 0; k < 6; ++k) c->mom_sums[k] = r[1 + k];
+      c->mom_sums_for = buf[y1];
+    }
+    return 0;
   }
   int rate(double thr, double* r) {
     double* part = wsp<double>(c, c->off_part);
@@ -958,6 +980,7 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
   ops.user = user;
   ops.st = st;
   c->mom_state = nullptr;
+  c->mom_sums_for = nullptr;
   HIPCHK(c, hipMemcpyAsync(ops.buf[B_Y], h, fb, hipMemcpyDeviceToDevice, c->stream));
   scfft_ode_opts od = *o;  // convert times to t' = t / t0
   od.dt0_s = o->dt0_s / c->u.t0;
@@ -967,6 +990,7 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
   scfft_status s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
   c->mom_state = nullptr;
   c->obs_state = nullptr;
+  c->mom_sums_for = nullptr;
   HIPCHK(c, hipMemcpyAsync(h, ops.buf[B_Y], fb, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   st->t_s *= c->u.t0;
@@ -2013,15 +2037,19 @@ scfft_status scfft_step_moment(scfft_ctx* ctx, int32_t omega_only, double m_Am2[
   if (!ctx->ws) return fail(ctx, SCFFT_ERR_WORKSPACE, "no workspace attached");
   if (!ctx->obs_state || ctx->mom_state != ctx->obs_state)
     return fail(ctx, SCFFT_ERR_STATE, "scfft_step_moment is valid inside an integrator observer only");
-  const int xb = ctx->prec == SCFFT_F64 ? xpass_blocks<double>(make_plan<double>(ctx))
-                                        : xpass_blocks<float>(make_plan<float>(ctx));
-  const double* part = wsp<double>(ctx, ctx->off_mom);
-  double* out = wsp<double>(ctx, ctx->off_mom) + 6 * ((size_t)ctx->n[1] * ctx->n[2]);
   const int first = omega_only ? 3 : 0;
-  HIPCHK(ctx, launch_sum_partials(part + first, xb, 6, 3, out, ctx->stream));
   double r[3];
-  HIPCHK(ctx, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->mom_sums_for == ctx->obs_state) {  // read back with the step's error norm
+    for (int d = 0; d < 3; ++d) r[d] = ctx->mom_sums[first + d];
+  } else {
+    const int xb = ctx->prec == SCFFT_F64 ? xpass_blocks<double>(make_plan<double>(ctx))
+                                          : xpass_blocks<float>(make_plan<float>(ctx));
+    const double* part = wsp<double>(ctx, ctx->off_mom);
+    double* out = wsp<double>(ctx, ctx->off_mom) + 6 * ((size_t)ctx->n[1] * ctx->n[2]);
+    HIPCHK(ctx, launch_sum_partials(part + first, xb, 6, 3, out, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(r, out, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
   const double dv = ctx->h[0] * ctx->h[1] * ctx->h[2];
   const double scale = ctx->u.jc * std::pow(ctx->u.l, 4.0);  // m' -> A m^2
   for (int d = 0; d < 3; ++d) m_Am2[d] = 0.5 * r[d] * dv * scale;
