@@ -301,7 +301,11 @@ scfft_status scfft_rhs_eval(scfft_ctx* ctx, double t_s, const void* h_dev, void*
  * SCFFT_ERR_STEP_UNDERFLOW h holds the last accepted state.  The state is
  * advanced in a workspace buffer and copied back to h when the call ends;
  * the Runge-Kutta stage arguments y + c k are formed inside the first
- * transform pass of each evaluation. */
+ * transform pass of each evaluation.  With fixed_steps the next step is
+ * enqueued before the host waits for the current one's error norm (the GPU
+ * does not idle during the observer): when the observer stops the run, that
+ * next step has already been evaluated and is dropped, and the context's
+ * warm start is that of its evaluations. */
 scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_dev,
                              const scfft_ode_opts* o, scfft_observer obs, void* user,
                              scfft_ode_stats* stats);

@@ -72,6 +72,10 @@ struct scfft_ctx {
   // error norm in one transfer; valid while mom_sums_for == mom_state
   double mom_sums[6] = {0, 0, 0, 0, 0, 0};
   const void* mom_sums_for = nullptr;
+  // fixed-step integrator: two pinned readback slots (error norm + moment
+  // sums, 8 doubles each) and their events, made on first use
+  double* rb_pin = nullptr;
+  hipEvent_t rb_ev[2] = {nullptr, nullptr};
 
   // graph-replayed fixed-step integration (scfft_integrate_graph): while a
   // step is captured, passes take their stop flag and applied-field rates
@@ -157,7 +161,7 @@ void layout(scfft_ctx* c) {
   // iterates (one field each), and device accumulators of scalar gradients
   c->off_adj = o;   o = align_up(o + 2 * 3 * nodes * w);
   c->off_adjs = o;  o = align_up(o + 16 * sizeof(double));
-  c->off_ode = o;   o = align_up(o + 6 * 3 * nodes * w);
+  c->off_ode = o;   o = align_up(o + 7 * 3 * nodes * w);  // 6 BS23 fields + a third state
   c->off_probe = o; o = align_up(o + (size_t)kProbeChunk * 6 * sizeof(double));
   c->total = o;
 }
@@ -870,6 +874,39 @@ struct DeviceOps {
     }
     return 0;
   }
+  // The same reduction as errnorm, read back into pinned slot `slot`
+  // behind an event instead of waited for: the host can enqueue the next
+  // step first.  errnorm_wait then waits for that event only.
+  const void* pend_mom[2] = {nullptr, nullptr};
+  int errnorm_enqueue(Buf y, Buf y1, double dt, double thr, int slot) {
+    double* part = wsp<double>(c, c->off_part);
+    double* out = wsp<double>(c, c->off_scal);
+    const bool with_mom = obs && c->mom_state == buf[y1];
+    hipError_t e = launch_errnorm<T>(buf[y], buf[y1], buf[B_K1], buf[B_K2], buf[B_K3], buf[B_K4],
+                                     dt, thr, 3 * c->nodes, part, kReduceBlocks, c->stream);
+    if (e == hipSuccess) e = launch_max_partials(part, kReduceBlocks, out, c->stream);
+    if (e == hipSuccess && with_mom)
+      e = launch_sum_partials(wsp<double>(c, c->off_mom), xpass_blocks<T>(make_plan<T>(c)), 6, 6,
+                              out + 1, c->stream);
+    const size_t nb = (with_mom ? 7 : 1) * sizeof(double);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->rb_pin + 8 * slot, out, nb, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->rb_ev[slot], c->stream);
+    if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "errnorm: %s", hipGetErrorString(e));
+    pend_mom[slot] = with_mom ? buf[y1] : nullptr;
+    return 0;
+  }
+  int errnorm_wait(int slot, double* err) {
+    const hipError_t e = hipEventSynchronize(c->rb_ev[slot]);
+    if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "errnorm: %s", hipGetErrorString(e));
+    const double* r = c->rb_pin + 8 * slot;
+    *err = r[0];
+    if (pend_mom[slot]) {
+      for (int k = 0; k < 6; ++k) c->mom_sums[k] = r[1 + k];
+      c->mom_sums_for = pend_mom[slot];
+    }
+    return 0;
+  }
   int rate(double thr, double* r) {
     double* part = wsp<double>(c, c->off_part);
     double* out = wsp<double>(c, c->off_scal);
@@ -967,6 +1004,63 @@ bool valid_ode_opts(const scfft_ode_opts* o) {
          o->max_steps >= 0;
 }
 
+// Fixed-step BS23 (the steps of bs23_run's fixed mode) with the next step
+// enqueued before the host waits for the current step's error norm and
+// moment sums, so the GPU does not idle while the host reads them and runs
+// the observer.  A third state buffer keeps the last accepted state intact
+// until the step after it has been checked: on a non-finite error norm the
+// state is the last accepted one, as in the sequential loop.  An observer
+// that stops the run does so after the next step was already computed (its
+// result is dropped; the warm start is that of its evaluations).
+template <typename T>
+scfft_status fixed_steps_pipelined(scfft_ctx* c, DeviceOps<T>& ops, T* third, double t0, double t1,
+                                   int nsteps, double rtol, double atol, scfft_ode_stats& st) {
+  const double thr = atol / rtol;
+  const double dt = (t1 - t0) / nsteps;
+  auto t_of = [&](int s) { return s < nsteps ? t0 + s * dt : t1; };
+  auto enqueue = [&](int s) -> int {  // step s from buf[B_Y], buf[B_K1] into buf[B_Y1], buf[B_K4]
+    const double t = t_of(s), h = t_of(s + 1) - t;
+    int r;
+    if ((r = ops.rhs_at(t + 0.5 * h, B_Y, B_K1, 0.5 * h, B_K2)) < 0) return r;
+    if ((r = ops.rhs_at(t + 0.75 * h, B_Y, B_K2, 0.75 * h, B_K3)) < 0) return r;
+    if ((r = ops.combo(B_Y1, B_Y, B_K1, h * (2.0 / 9.0), B_K2, h * (1.0 / 3.0), B_K3,
+                       h * (4.0 / 9.0))) < 0)
+      return r;
+    if ((r = ops.rhs(t + h, B_Y1, B_K4)) < 0) return r;
+    st.rhs_calls += 3;
+    return ops.errnorm_enqueue(B_Y, B_Y1, h, thr, s & 1);
+  };
+  int rc;
+  if ((rc = ops.rhs(t0, B_Y, B_K1)) < 0) return (scfft_status)rc;
+  st.rhs_calls += 1;
+  if ((rc = enqueue(0)) < 0) return (scfft_status)rc;
+  for (int s = 0; s < nsteps; ++s) {
+    // buffers of step s: state y_s in B_Y, y_{s+1} in B_Y1, f(y_s) in B_K1,
+    // f(y_{s+1}) in B_K4.  Step s + 1 reads y_{s+1}, f(y_{s+1}) and writes
+    // the free state buffer and f(y_s)'s buffer (read by step s only).
+    T* prev = ops.buf[B_Y];
+    ops.buf[B_Y] = ops.buf[B_Y1];
+    ops.buf[B_Y1] = third;
+    third = prev;
+    std::swap(ops.buf[B_K1], ops.buf[B_K4]);
+    if (s + 1 < nsteps && (rc = enqueue(s + 1)) < 0) return (scfft_status)rc;
+    double err = 0.0;
+    if ((rc = ops.errnorm_wait(s & 1, &err)) < 0) return (scfft_status)rc;
+    if (!std::isfinite(err)) {
+      ops.buf[B_Y] = prev;  // the last accepted state
+      return SCFFT_ERR_NAN;
+    }
+    st.dt_last_s = t_of(s + 1) - t_of(s);
+    st.err_last = err;
+    st.t_s = t_of(s + 1);
+    st.accepted += 1;
+    int stop = 0;
+    if ((rc = ops.observe(t_of(s + 1), &stop)) < 0) return (scfft_status)rc;
+    if (stop) break;
+  }
+  return SCFFT_OK;
+}
+
 template <typename T>
 scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scfft_ode_opts* o,
                             scfft_observer obs, void* user, scfft_ode_stats* st) {
@@ -987,7 +1081,18 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
   od.dt_max_s = o->dt_max_s / c->u.t0;
   std::vector<double> stops = c->drive.kinks();
   for (int i = 0; i < o->n_bp; ++i) stops.push_back(o->breakpoints_s[i] / c->u.t0);
-  scfft_status s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
+  scfft_status s;
+  if (o->fixed_steps > 0 && t1 > t0) {
+    if (!c->rb_pin) {
+      HIPCHK(c, hipHostMalloc((void**)&c->rb_pin, 16 * sizeof(double), hipHostMallocDefault));
+      for (auto& e : c->rb_ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    st->t_s = t0 / c->u.t0;
+    s = fixed_steps_pipelined<T>(c, ops, wsp<T>(c, c->off_ode + 6 * fb), t0 / c->u.t0, t1 / c->u.t0,
+                                 o->fixed_steps, od.rtol, od.atol, *st);
+  } else {
+    s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
+  }
   c->mom_state = nullptr;
   c->obs_state = nullptr;
   c->mom_sums_for = nullptr;
@@ -1673,6 +1778,10 @@ void scfft_destroy(scfft_ctx* ctx) {
   for (auto& x : ctx->graph_exec)
     if (x) (void)hipGraphExecDestroy(x);
   for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->rb_pin || ctx->rb_ev[0]) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->rb_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->rb_pin) (void)hipHostFree(ctx->rb_pin);
   delete ctx;
 }
 
@@ -2035,7 +2144,8 @@ scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only,
 scfft_status scfft_step_moment(scfft_ctx* ctx, int32_t omega_only, double m_Am2[3]) {
   if (!ctx || !m_Am2) return SCFFT_ERR_ARG;
   if (!ctx->ws) return fail(ctx, SCFFT_ERR_WORKSPACE, "no workspace attached");
-  if (!ctx->obs_state || ctx->mom_state != ctx->obs_state)
+  if (!ctx->obs_state ||
+      (ctx->mom_sums_for != ctx->obs_state && ctx->mom_state != ctx->obs_state))
     return fail(ctx, SCFFT_ERR_STATE, "scfft_step_moment is valid inside an integrator observer only");
   const int first = omega_only ? 3 : 0;
   double r[3];
