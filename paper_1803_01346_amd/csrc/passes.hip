@@ -340,16 +340,18 @@ __global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SC
     if (packed) f = T(1);
     zsym_apply(v[0][m], v[1][m], v[2][m], kxo, kyo, tz.kodd[kz], f);
   }
+  // each component is stored as soon as its inverse is done, so its stores
+  // overlap the inverse transforms of the next ones
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_inverse<T, NZ, E>(v[c], j, lds, tz.tw, 1);
-  if (valid) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
+    fft_inverse<T, NZ, E>(v[c], j, lds, tz.tw, 1);
+    if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int z = j + m * TPT;
         if (z >= R.zlo_out && z < R.zhi_out) p[c * cs + (size_t)z * es] = v[c][m];
       }
+    }
   }
 }
 
