@@ -100,3 +100,21 @@ def test_anisotropic_fp32_argument_checks_and_reverse_mode():
     scfft.scfft_set_anisotropy(s64.ctx, None)                # isotropic again: accepted
     scfft.scfft_rhs_vjp(s64.ctx, dh, True, dh, None, hb)
     torch.cuda.synchronize()
+
+
+def test_rhs_anisotropic_adaptive_fp64():
+    """Adaptive exterior iteration under the anisotropic law: the same
+    iteration count and result as the oracle."""
+    cfg = NONCUBIC
+    prob, u = oracle_problem(cfg, delta_it=2e-5)
+    prob.aniso = W
+    s = sim(cfg, delta_it=2e-5)
+    scfft.scfft_set_anisotropy(s.ctx, W)
+    h = state(cfg, seed=24)
+    dh = to_dev(torch, h, torch.float64)
+    for t_s in (0.2, 0.21):
+        stats = scfft.RhsStats()
+        out, _ = s.rhs_eval(t_s, dh, stats=stats)
+        want = orhs.rhs_eval(prob, t_s / u.t0, h)
+        assert stats.iters == prob.last_iters
+        assert rel_max(_np(out), want) < 1e-10
