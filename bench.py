@@ -143,7 +143,7 @@ def rhs_bandwidth(sim, h, hd, rhs_ps, n, calls=10):
     (the library's count for the launches of this schedule, and the counter
     bytes of the committed traffic summary per launch of each kernel kind
     when it matches the sources) times the calls per second of the timed
-    run; beside it the survey-style model of a plain R2C pencil schedule,
+    run; beside it the byte model of a plain R2C pencil schedule,
     (3 + 2k) F + (17 + 16k) S + (2 + 2k) N^3 with F = 3 N^3 w and
     S = 3 N^2 (N/2 + 1) 2w, at the same rate."""
     pk = kernel_profile(sim, lambda: [sim.rhs_eval(T_STAR, h, hd) for _ in range(calls)])
