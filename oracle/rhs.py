@@ -59,12 +59,24 @@ class Problem:
         self.last_converged = True
 
 
+def stopping_measure(new, old, chi):
+    """The quantity the stopping rule of iteration (5) tests (Sec. 2, last
+    paragraph): the mean over the nodes of Omega_out (chi = 0) of the
+    Euclidean length of hdot^{i+1} - hdot^i; 0 when Omega_out is empty."""
+    out = np.asarray(chi) == 0
+    n_out = int(np.sum(out))
+    if n_out == 0:
+        return 0.0
+    diff = np.asarray(new) - np.asarray(old)
+    mag = np.sqrt(diff[0] ** 2 + diff[1] ** 2 + diff[2] ** 2)
+    return float(np.sum(mag[out]) / n_out)
+
+
 def rhs_eval(prob, t, h):
     """hdot = f(t, h) for h of shape (3, Nz, Ny, Nx); updates prob.warm."""
     g = prob.grid
     inside = prob.chi.astype(np.float64)       # chi
     outside = 1.0 - inside                     # 1 - chi
-    n_out = int(np.sum(prob.chi == 0))
     o = prob.opts
 
     j = operators.curl_s(h, g)                                   # Eq. 4
@@ -86,9 +98,7 @@ def rhs_eval(prob, t, h):
         jdot = operators.curl_s(hdot, g)                         # jdot^i = curl hdot^i
         jdot_in = jdot * inside                                  # zero in Omega_out
         new = hdot_in + outside * (hedot + operators.phi(jdot_in, g, o.smooth_phi))  # Eq. 5
-        diff = new - hdot
-        mag = np.sqrt(diff[0] ** 2 + diff[1] ** 2 + diff[2] ** 2)
-        d = float(np.sum(mag * outside) / n_out) if n_out > 0 else 0.0
+        d = stopping_measure(new, hdot, prob.chi)
         deltas.append(d)
         hdot = new
         i += 1

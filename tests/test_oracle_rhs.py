@@ -133,3 +133,48 @@ def test_uniform_state_gives_applied_rate():
     # far from the cube the rate is the applied rate plus a weak dipole field
     dev = np.abs(hd[2, far] - hedot[2]).mean() / hedot[2]
     assert dev < 0.3
+
+
+def test_stopping_measure_hand_built():
+    """The stopping measure of iteration (5) (Sec. 2, last paragraph) on hand-
+    built iterates: the mean over Omega_out nodes of the Euclidean length of
+    hdot^{i+1} - hdot^i.  A 4^3 grid with an 8-node Omega (n_out = 56); two
+    Omega_out nodes move by (3, 4, 0) and (0, 0, -2), one Omega node by 100.
+    Dividing by all nodes (7/64), the largest move (5 or 100), summing
+    components (9/56), squares (29/56) or including Omega (107/56) all fail."""
+    chi = np.zeros((4, 4, 4), dtype=np.uint8)
+    chi[1:3, 1:3, 1:3] = 1
+    old = np.random.default_rng(3).normal(size=(3, 4, 4, 4))
+    new = old.copy()
+    new[:, 0, 0, 0] += (3.0, 4.0, 0.0)
+    new[:, 3, 2, 1] += (0.0, 0.0, -2.0)
+    new[:, 1, 2, 1] += (100.0, 0.0, 0.0)
+    assert abs(rhs.stopping_measure(new, old, chi) - 7.0 / 56.0) < 1e-14
+    assert rhs.stopping_measure(new, old, np.ones_like(chi)) == 0.0     # no Omega_out
+
+
+def test_first_delta_of_a_uniform_state_is_the_applied_rate():
+    """With h uniform, j = C_s h vanishes to round-off, so e, hdot_in and the
+    Ohm-law start vanish, and the first update of Eq. 5 sets hdot_out to the
+    applied rate: d_0 = |dh_e/dt| (Euclidean, oblique drive) exactly as the
+    stopping measure defines it."""
+    p = _problem(fixed_iter=1, direction=(0.0, 0.6, 0.8))
+    h = np.zeros((3,) + p.grid.shape) + np.array([0.0, 0.03, 0.04]).reshape(3, 1, 1, 1)
+    rhs.rhs_eval(p, 0.25, h)
+    rate = float(np.linalg.norm(p.drive.hedot(0.25)))
+    assert abs(p.last_deltas[0] - rate) <= 1e-12 * rate
+
+
+def test_recorded_deltas_are_the_stopping_measure_of_the_iterates():
+    """Each recorded delta is the stopping measure of two consecutive
+    iterates: rerunning with fixed_iter = i + 1 returns hdot^{i+1}."""
+    h = _state(_problem())
+    iterates = []
+    for k in (1, 2, 3):
+        q = _problem(fixed_iter=k)
+        iterates.append(rhs.rhs_eval(q, 0.01, h))
+    q = _problem(fixed_iter=3)
+    rhs.rhs_eval(q, 0.01, h)
+    for i in (1, 2):
+        want = rhs.stopping_measure(iterates[i], iterates[i - 1], q.chi)
+        assert abs(q.last_deltas[i] - want) <= 1e-12 * want
