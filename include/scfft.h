@@ -21,6 +21,11 @@
  *                   precision: double for SCFFT_F64, float for SCFFT_F32.
  *                   Field values are dimensionless (h' = h/(jc l), Eq. 8).
  *                   A scalar mask is uint8 [Nz][Ny][Nx], nonzero = inside.
+ *                   Vector fields must start on a multiple of 2 * element
+ *                   size (16 bytes FP64, 8 bytes FP32): the transform passes
+ *                   move the two nodes x = 2i, 2i+1 in one access.  A
+ *                   misaligned field pointer is refused with SCFFT_ERR_ARG
+ *                   (e.g. a view of a tensor at an odd element offset).
  *   Nodes           cell-centred: x_i = -L + (i + 1/2) 2L/N, i = 0..N-1.
  *   Streams         every call is ordered on the HIP stream given at create;
  *                   calls that return host values synchronise that stream.
@@ -164,7 +169,17 @@ typedef struct {
  *   max(|y_i|, |y_new,i|, atol/rtol), accept iff err <= rtol.
  *   dt0_s (0 = automatic), dt_max_s (0 = no cap), fixed_steps > 0 = that many
  *   equal steps, all accepted.  breakpoints_s: extra times never stepped over.
- *   max_steps bounds accepted + rejected steps (0 = 10^7). */
+ *   max_steps bounds accepted + rejected steps (0 = 10^7).
+ *   resume (0 = off): with adaptive steps, continue the step controller
+ *   that the context keeps from its last adaptive integration (or from a
+ *   state blob, scfft_set_state) when t0_s is the time where that
+ *   integration stopped: the right-hand side value there (first same as
+ *   last) and the next step size are reused instead of recomputed, so a run
+ *   stopped by its observer and resumed from a checkpoint takes the steps
+ *   the uninterrupted run takes.  The caller passes the state it stopped
+ *   with.  Ignored (a fresh start) when t0_s differs or no continuation is
+ *   held; every call that changes the mask, jc map, laws, drive, options,
+ *   warm start or workspace drops the continuation. */
 typedef struct {
   double rtol;
   double atol;
@@ -174,6 +189,8 @@ typedef struct {
   int32_t n_bp;
   const double* breakpoints_s;
   int64_t max_steps;
+  int32_t resume;
+  int32_t reserved;
 } scfft_ode_opts;
 
 typedef struct {
@@ -260,7 +277,10 @@ scfft_status scfft_set_mask(scfft_ctx* ctx, const uint8_t* dev_mask);
  * SCFFT_ERR_GEOMETRY without a mask. */
 scfft_status scfft_mask_betti(const scfft_ctx* ctx, int64_t betti[3]);
 /* Optional local critical density kappa = jc(x)/jc [Nz][Ny][Nx] in the
- * context precision, all > 0; NULL clears it (kappa = 1).  Copied. */
+ * context precision, all finite and > 0; NULL clears it (kappa = 1).
+ * Copied, then checked on the device: SCFFT_ERR_ARG (and no map, kappa = 1)
+ * if any value is not finite or not > 0, since Eq. 1 takes its logarithm.
+ * Synchronous. */
 scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa);
 scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d);
 /* Field-dependent critical density, the e(j, h) relation that Sec. 2 allows
@@ -476,7 +496,15 @@ scfft_status scfft_profile_read(scfft_ctx* ctx, int64_t launches[SCFFT_KERNEL_KI
 
 /* ---- checkpoint ---- */
 
-/* Serialise the warm start and options (pass blob = NULL to query bytes). */
+/* Serialise the context's evolving state (pass blob = NULL to query
+ * bytes): the right-hand-side options, the warm start of iteration (5), the
+ * iteration count the adaptive loop launches first, and the continuation of
+ * the adaptive step controller (time, next step size, whether the last
+ * step was rejected, and the first-same-as-last right-hand side k1 at that
+ * time), so that scfft_set_state on a fresh context of the same grid and
+ * precision followed by scfft_integrate with resume = 1 repeats what the
+ * original context would have done.  Host blob, caller-owned; SCFFT_ERR_STATE
+ * on a blob for another grid or precision, or cut short. */
 scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes);
 scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes);
 

@@ -35,9 +35,27 @@ namespace scfft {
 
 enum Buf : int { B_Y = 0, B_K1, B_K2, B_K3, B_K4, B_Y1, B_NONE = -1 };
 
+// Continuation of the adaptive controller between calls.  In: if `use`, the
+// run starts from it (k1 already in K1 when has_k1, step size dt, whether
+// the last step was rejected) instead of computing k1 and a first step.
+// Out: where the run stopped (its observer, t1 or max_steps) and what the
+// next step would have started with; valid = false after a failure and in
+// fixed-step mode.
+struct Bs23Cont {
+  bool use = false;
+  bool valid = false;
+  double t = 0.0;
+  double dt = 0.0;
+  bool rejected_last = false;
+  bool has_k1 = false;
+};
+
 template <class Ops>
 scfft_status bs23_run(Ops& ops, double t0, double t1, const scfft_ode_opts& o,
-                      const std::vector<double>& extra_stops, scfft_ode_stats& st) {
+                      const std::vector<double>& extra_stops, scfft_ode_stats& st,
+                      Bs23Cont* cont = nullptr) {
+  const bool resume = cont && cont->use;
+  if (cont) cont->valid = false;
   const double rtol = o.rtol, atol = o.atol;
   const double thr = atol / rtol;
   const int64_t max_steps = o.max_steps > 0 ? o.max_steps : 10000000;
@@ -89,11 +107,20 @@ scfft_status bs23_run(Ops& ops, double t0, double t1, const scfft_ode_opts& o,
   std::sort(stops.begin(), stops.end());
   stops.erase(std::unique(stops.begin(), stops.end()), stops.end());
 
+  // a drive kink at t1 itself: the next run recomputes k1 there
+  bool kink_at_t1 = false;
+  for (double b : extra_stops)
+    if (std::fabs(b - t1) <= 1e-12 * std::max(std::fabs(t1), 1.0)) kink_at_t1 = true;
+
   double t = t0;
-  if ((rc = ops.rhs(t, B_Y, B_K1)) < 0) return (scfft_status)rc;
-  st.rhs_calls += 1;
+  if (!(resume && cont->has_k1)) {
+    if ((rc = ops.rhs(t, B_Y, B_K1)) < 0) return (scfft_status)rc;
+    st.rhs_calls += 1;
+  }
   double dt;
-  if (o.dt0_s > 0.0) {
+  if (resume) {
+    dt = cont->dt;
+  } else if (o.dt0_s > 0.0) {
     dt = o.dt0_s;
   } else {
     double r = 0.0;
@@ -102,8 +129,16 @@ scfft_status bs23_run(Ops& ops, double t0, double t1, const scfft_ode_opts& o,
   }
   dt = std::min(std::min(dt, dt_max), t1 - t0);
   size_t si = 0;
-  bool rejected_last = false;
+  bool rejected_last = resume && cont->rejected_last;
   bool nonfinite_last = false;
+  auto save = [&](double tt, double dnext, bool rej, bool k1) {
+    if (!cont) return;
+    cont->valid = true;
+    cont->t = tt;
+    cont->dt = dnext;
+    cont->rejected_last = rej;
+    cont->has_k1 = k1;
+  };
   while (t < t1 && st.accepted + st.rejected < max_steps) {
     const double stop = stops[si];
     bool hit = false;
@@ -122,28 +157,36 @@ scfft_status bs23_run(Ops& ops, double t0, double t1, const scfft_ode_opts& o,
       st.dt_last_s = dt;
       st.accepted += 1;
       nonfinite_last = false;
+      // after a drive kink (a stop before t1) k1 is recomputed: the rate may jump
+      const bool kink = hit && si + 1 < stops.size() && stop < t1;
+      double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.8 * std::cbrt(rtol / err)));
+      if (rejected_last) fac = std::min(fac, 1.0);
+      const double dt_next = std::min(dt * fac, dt_max);
+      save(t, dt_next, false, !kink && !(t >= t1 && kink_at_t1));
       int stop_req = 0;
       if ((rc = ops.observe(t, &stop_req)) < 0) return (scfft_status)rc;
       if (stop_req) return SCFFT_OK;
       if (hit) {
         ++si;
-        if (si < stops.size() && stop < t1) {
+        if (kink) {
           if ((rc = ops.rhs(t, B_Y, B_K1)) < 0) return (scfft_status)rc;
           st.rhs_calls += 1;
+          save(t, dt_next, false, true);
         }
       }
-      double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.8 * std::cbrt(rtol / err)));
-      if (rejected_last) fac = std::min(fac, 1.0);
       rejected_last = false;
-      dt = std::min(dt * fac, dt_max);
+      dt = dt_next;
     } else {
       st.rejected += 1;
       nonfinite_last = !std::isfinite(err);
       const double fac = nonfinite_last ? 0.2 : std::max(0.2, 0.8 * std::cbrt(rtol / err));
       dt = dt * std::min(fac, rejected_last ? 0.5 : fac);
       rejected_last = true;
-      if (dt < 1e-14 * std::max(std::fabs(t), 1.0))
+      if (dt < 1e-14 * std::max(std::fabs(t), 1.0)) {
+        if (cont) cont->valid = false;
         return nonfinite_last ? SCFFT_ERR_NAN : SCFFT_ERR_STEP_UNDERFLOW;
+      }
+      save(t, dt, true, true);
     }
   }
   return SCFFT_OK;

@@ -422,6 +422,27 @@ hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t n
   return hipGetLastError();
 }
 
+// partials[b] = number of values in block b's share that are not finite and > 0
+template <typename T>
+__global__ __launch_bounds__(kRB) void count_nonpositive_kernel(const T* __restrict__ v, size_t n,
+                                                                double* __restrict__ partials) {
+  __shared__ double sh[kRB];
+  double bad = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
+    const T x = v[i];
+    if (!(x > T(0) && x <= HUGE_VAL)) bad += 1.0;  // NaN fails both tests
+  }
+  const double b = block_sum(bad, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+template <typename T>
+hipError_t launch_count_nonpositive(const T* v, size_t n, double* partials, int nblocks,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL((count_nonpositive_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, v, n, partials);
+  return hipGetLastError();
+}
+
 #define SCFFT_INST(T)                                                                          \
   template hipError_t launch_fill_uniform<T>(T*, size_t, const double[3], hipStream_t);        \
   template hipError_t launch_combo<T>(T*, const T*, const T*, double, const T*, double,        \
@@ -438,7 +459,8 @@ hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t n
                                       hipStream_t);                                             \
   template hipError_t launch_masked_copy<T>(T*, const T*, const uint8_t*, size_t, hipStream_t); \
   template hipError_t launch_ratio_max<T>(const T*, const T*, double, size_t, double*, int,     \
-                                          hipStream_t);
+                                          hipStream_t);                                         \
+  template hipError_t launch_count_nonpositive<T>(const T*, size_t, double*, int, hipStream_t);
 SCFFT_INST(double)
 SCFFT_INST(float)
 #undef SCFFT_INST

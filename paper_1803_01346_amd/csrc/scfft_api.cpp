@@ -64,6 +64,9 @@ struct scfft_ctx {
   std::string err;
   int64_t clamp_seen = 0;
   int iter_guess = 0;  // exterior iterations of the last converged adaptive call
+  // where the last adaptive integration stopped, for scfft_ode_opts.resume:
+  // its k1 then sits in the K1 slot of the ODE buffers
+  Bs23Cont cont;
   // integrator: state whose moment partials the last power-law pass recorded,
   // and whether an observer callback is running (scfft_step_moment)
   const void* mom_state = nullptr;
@@ -130,6 +133,22 @@ scfft_status fail(scfft_ctx* c, scfft_status s, const char* fmt, ...) {
   }
   return s;
 }
+
+// Vector fields are read and written two nodes per access (x = 2i, 2i+1).
+bool field_aligned(const scfft_ctx* c, const void* p) {
+  return p == nullptr || ((uintptr_t)p) % (2 * c->wsize) == 0;
+}
+
+#define CHECK_FIELD(ctx, p)                                                                \
+  do {                                                                                     \
+    if (!field_aligned(ctx, p))                                                            \
+      return fail(ctx, SCFFT_ERR_ARG, "%s is not %zu-byte aligned", #p, 2 * (ctx)->wsize); \
+  } while (0)
+
+// The controller continuation belongs to the state the last integration
+// ended with; anything that changes the right-hand side or the warm start
+// drops it.
+void drop_cont(scfft_ctx* c) { c->cont = Bs23Cont{}; }
 
 #define HIPCHK(ctx, call)                                                                  \
   do {                                                                                     \
@@ -1001,7 +1020,7 @@ struct HostOps {
 bool valid_ode_opts(const scfft_ode_opts* o) {
   return o && o->rtol > 0.0 && o->atol > 0.0 && o->dt0_s >= 0.0 && o->dt_max_s >= 0.0 &&
          o->fixed_steps >= 0 && o->n_bp >= 0 && (o->n_bp == 0 || o->breakpoints_s) &&
-         o->max_steps >= 0;
+         o->max_steps >= 0 && (o->resume == 0 || o->resume == 1);
 }
 
 // Fixed-step BS23 (the steps of bs23_run's fixed mode) with the next step
@@ -1082,6 +1101,13 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
   std::vector<double> stops = c->drive.kinks();
   for (int i = 0; i < o->n_bp; ++i) stops.push_back(o->breakpoints_s[i] / c->u.t0);
   scfft_status s;
+  // resume the adaptive controller where the last adaptive integration (or
+  // a restored state blob) stopped; its k1 sits in the K1 slot
+  Bs23Cont cont = c->cont;
+  const double t0d = t0 / c->u.t0;
+  cont.use = o->resume && o->fixed_steps <= 0 && cont.valid &&
+             std::fabs(cont.t - t0d) <= 1e-12 * std::max(std::fabs(t0d), 1.0);
+  drop_cont(c);
   if (o->fixed_steps > 0 && t1 > t0) {
     if (!c->rb_pin) {
       HIPCHK(c, hipHostMalloc((void**)&c->rb_pin, 16 * sizeof(double), hipHostMallocDefault));
@@ -1091,7 +1117,17 @@ scfft_status integrate_impl(scfft_ctx* c, double t0, double t1, T* h, const scff
     s = fixed_steps_pipelined<T>(c, ops, wsp<T>(c, c->off_ode + 6 * fb), t0 / c->u.t0, t1 / c->u.t0,
                                  o->fixed_steps, od.rtol, od.atol, *st);
   } else {
-    s = bs23_run(ops, t0 / c->u.t0, t1 / c->u.t0, od, stops, *st);
+    // a resumed run starts at the stored time itself, not at t0_s / t0
+    // (which may differ from it in the last bit)
+    s = bs23_run(ops, cont.use ? cont.t : t0d, t1 / c->u.t0, od, stops, *st, &cont);
+    if (s >= 0 && cont.valid) {
+      // keep k1 in the K1 slot, where the next resumed run expects it
+      T* slot = wsp<T>(c, c->off_ode + (size_t)B_K1 * fb);
+      if (cont.has_k1 && ops.buf[B_K1] != slot)
+        HIPCHK(c, hipMemcpyAsync(slot, ops.buf[B_K1], fb, hipMemcpyDeviceToDevice, c->stream));
+      cont.use = false;
+      c->cont = cont;
+    }
   }
   c->mom_state = nullptr;
   c->obs_state = nullptr;
@@ -1629,6 +1665,7 @@ scfft_status set_mask_host(scfft_ctx* c, const std::vector<uint8_t>& m) {
   c->n_out = (int64_t)c->nodes - in;
   c->has_mask = true;
   c->has_warm = false;
+  drop_cont(c);
   ++c->epoch;
   mask_betti(c->n, m.data(), c->betti);
   return c->betti[1] > 0 ? SCFFT_WARN_TOPOLOGY : SCFFT_OK;
@@ -1649,6 +1686,11 @@ struct StateHeader {
   int32_t version, prec, n[3], has_warm;
   scfft_rhs_opts opts;
   uint64_t warm_bytes;
+  // version 2: the adaptive iteration's first launch count and the
+  // continuation of the adaptive step controller (k1 follows the warm start)
+  int32_t iter_guess, cont_valid, cont_rejected, cont_has_k1;
+  double cont_t, cont_dt;
+  uint64_t k1_bytes;
 };
 const uint64_t kStateMagic = 0x5343464654535431ull;  // "SCFFTST1"
 
@@ -1803,6 +1845,7 @@ scfft_status scfft_set_workspace(scfft_ctx* ctx, void* dev_ptr, size_t bytes) {
   ctx->ws = (char*)dev_ptr;
   ctx->ws_bytes = bytes;
   ctx->has_mask = ctx->has_kappa = ctx->has_warm = false;
+  drop_cont(ctx);
   // the sigma of the context may have been rescaled by options; rebuild tables
   return ctx->prec == SCFFT_F64 ? upload_tables<double>(ctx) : upload_tables<float>(ctx);
 }
@@ -1841,8 +1884,24 @@ scfft_status scfft_set_jc_map(scfft_ctx* ctx, const void* dev_kappa) {
     ctx->has_kappa = false;
     return SCFFT_OK;
   }
+  drop_cont(ctx);
+  ctx->has_kappa = false;
   HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->off_kappa, dev_kappa, ctx->nodes * ctx->wsize,
                              hipMemcpyDeviceToDevice, ctx->stream));
+  // Eq. 1 uses ln kappa: every value must be finite and > 0
+  double* part = wsp<double>(ctx, ctx->off_part);
+  double* out = wsp<double>(ctx, ctx->off_scal);
+  HIPCHK(ctx, ctx->prec == SCFFT_F64
+                  ? launch_count_nonpositive<double>(wsp<double>(ctx, ctx->off_kappa), ctx->nodes, part,
+                                                     kReduceBlocks, ctx->stream)
+                  : launch_count_nonpositive<float>(wsp<float>(ctx, ctx->off_kappa), ctx->nodes, part,
+                                                    kReduceBlocks, ctx->stream));
+  HIPCHK(ctx, launch_sum_partials(part, kReduceBlocks, 1, 1, out, ctx->stream));
+  double bad = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&bad, out, sizeof bad, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (bad > 0.0)
+    return fail(ctx, SCFFT_ERR_ARG, "jc map: %.0f values are not finite and > 0", bad);
   ctx->has_kappa = true;
   return SCFFT_OK;
 }
@@ -1851,6 +1910,7 @@ scfft_status scfft_set_drive(scfft_ctx* ctx, const scfft_drive* d) {
   if (!ctx || !d) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ++ctx->epoch;
+  drop_cont(ctx);
   const char* why = nullptr;
   Drive dr;
   if (!dr.set(*d, ctx->u, &why)) return fail(ctx, SCFFT_ERR_ARG, "%s", why);
@@ -1863,6 +1923,7 @@ scfft_status scfft_set_field_law(scfft_ctx* ctx, double b0_T, double alpha) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ++ctx->epoch;
+  drop_cont(ctx);
   if (!(b0_T >= 0.0) || !(alpha >= 0.0) || !std::isfinite(b0_T) || !std::isfinite(alpha))
     return fail(ctx, SCFFT_ERR_ARG, "field law needs b0_T >= 0 and alpha >= 0");
   // |B| / B0 = mu0 h_scale |h'| / B0 with h' the dimensionless field (Eq. 8)
@@ -1875,6 +1936,7 @@ scfft_status scfft_set_anisotropy(scfft_ctx* ctx, const double a[3]) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ++ctx->epoch;
+  drop_cont(ctx);
   if (a) {
     for (int d = 0; d < 3; ++d)
       if (!(a[d] > 0.0) || !std::isfinite(a[d]))
@@ -1890,6 +1952,7 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   if (!ctx || !o) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ++ctx->epoch;
+  drop_cont(ctx);
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
       !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2 ||
       o->x_alt < 0 || o->x_alt > 1)
@@ -1917,6 +1980,8 @@ scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, in
   if (!ready(ctx, true, &st)) return st;
   if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
   if (!h_dev || calls < 1) return fail(ctx, SCFFT_ERR_ARG, "invalid autotune arguments");
+  CHECK_FIELD(ctx, h_dev);
+  drop_cont(ctx);
   if (ctx->opts.fixed_iter <= 0)
     return fail(ctx, SCFFT_ERR_ARG, "autotune times a fixed iteration count (fixed_iter > 0)");
   int pick = 0;
@@ -1937,12 +2002,15 @@ scfft_status scfft_reset_warm(scfft_ctx* ctx) {
   if (!ctx) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   ctx->has_warm = false;
+  drop_cont(ctx);
   return SCFFT_OK;
 }
 
 scfft_status scfft_init_state(scfft_ctx* ctx, double t0_s, void* h_dev) {
   if (!ctx || !h_dev) return SCFFT_ERR_ARG;
+  CHECK_FIELD(ctx, h_dev);
   if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  drop_cont(ctx);
   double he[3], hd[3];
   ctx->drive.eval(t0_s / ctx->u.t0, he, hd);
   hipError_t e = ctx->prec == SCFFT_F64
@@ -1960,7 +2028,10 @@ scfft_status scfft_rhs_eval(scfft_ctx* ctx, double t_s, const void* h_dev, void*
   if (!ready(ctx, true, &st)) return st;
   if (!h_dev || !hdot_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
   if (h_dev == hdot_dev) return fail(ctx, SCFFT_ERR_ARG, "h and hdot must not alias");
+  CHECK_FIELD(ctx, h_dev);
+  CHECK_FIELD(ctx, hdot_dev);
   if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
+  drop_cont(ctx);  // the warm start changes
   const double t = t_s / ctx->u.t0;
   return ctx->prec == SCFFT_F64
              ? rhs_impl<double>(ctx, t, (const double*)h_dev, (double*)hdot_dev, stats)
@@ -1975,6 +2046,7 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
   if (!ready(ctx, true, &st)) return st;
   if (!h_dev || !valid_ode_opts(o) || !(t1_s > t0_s))
     return fail(ctx, SCFFT_ERR_ARG, "invalid integrate arguments");
+  CHECK_FIELD(ctx, h_dev);
   if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
   scfft_ode_stats local;
   scfft_ode_stats* s = stats ? stats : &local;
@@ -1994,8 +2066,14 @@ scfft_status scfft_rhs_vjp(scfft_ctx* ctx, const void* h_dev, int32_t warm_used,
   if (hbar_dev == h_dev || hbar_dev == lam_dev || hbar_dev == mu_dev ||
       (wbar_dev && (wbar_dev == h_dev || wbar_dev == hbar_dev)))
     return fail(ctx, SCFFT_ERR_ARG, "outputs must not alias inputs");
+  CHECK_FIELD(ctx, h_dev);
+  CHECK_FIELD(ctx, lam_dev);
+  CHECK_FIELD(ctx, mu_dev);
+  CHECK_FIELD(ctx, hbar_dev);
+  CHECK_FIELD(ctx, wbar_dev);
   if (ctx->opts.fixed_iter <= 0)
     return fail(ctx, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  drop_cont(ctx);
   double* sc = wsp<double>(ctx, ctx->off_adjs);
   HIPCHK(ctx, launch_zero_doubles(sc, 4, ctx->stream));
   st = ctx->prec == SCFFT_F64
@@ -2036,8 +2114,13 @@ scfft_status scfft_integrate_adjoint(scfft_ctx* ctx, double t0_s, double t1_s, i
   if (!h0_dev || !hT_bar_dev || !h0_bar_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
   if (h0_bar_dev == h0_dev || h0_bar_dev == hT_bar_dev || (hT_dev && (hT_dev == h0_dev || hT_dev == h0_bar_dev)))
     return fail(ctx, SCFFT_ERR_ARG, "outputs must not alias inputs");
+  CHECK_FIELD(ctx, h0_dev);
+  CHECK_FIELD(ctx, hT_bar_dev);
+  CHECK_FIELD(ctx, hT_dev);
+  CHECK_FIELD(ctx, h0_bar_dev);
   if (ctx->opts.fixed_iter <= 0)
     return fail(ctx, SCFFT_ERR_ARG, "reverse mode needs a fixed iteration count (fixed_iter > 0)");
+  drop_cont(ctx);
   if (p_bar && ctx->drive.kind == SCFFT_DRIVE_PWL)
     return fail(ctx, SCFFT_ERR_ARG, "p_bar needs a drive of the form p f(t) (ramp-hold or sine)");
   const int every = std::min<int>(checkpoint_every, steps);
@@ -2068,8 +2151,10 @@ scfft_status scfft_integrate_graph(scfft_ctx* ctx, double t0_s, double t1_s, int
   if (!ready(ctx, true, &st)) return st;
   if (!ctx->has_drive) return fail(ctx, SCFFT_ERR_ARG, "no drive set");
   if (!h_dev || steps <= 0 || !(t1_s > t0_s)) return fail(ctx, SCFFT_ERR_ARG, "invalid integrate arguments");
+  CHECK_FIELD(ctx, h_dev);
   if (ctx->opts.fixed_iter <= 0)
     return fail(ctx, SCFFT_ERR_ARG, "graph replay needs a fixed iteration count (fixed_iter > 0)");
+  drop_cont(ctx);
   const size_t need = graph_layout(steps).total;
   if (!graph_ws || graph_bytes < need || (reinterpret_cast<uintptr_t>(graph_ws) & 255))
     return fail(ctx, SCFFT_ERR_WORKSPACE, "graph workspace: %zu bytes at a 256-byte boundary needed", need);
@@ -2112,6 +2197,8 @@ scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!v_dev || !out_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  CHECK_FIELD(ctx, v_dev);
+  CHECK_FIELD(ctx, out_dev);
   return ctx->prec == SCFFT_F64
              ? apply_operator<double>(ctx, (const double*)v_dev, (double*)out_dev, Z_CURL, 1.0)
              : apply_operator<float>(ctx, (const float*)v_dev, (float*)out_dev, Z_CURL, 1.0);
@@ -2122,6 +2209,8 @@ scfft_status scfft_phi(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!v_dev || !out_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  CHECK_FIELD(ctx, v_dev);
+  CHECK_FIELD(ctx, out_dev);
   const int sym = ctx->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
   return ctx->prec == SCFFT_F64
              ? apply_operator<double>(ctx, (const double*)v_dev, (double*)out_dev, sym, 1.0)
@@ -2137,6 +2226,7 @@ scfft_status scfft_moment(scfft_ctx* ctx, const void* h_dev, int32_t omega_only,
   scfft_status st;
   if (!ready(ctx, omega_only != 0, &st)) return st;
   if (!h_dev || !m_Am2) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  CHECK_FIELD(ctx, h_dev);
   return ctx->prec == SCFFT_F64 ? moment_impl<double>(ctx, (const double*)h_dev, omega_only, m_Am2)
                                 : moment_impl<float>(ctx, (const float*)h_dev, omega_only, m_Am2);
 }
@@ -2172,6 +2262,7 @@ scfft_status scfft_region_mean_abs_b(scfft_ctx* ctx, const void* h_dev, const ui
   scfft_status st;
   if (!ready(ctx, false, &st)) return st;
   if (!h_dev || !dev_region || !b_T) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  CHECK_FIELD(ctx, h_dev);
   return ctx->prec == SCFFT_F64 ? region_impl<double>(ctx, (const double*)h_dev, dev_region, b_T)
                                 : region_impl<float>(ctx, (const float*)h_dev, dev_region, b_T);
 }
@@ -2181,6 +2272,7 @@ scfft_status scfft_stray_fraction(scfft_ctx* ctx, const void* h_dev, double* fra
   scfft_status st;
   if (!ready(ctx, true, &st)) return st;
   if (!h_dev || !frac) return fail(ctx, SCFFT_ERR_ARG, "NULL pointer");
+  CHECK_FIELD(ctx, h_dev);
   return ctx->prec == SCFFT_F64 ? stray_impl<double>(ctx, (const double*)h_dev, frac)
                                 : stray_impl<float>(ctx, (const float*)h_dev, frac);
 }
@@ -2192,6 +2284,7 @@ scfft_status scfft_probe_b(scfft_ctx* ctx, const void* h_dev, const double* xyz_
   if (!ready(ctx, false, &st)) return st;
   if (!h_dev || npts < 0 || (npts > 0 && (!xyz_m || !b_T)))
     return fail(ctx, SCFFT_ERR_ARG, "invalid probe arguments");
+  CHECK_FIELD(ctx, h_dev);
   for (int i = 0; i < 3 * npts; ++i)
     if (!std::isfinite(xyz_m[i])) return fail(ctx, SCFFT_ERR_ARG, "non-finite probe point");
   if (npts == 0) return SCFFT_OK;
@@ -2203,7 +2296,9 @@ scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes) {
   if (!ctx || !bytes) return SCFFT_ERR_ARG;
   if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
   const size_t wb = ctx->has_warm ? 3 * ctx->nodes * ctx->wsize : 0;
-  const size_t need = sizeof(StateHeader) + wb;
+  const bool k1 = ctx->cont.valid && ctx->cont.has_k1;
+  const size_t kb = k1 ? 3 * ctx->nodes * ctx->wsize : 0;
+  const size_t need = sizeof(StateHeader) + wb + kb;
   if (!blob) {
     *bytes = need;
     return SCFFT_OK;
@@ -2212,18 +2307,27 @@ scfft_status scfft_get_state(scfft_ctx* ctx, void* blob, size_t* bytes) {
   StateHeader hd;
   std::memset(&hd, 0, sizeof hd);
   hd.magic = kStateMagic;
-  hd.version = 1;
+  hd.version = 2;
   hd.prec = ctx->prec;
   for (int a = 0; a < 3; ++a) hd.n[a] = ctx->n[a];
   hd.has_warm = ctx->has_warm ? 1 : 0;
   hd.opts = ctx->opts;
   hd.warm_bytes = wb;
+  hd.iter_guess = ctx->iter_guess;
+  hd.cont_valid = ctx->cont.valid ? 1 : 0;
+  hd.cont_rejected = ctx->cont.rejected_last ? 1 : 0;
+  hd.cont_has_k1 = k1 ? 1 : 0;
+  hd.cont_t = ctx->cont.t;
+  hd.cont_dt = ctx->cont.dt;
+  hd.k1_bytes = kb;
   std::memcpy(blob, &hd, sizeof hd);
-  if (wb) {
+  if (wb)
     HIPCHK(ctx, hipMemcpyAsync((char*)blob + sizeof hd, ctx->ws + ctx->off_warm, wb,
                                hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  }
+  if (kb)  // k1 sits in the K1 slot of the ODE buffers (one field each)
+    HIPCHK(ctx, hipMemcpyAsync((char*)blob + sizeof hd + wb, ctx->ws + ctx->off_ode + (size_t)B_K1 * kb,
+                               kb, hipMemcpyDeviceToHost, ctx->stream));
+  if (wb || kb) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   *bytes = need;
   return SCFFT_OK;
 }
@@ -2236,21 +2340,35 @@ scfft_status scfft_set_state(scfft_ctx* ctx, const void* blob, size_t bytes) {
   StateHeader hd;
   if (bytes < sizeof hd) return fail(ctx, SCFFT_ERR_STATE, "state blob too short");
   std::memcpy(&hd, blob, sizeof hd);
-  if (hd.magic != kStateMagic || hd.version != 1)
+  if (hd.magic != kStateMagic || hd.version != 2)
     return fail(ctx, SCFFT_ERR_STATE, "not an scfft state blob");
   if (hd.prec != ctx->prec || hd.n[0] != ctx->n[0] || hd.n[1] != ctx->n[1] || hd.n[2] != ctx->n[2])
     return fail(ctx, SCFFT_ERR_STATE, "state blob is for another grid or precision");
-  const size_t wb = hd.has_warm ? 3 * ctx->nodes * ctx->wsize : 0;
-  if (hd.warm_bytes != wb || bytes < sizeof hd + wb)
+  const size_t fb = 3 * ctx->nodes * ctx->wsize;
+  const size_t wb = hd.has_warm ? fb : 0;
+  const size_t kb = hd.cont_has_k1 ? fb : 0;
+  if (hd.warm_bytes != wb || hd.k1_bytes != kb || bytes < sizeof hd + wb + kb ||
+      (hd.cont_has_k1 && !hd.cont_valid) || hd.iter_guess < 0 ||
+      (hd.cont_valid && !(std::isfinite(hd.cont_t) && hd.cont_dt > 0.0 && std::isfinite(hd.cont_dt))))
     return fail(ctx, SCFFT_ERR_STATE, "state blob size mismatch");
-  scfft_status s = scfft_set_rhs_opts(ctx, &hd.opts);
+  scfft_status s = scfft_set_rhs_opts(ctx, &hd.opts);  // drops the continuation
   if (s != SCFFT_OK) return s;
-  if (wb) {
+  if (wb)
     HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->off_warm, (const char*)blob + sizeof hd, wb,
                                hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  }
+  if (kb)
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->off_ode + (size_t)B_K1 * fb, (const char*)blob + sizeof hd + wb,
+                               kb, hipMemcpyHostToDevice, ctx->stream));
+  if (wb || kb) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->has_warm = hd.has_warm != 0;
+  ctx->iter_guess = hd.iter_guess;
+  if (hd.cont_valid) {
+    ctx->cont.valid = true;
+    ctx->cont.t = hd.cont_t;
+    ctx->cont.dt = hd.cont_dt;
+    ctx->cont.rejected_last = hd.cont_rejected != 0;
+    ctx->cont.has_k1 = hd.cont_has_k1 != 0;
+  }
   return SCFFT_OK;
 }
 

@@ -69,7 +69,8 @@ class RhsStats(C.Structure):
 class OdeOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("dt0_s", C.c_double),
                 ("dt_max_s", C.c_double), ("fixed_steps", C.c_int32), ("n_bp", C.c_int32),
-                ("breakpoints_s", C.POINTER(C.c_double)), ("max_steps", C.c_int64)]
+                ("breakpoints_s", C.POINTER(C.c_double)), ("max_steps", C.c_int64),
+                ("resume", C.c_int32), ("reserved", C.c_int32)]
 
 
 class OdeStats(C.Structure):

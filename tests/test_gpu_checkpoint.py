@@ -61,3 +61,54 @@ def test_state_blob_is_checked():
             scfft.scfft_set_state(ctx, b)
         assert e.value.status == scfft.ERR_STATE
     assert scfft.scfft_set_state(a.ctx, blob) == scfft.OK
+
+
+def test_adaptive_resume_repeats_the_uninterrupted_steps():
+    """A run stopped by its observer, checkpointed (warm start, first launch
+    count of the adaptive iteration, controller continuation with its FSAL
+    k1) and resumed in a fresh context with resume = 1 takes the steps the
+    uninterrupted run takes and ends in the same state, bit for bit; a
+    restart without the continuation recomputes k1 and a first step size and
+    does not."""
+    h0 = to_dev(torch, state(CUP, seed=3), torch.float64)
+    t_end = 0.002
+
+    a = sim(CUP, delta_it=2e-5)
+    ha = h0.clone()
+    ta = []
+    sa = scfft.OdeStats()
+    scfft.scfft_integrate(a.ctx, 0.0, t_end, ha, scfft.default_ode_opts(),
+                          observer=lambda _u, t, _p: ta.append(t) or 0, stats=sa)
+    assert sa.accepted >= 8 and sa.rejected + sa.accepted > 0
+    k = sa.accepted // 2
+
+    b = sim(CUP, delta_it=2e-5)
+    hb = h0.clone()
+    tb = []
+
+    def stop_at_k(_u, t, _p):
+        tb.append(t)
+        return 1 if len(tb) == k else 0
+
+    scfft.scfft_integrate(b.ctx, 0.0, t_end, hb, scfft.default_ode_opts(), observer=stop_at_k)
+    assert len(tb) == k
+    blob = scfft.scfft_get_state(b.ctx)
+    h_mid = hb.clone()
+
+    c = scfft.Simulation(CUP, precision=scfft.F64)
+    scfft.scfft_set_state(c.ctx, blob)
+    sc = scfft.OdeStats()
+    scfft.scfft_integrate(c.ctx, tb[-1], t_end, hb, scfft.default_ode_opts(resume=1),
+                          observer=lambda _u, t, _p: tb.append(t) or 0, stats=sc)
+    torch.cuda.synchronize()
+    assert tb == ta
+    assert torch.equal(hb, ha)
+
+    d = scfft.Simulation(CUP, precision=scfft.F64)
+    scfft.scfft_set_state(d.ctx, blob)
+    hd = h_mid.clone()
+    td = tb[:k]
+    scfft.scfft_integrate(d.ctx, tb[k - 1], t_end, hd, scfft.default_ode_opts(),
+                          observer=lambda _u, t, _p: td.append(t) or 0)
+    torch.cuda.synchronize()
+    assert td != ta                                       # a fresh start of the controller
