@@ -113,13 +113,30 @@ def kernel_profile(sim, fn):
     return per_kind
 
 
-def roofline_of(per_kind, traffic=None):
-    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
-    d = per_kind[dom]
-    return {"bound": "hbm", "kernel": dom, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic(dom) if traffic else None,
-            "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
-            "launches": d["launches"]}
+def roofline_of(per_kind, traffic=None, rhs=None):
+    """The kernel with the largest total time against the HBM peak, the
+    runner-up beside it (two kinds can be within a percent of each other, so
+    either may lead from run to run), and the whole right-hand side."""
+    order = sorted(per_kind, key=lambda k: -per_kind[k]["total_ms"])
+    total = sum(v["total_ms"] for v in per_kind.values())
+
+    def one(k):
+        d = per_kind[k]
+        return {"kernel": k, "achieved": d["GBs"], "frac": round(d["GBs"] / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+                "launches": d["launches"], "time_share": round(d["total_ms"] / total, 4),
+                "traffic": traffic(k) if traffic else None}
+
+    top = one(order[0])
+    out = {"bound": "hbm", "kernel": top["kernel"], "achieved": top["achieved"], "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": top["frac"], "traffic": top["traffic"],
+           "bytes_per_launch": top["bytes_per_launch"], "avg_launch_us": top["avg_launch_us"],
+           "launches": top["launches"], "time_share": top["time_share"]}
+    if len(order) > 1:
+        out["runner_up"] = one(order[1])
+    if rhs is not None:
+        out["whole_rhs"] = rhs
+    return out
 
 
 def rhs_event_median(sim, h, hd, calls=100, warm=10):
@@ -148,14 +165,14 @@ def rhs_bandwidth(sim, h, hd, rhs_ps, n, calls=10):
     S = 3 N^2 (N/2 + 1) 2w, at the same rate."""
     pk = kernel_profile(sim, lambda: [sim.rhs_eval(T_STAR, h, hd) for _ in range(calls)])
     b = sum(v["bytes_per_launch"] * v["launches"] for v in pk.values()) / calls
-    tr = {k: measured_traffic(k) for k in pk}
-    cb = (sum(tr[k] * pk[k]["launches"] for k in pk) / calls) if all(v is not None for v in tr.values()) else None
-    w, k = 8.0, FIXED_ITER
+    tr = {k: measured_traffic(k) for k in pk} if sim.dtype == __import__("torch").float64 else {}
+    cb = (sum(tr[k] * pk[k]["launches"] for k in pk) / calls) if tr and all(v is not None for v in tr.values()) else None
+    w, k = float(sim.dtype.itemsize), FIXED_ITER
     nodes = float(n[0] * n[1] * n[2])
     F = 3.0 * nodes * w
     S = 3.0 * n[2] * n[1] * (n[0] // 2 + 1) * 2.0 * w
     model = (3 + 2 * k) * F + (17 + 16 * k) * S + (2 + 2 * k) * nodes
-    out = dict(bytes_per_rhs=int(b), achieved_GBs=round(b * rhs_ps / 1e9, 1),
+    out = dict(bytes_per_rhs=int(b), rhs_per_s=round(rhs_ps, 2), achieved_GBs=round(b * rhs_ps / 1e9, 1),
                frac=round(b * rhs_ps / (HBM_PEAK_GBS * 1e9), 4),
                counter_bytes_per_rhs=int(cb) if cb is not None else None,
                counter_frac=round(cb * rhs_ps / (HBM_PEAK_GBS * 1e9), 4) if cb is not None else None,
@@ -187,7 +204,7 @@ def converged_leg(cfg, h, calls=20):
                 delta_it=2e-5, calls=calls)
 
 
-def lens256_leg(calls=10):
+def lens256_leg(calls=30):
     """The 256^3 lens box in FP32 (working set beyond the 256 MB last-level
     cache: the HBM regime): RHS/s with 3 exterior iterations and the
     dominant kernel against the HBM peak."""
@@ -197,11 +214,11 @@ def lens256_leg(calls=10):
     sim = make_sim(cfg, scfft.F32, FIXED_ITER)
     h = torch.from_numpy(workloads.synthetic_state(cfg, seed=0, background=(0.0, 0.0, 0.1))).to(
         device="cuda", dtype=torch.float32).contiguous()
-    rate, _ = time_rhs_only(sim, h, calls, warm=3)
-    hd = sim.empty_field()
-    per_kind = kernel_profile(sim, lambda: [sim.rhs_eval(10.0, h, hd) for _ in range(3)])
+    rate, hd = time_rhs_only(sim, h, calls, warm=3)
+    per_kind = kernel_profile(sim, lambda: [sim.rhs_eval(T_STAR, h, hd) for _ in range(3)])
+    whole = rhs_bandwidth(sim, h, hd, rate, cfg["n"], calls=3)
     out = dict(value=round(rate, 2), unit="RHS evals/s", dtype="f32", grid=[256, 256, 256],
-               exterior_iters=FIXED_ITER, roofline=roofline_of(per_kind), kernels=per_kind)
+               exterior_iters=FIXED_ITER, roofline=roofline_of(per_kind, None, whole), kernels=per_kind)
     sim.close()
     return out
 
@@ -462,128 +479,277 @@ def shield_leg(n_grid=128):
     return out
 
 
-def cpu_baseline(cfg, h_np):
-    """The oracle's rhs_eval on the same 128^3 state with one exterior
-    iteration (4 of the 8 spectral operator applications of a k = 3 call),
-    timed once and scaled by the operator count to a k = 3 call; beside it
-    full k = 3 calls on the same body at 32^3 and 64^3 (median of 3)."""
+# A multi-core CPU right-hand side with scipy.fft, timed as context beside the
+# oracle (never used by the GPU path).  It computes what the method computes
+# (Sec. 2): j = C_s h (Eq. 4, smoothed spectral curl), e from the power law
+# (Eq. 1) in Omega and rho_out j outside, hdot_in = -C_s e on Omega (Eq. 3),
+# then a fixed number of exterior iterations (Eq. 5) with Phi of Eq. 7
+# (1/|k|^2 := 0 at k = 0), from the Ohm-law start or the previous call's
+# exterior rate.  Real-to-complex transforms run on `workers` threads; k_odd
+# has 0 on the Nyquist index of each axis, |k|^2 and the smoothing use the
+# true k.  Uniform jc (kappa = 1), isotropic law.
+import numpy as np  # noqa: E402
+
+
+class ScipyRhs:
+    def __init__(self, n, half_width, chi, n_power, rho_out, fixed_iter, workers=None):
+        import os
+
+        import scipy.fft as sf
+        self.sf = sf
+        self.workers = workers or os.cpu_count() or 1
+        nx, ny, nz = (int(v) for v in n)
+        L = [float(v) for v in half_width]
+        h = [2.0 * L[a] / n[a] for a in range(3)]
+        sigma = 0.5 * np.sqrt(h[0] ** 2 + h[1] ** 2 + h[2] ** 2)
+
+        def axis(a, half):
+            N = (nx, ny, nz)[a]
+            m = np.arange(N // 2 + 1) if half else np.where(np.arange(N) < N // 2, np.arange(N), np.arange(N) - N)
+            k = np.pi * m / L[a]
+            ko = k.copy()
+            ko[np.abs(m) == N // 2] = 0.0
+            return k, ko
+
+        kx, kxo = axis(0, True)
+        ky, kyo = axis(1, False)
+        kz, kzo = axis(2, False)
+        sh = (nz, ny, nx // 2 + 1)
+        self.kx, self.ky, self.kz = (np.broadcast_to(kxo[None, None, :], sh),
+                                     np.broadcast_to(kyo[None, :, None], sh),
+                                     np.broadcast_to(kzo[:, None, None], sh))
+        k2 = kx[None, None, :] ** 2 + ky[None, :, None] ** 2 + kz[:, None, None] ** 2
+        self.smooth = np.exp(-0.5 * sigma ** 2 * k2)
+        inv = np.zeros_like(k2)
+        inv[k2 > 0] = 1.0 / k2[k2 > 0]
+        self.inv_k2 = inv
+        self.chi = np.asarray(chi) != 0
+        self.out = ~self.chi
+        self.n_power = float(n_power)
+        self.rho_out = float(rho_out)
+        self.fixed_iter = int(fixed_iter)
+        self.shape = (nz, ny, nx)
+        self.warm = None
+
+    def _apply(self, v, mult):
+        """Re F^-1 { mult * i k_odd x F(v) } with real-to-complex transforms."""
+        sf = self.sf
+        V = sf.rfftn(v, axes=(1, 2, 3), workers=self.workers)
+        kx, ky, kz = self.kx, self.ky, self.kz
+        c = np.stack([ky * V[2] - kz * V[1], kz * V[0] - kx * V[2], kx * V[1] - ky * V[0]])
+        c *= 1j * mult
+        return sf.irfftn(c, s=self.shape, axes=(1, 2, 3), workers=self.workers)
+
+    def curl(self, v):
+        return self._apply(v, self.smooth)
+
+    def phi(self, v):
+        return self._apply(v, self.inv_k2)
+
+    def __call__(self, hedot, h):
+        j = self.curl(h)
+        s = np.sum(j * j, axis=0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = np.where(s > 0.0, s ** (0.5 * (self.n_power - 1.0)), 0.0)
+        e = np.where(self.chi, f * j, self.rho_out * j)
+        g = -self.curl(e)
+        hdot_in = g * self.chi
+        hdot = hdot_in + (self.warm if self.warm is not None else g) * self.out
+        he = np.asarray(hedot, dtype=np.float64).reshape(3, 1, 1, 1)
+        for _ in range(self.fixed_iter):
+            jd = self.curl(hdot) * self.chi
+            hdot = hdot_in + self.out * (he + self.phi(jd))
+        self.warm = hdot * self.out
+        return hdot
+
+
+def host_cpu():
+    """CPU model and the threads this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(model=model, nproc=usable, logical_cpus=os.cpu_count())
+
+
+def cpu_baseline(cfg, h_np, calls=3):
+    """The oracle's rhs_eval (plain NumPy FP64, its own radix-2 FFT) on the
+    same 128^3 state with 3 exterior iterations: median of `calls` full
+    calls, BLAS and OpenMP pools held to one thread (NumPy's elementwise work
+    is single-threaded).  Beside it, as context, the multi-core scipy.fft
+    right-hand side (ScipyRhs) on all usable threads, median of 3."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import geometry, grid, rhs, units
-    from paper_1803_01346_amd import workloads
 
-    def problem(c, k):
-        g = grid.Grid(c["n"], c["half_width"])
-        chi = geometry.voxelize(g, c["shapes"])
-        u = units.Units(c["jc"], c["l_m"])
-        d = dict(c["drive"])
-        return rhs.Problem(g, chi, c["n_power"], c["rho_out"], units.Drive(u, d.pop("kind"), **d),
-                           rhs.RhsOptions(fixed_iter=k)), u
-
-    prob, u = problem(cfg, 1)
-    t = time.perf_counter()
-    rhs.rhs_eval(prob, T_STAR / u.t0, h_np)
-    dt = time.perf_counter() - t
-    ops_k1, ops_k3 = 2 + 2 * 1, 2 + 2 * FIXED_ITER
-    small = {}
-    for n in (32, 64):
-        c = dict(cfg, n=(n, n, n))
-        p, uu = problem(c, FIXED_ITER)
-        hs = workloads.synthetic_state(c, seed=0)
-        ts = []
-        for _ in range(3):
-            t1 = time.perf_counter()
-            rhs.rhs_eval(p, T_STAR / uu.t0, hs)
-            ts.append(time.perf_counter() - t1)
-        small["%d^3" % n] = round(1.0 / float(np.median(ts)), 3)
-    return dict(value=1.0 / (dt * ops_k3 / ops_k1), unit="RHS evals/s", cores=1, kind="oracle",
-                sample="one oracle rhs_eval at 128^3 (cup shield, FP64, own radix-2 FFT) with 1 "
-                       "exterior iteration: %.1f s for 4 operator applications, scaled x2 to the "
-                       "8 of a 3-iteration call" % dt,
-                smaller_boxes_rhs_per_s=small)
+    g = grid.Grid(cfg["n"], cfg["half_width"])
+    chi = geometry.voxelize(g, cfg["shapes"])
+    u = units.Units(cfg["jc"], cfg["l_m"])
+    d = dict(cfg["drive"])
+    drive = units.Drive(u, d.pop("kind"), **d)
+    prob = rhs.Problem(g, chi, cfg["n_power"], cfg["rho_out"], drive, rhs.RhsOptions(fixed_iter=FIXED_ITER))
+    ts = []
+    with threadpool_limits(1):
+        for _ in range(calls):
+            t = time.perf_counter()
+            rhs.rhs_eval(prob, T_STAR / u.t0, h_np)
+            ts.append(time.perf_counter() - t)
+            print("bench: oracle call %.1f s" % ts[-1], file=sys.stderr, flush=True)
+    med = float(np.median(ts))
+    host = host_cpu()
+    f = ScipyRhs(cfg["n"], cfg["half_width"], chi, cfg["n_power"], cfg["rho_out"], FIXED_ITER,
+                 workers=host["nproc"])
+    hedot = drive.hedot(T_STAR / u.t0)
+    f(hedot, h_np)                                   # warm-up (plans, warm start)
+    tq = []
+    for _ in range(3):
+        t = time.perf_counter()
+        f(hedot, h_np)
+        tq.append(time.perf_counter() - t)
+    return dict(value=round(1.0 / med, 5), unit="RHS evals/s", cores=1, kind="oracle",
+                sample="the oracle's rhs_eval at 128^3 (cup shield, FP64, 3 exterior iterations, own "
+                       "radix-2 FFT), median of %d full calls (%s s), one thread"
+                       % (calls, ", ".join("%.1f" % x for x in ts)),
+                host_cpu=host["model"], host_nproc=host["nproc"],
+                context_scipy_fft=dict(value=round(1.0 / float(np.median(tq)), 4), unit="RHS evals/s",
+                                       workers=host["nproc"], kind="scipy.fft rfftn/irfftn, FP64",
+                                       sample="median of 3 calls at 128^3 after one warm-up call"))
 
 
 def copy_calibration(nbytes=256 << 20, reps=5):
     """A plain device-to-device copy of known size: reads and writes nbytes per
-    launch.  Used to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    launch.  Used to scale the FETCH_SIZE / WRITE_SIZE counters and, at sizes
+    beyond the 256 MB last-level cache, as the achievable-bandwidth anchor
+    (timed with HIP events on the current stream)."""
     import torch
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": reps}))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        b.copy_(a)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)[reps // 2]
+    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 2 * reps,
+                      "median_ms": round(ms, 4), "read_plus_write_GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}))
+
+
+def profile_leg(leg, cfg, calls=6):
+    """A few right-hand sides of one leg only, for a kernel trace or counter
+    run under rocprofv3 (f64 / f32: the 128^3 shield; lens: the 256^3 lens)."""
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    if leg == "lens":
+        cfg = workloads.config("lens256")
+        sim = make_sim(cfg, scfft.F32, FIXED_ITER)
+        h = torch.from_numpy(workloads.synthetic_state(cfg, seed=0, background=(0.0, 0.0, 0.1))).to(
+            device="cuda", dtype=torch.float32).contiguous()
+        t = 10.0
+    else:
+        sim = make_sim(cfg, scfft.F64 if leg == "f64" else scfft.F32, FIXED_ITER)
+        h, _ = initial_state(sim, cfg)
+        t = T_STAR
+    hd = sim.empty_field()
+    for _ in range(calls):
+        sim.rhs_eval(t, h, hd)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_leg": leg, "rhs_calls": calls}))
+
+
+def timed_steps(sim, h, steps, warmup):
+    import torch
+    run_steps(sim, h, T_STAR, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, moments = run_steps(sim, h, T_STAR + warmup * DT_STEP, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if rc < 0 or st.accepted != steps:
+        raise RuntimeError("timed integration failed: rc=%d accepted=%d" % (rc, st.accepted))
+    return st, elapsed
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="cup128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-events", action="store_true", help="skip the per-kernel event timing run")
+    ap.add_argument("--no-events", action="store_true", help="skip the per-kernel event timing runs")
     ap.add_argument("--no-converged", action="store_true", help="skip the delta_it stopping-rule leg")
     ap.add_argument("--no-lens", action="store_true", help="skip the 256^3 FP32 lens leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay / batch leg")
-    ap.add_argument("--no-lens-gain", action="store_true", help="skip the lens field-concentration run")
-    ap.add_argument("--no-shield", action="store_true", help="skip the shield cases A/B run")
-    ap.add_argument("--no-shield-config", action="store_true",
-                    help="skip the two-period shield run (bore-axis probe, FP64 and FP32)")
-    ap.add_argument("--no-lens-config", action="store_true",
-                    help="skip the 256^3 lens ramp (field-concentration factor at the bore centre)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the paper's shield and lens runs (lens gain, shield cases, "
+                         "two-period shield, 256^3 lens ramp)")
+    ap.add_argument("--profile-leg", choices=["f64", "f32", "lens"],
+                    help="only run a few right-hand sides of one leg (for rocprofv3)")
+    ap.add_argument("--copy-calibration", type=int, nargs="?", const=256 << 20, default=None,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method here runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); rerun with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration is not None:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     from paper_1803_01346_amd import scfft, workloads
     scfft.load()
     torch.cuda.set_device(0)
     cfg = workloads.config(args.config)
+    if args.profile_leg:
+        profile_leg(args.profile_leg, cfg)
+        return
 
     sim = make_sim(cfg, scfft.F64, FIXED_ITER)
     h, h_np = initial_state(sim, cfg)
     print("bench: %s FP64, warmup %d steps" % (args.config, args.warmup), file=sys.stderr, flush=True)
-    run_steps(sim, h, T_STAR, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, st, moments = run_steps(sim, h, T_STAR + args.warmup * DT_STEP, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    if rc < 0 or st.accepted != args.steps:
-        raise RuntimeError("timed integration failed: rc=%d accepted=%d" % (rc, st.accepted))
+    st, elapsed = timed_steps(sim, h, args.steps, args.warmup)
     value = st.rhs_calls / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
     print("bench: %d steps, %d RHS calls in %.3f s" % (args.steps, st.rhs_calls, elapsed),
           file=sys.stderr, flush=True)
     n = tuple(cfg["n"])
 
-    # per-kernel durations with HIP events on the library's stream, same steps
-    per_kind, roof = {}, None
-    if not args.no_events:
-        per_kind = kernel_profile(sim, lambda: run_steps(sim, h, T_STAR, args.steps))
-        roof = roofline_of(per_kind, measured_traffic)
-
     # right-hand side alone (no integrator work)
-    rhs_ps, hd64 = time_rhs_only(sim, h, 50)
+    rhs_ps, hd64 = time_rhs_only(sim, h, 200)
     rhs_med_ms = rhs_event_median(sim, h, hd64)
     rhs_hbm = None if args.no_events else rhs_bandwidth(sim, h, hd64, rhs_ps, n)
 
+    # per-kernel durations with HIP events on the library's stream, same steps
+    per_kind, roof = {}, None
+    if not args.no_events:
+        per_kind = kernel_profile(sim, lambda: run_steps(sim, h, T_STAR, min(args.steps, 50)))
+        whole = dict(rhs_hbm, note="whole right-hand side: library byte count per call x calls/s "
+                                   "(rhs_only); at 128^3 its working set (~105 MB FP64) fits in the "
+                                   "256 MB last-level cache, so lens256_f32 is the HBM regime")
+        roof = roofline_of(per_kind, measured_traffic, whole)
+
     fp32 = None
     if not args.no_fp32:
+        print("bench: FP32 leg", file=sys.stderr, flush=True)
         sim32 = make_sim(cfg, scfft.F32, FIXED_ITER)
         h32 = h.float()
-        rhs32, _ = time_rhs_only(sim32, h32, 50)
+        rhs32, hd32 = time_rhs_only(sim32, h32, 200)
         # FP32 against FP64 on the same state, both from an Ohm-law start
         s32 = make_sim(cfg, scfft.F32, FIXED_ITER)
         s64 = make_sim(cfg, scfft.F64, FIXED_ITER)
@@ -591,30 +757,34 @@ def main():
         o64, _ = s64.rhs_eval(T_STAR, h)
         torch.cuda.synchronize()
         rel = float(torch.linalg.vector_norm(o32.double() - o64) / torch.linalg.vector_norm(o64))
-        run_steps(sim32, h32, T_STAR, args.warmup)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rc32, st32, _ = run_steps(sim32, h32, T_STAR + args.warmup * DT_STEP, args.steps)
-        torch.cuda.synchronize()
-        el32 = time.perf_counter() - t1
+        s32.close()
+        s64.close()
+        st32, el32 = timed_steps(sim32, h32, args.steps, args.warmup)
         fp32 = dict(value=round(st32.rhs_calls / el32, 2), rhs_only=round(rhs32, 2),
                     rel_l2_vs_fp64=rel, ms_per_step=round(1e3 * el32 / args.steps, 3))
+        if not args.no_events:
+            pk32 = kernel_profile(sim32, lambda: run_steps(sim32, h32, T_STAR, min(args.steps, 50)))
+            fp32["roofline"] = roofline_of(pk32, None, rhs_bandwidth(sim32, h32, hd32, rhs32, n))
+            fp32["kernels"] = pk32
+        sim32.close()
 
     converged = None if args.no_converged else converged_leg(cfg, h)
+    print("bench: 256^3 lens leg", file=sys.stderr, flush=True)
     lens = None if args.no_lens else lens256_leg()
+    print("bench: adjoint leg", file=sys.stderr, flush=True)
     adj = None if args.no_adjoint else adjoint_leg(cfg)
+    print("bench: batch leg", file=sys.stderr, flush=True)
     gleg = None if args.no_graph else graph_leg()
-    shield = None if args.no_shield else shield_leg()
-    lens_cfg = None if args.no_lens_config else lens_config_leg()
-    shield_cfg = None if args.no_shield_config else shield_config_leg()
-    lgain = None
-    if not args.no_lens_gain:
-        lgain = {"n_power": 30.0, "rho_out": 100.0, "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
-                 "128": lens_gain_leg(128), "256": lens_gain_leg(256, f32=True)}
+    extras = None
+    if args.extras:
+        extras = {"shield": shield_leg(), "lens_config": lens_config_leg(), "shield_config": shield_config_leg(),
+                  "lens_gain": {"n_power": 30.0, "rho_out": 100.0,
+                                "paper_biconical": {"gain_0.05": 2.0, "gain_0.20": 1.6},
+                                "128": lens_gain_leg(128), "256": lens_gain_leg(256, f32=True)}}
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline (about 30 s)", file=sys.stderr, flush=True)
+        print("bench: CPU oracle baseline (3 oracle calls at 128^3)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg, h_np)
 
     line = {
@@ -642,10 +812,7 @@ def main():
         "lens256_f32": lens,
         "adjoint_cost": adj,
         "graphs": gleg,
-        "lens_gain": lgain,
-        "shield": shield,
-        "lens_config": lens_cfg,
-        "shield_config": shield_cfg,
+        "extras": extras,
         "roofline": roof,
         "kernels": per_kind,
         "cpu_baseline": cpu,
