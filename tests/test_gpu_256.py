@@ -121,3 +121,52 @@ def test_rhs_lens_256():
     b, _ = s32.rhs_eval(10.0, dh.float())
     torch.cuda.synchronize()
     assert rel_l2(_np(b), A) < 1e-4
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                    "lens256_rhs_samples.npz")
+
+
+@pytest.fixture(scope="module")
+def lens_golden():
+    """The FP64 oracle's right-hand side of the 256^3 lens box at sampled
+    nodes (written by tests/golden/make_lens256_samples.py, which calls only
+    the oracle) and the same seeded input, regenerated here."""
+    import hashlib
+    z = np.load(GOLDEN, allow_pickle=False)
+    h = state(LENS, seed=int(z["seed_state"]), bg=tuple(z["background"]))
+    idx = z["idx"]
+    at = np.ascontiguousarray(h.reshape(3, -1)[:, idx], dtype=np.float64)
+    assert hashlib.sha256(at.tobytes()).hexdigest() == str(z["h_sha256"])     # the same input
+    return z, h, idx
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+def test_rhs_lens_256_against_oracle_samples(prec, lens_golden):
+    """The 256^3 lens right-hand side (3 exterior iterations, the bench's
+    schedule) against the oracle at 9.2k sampled nodes, including the bore
+    axis and the line through the slit: a first call (Ohm-law start of
+    Eq. 5) and a warm-started second call.  FP64 <= 1e-10 relative to the
+    largest magnitude over all nodes; FP32 <= 1e-4 relative L2 over the
+    samples."""
+    z, h, idx = lens_golden
+    s = sim(LENS, precision=prec, fixed_iter=int(z["fixed_iter"]))
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    dh = to_dev(torch, h, dt)
+    for k, t_s in enumerate(z["t_s"]):
+        out, _ = s.rhs_eval(float(t_s), dh)
+        torch.cuda.synchronize()
+        got = _np(out).reshape(3, -1)[:, idx]
+        want = z["hdot%d" % k]
+        if prec == scfft.F64:
+            err = float(np.max(np.abs(got - want))) / float(z["scale%d" % k])
+            out = z["chi_at"] == 0
+            err_out = float(np.max(np.abs(got[:, out] - want[:, out]) / np.max(np.abs(want[:, out]))))
+            print("256^3 FP64 call %d: rel max %.2e (Omega_out samples on their own scale %.2e)"
+                  % (k, err, err_out))
+            assert err < 1e-10, k
+        else:
+            err = rel_l2(got, want)
+            print("256^3 FP32 call %d: rel L2 %.2e over the samples" % (k, err))
+            assert err < 1e-4, k
+    s.close()
