@@ -425,6 +425,19 @@ scfft_status scfft_integrate_adjoint(scfft_ctx* ctx, double t0_s, double t1_s, i
 
 /* out = C_s v, the smoothed spectral curl (derivatives of Eqs. 3, 4). */
 scfft_status scfft_curl(scfft_ctx* ctx, const void* v_dev, void* out_dev);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): out =
+ * C_s v exactly as scfft_curl computes it, but the half spectrum and the
+ * axis tables live in a static device array of the library instead of the
+ * context's workspace, which need not be attached.  The array holds 8 MiB
+ * on each GPU the library runs on, kept until the process ends; grids whose
+ * spectrum and tables need more (e.g. above 64^3 nodes in FP64, 64 x 64 x
+ * 128 in FP32) are refused with SCFFT_ERR_WORKSPACE.  No allocating routine
+ * is called.  Every call on one GPU reuses that GPU's array: calls ordered
+ * on one stream are safe, calls that overlap in time on one GPU (other
+ * streams or threads) race.  The current device must be the context's
+ * (SCFFT_ERR_DEVICE otherwise).  Asynchronous on the context stream. */
+scfft_status scfft_curl_noalloc(scfft_ctx* ctx, const void* v_dev, void* out_dev);
 /* out = Phi[v], Eq. 7 with the k = 0 rule (smoothed iff smooth_phi). */
 scfft_status scfft_phi(scfft_ctx* ctx, const void* v_dev, void* out_dev);
 /* j' = C_s h (dimensionless current density, all nodes). */

@@ -211,6 +211,10 @@ hipError_t launch_probe(const T* h, int nx, int ny, int nz, const double* pts, i
 template <typename T>
 hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t nodes,
                               hipStream_t s);
+// the tables of one axis (AxisTab layout) computed on the device, in FP64
+template <typename T>
+hipError_t launch_axis_table(C2<T>* tw, T* kodd, T* kk, T* sm, int n, double L, double sigma,
+                             hipStream_t s);
 // per-block counts of values that are not finite and > 0 (jc map check)
 template <typename T>
 hipError_t launch_count_nonpositive(const T* v, size_t n, double* partials, int nblocks,

@@ -443,6 +443,34 @@ hipError_t launch_count_nonpositive(const T* v, size_t n, double* partials, int 
   return hipGetLastError();
 }
 
+// The axis tables of one axis on the device (the layout of AxisTab):
+// tw[i] = exp(-2 pi i / n), kodd[i] = pi m / L (0 at the Nyquist index),
+// kk[i] = (pi m / L)^2, sm[i] = exp(-sigma^2 (pi m / L)^2 / 2), m the signed
+// index of i.  Evaluated in FP64.
+template <typename T>
+__global__ __launch_bounds__(kRB) void axis_table_kernel(C2<T>* __restrict__ tw, T* __restrict__ kodd,
+                                                         T* __restrict__ kk, T* __restrict__ sm, int n,
+                                                         double L, double sigma) {
+  const int i = blockIdx.x * kRB + threadIdx.x;
+  if (i >= n) return;
+  double sn, cs;
+  sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
+  tw[i] = {(T)cs, (T)sn};
+  const int m = 2 * i < n ? i : i - n;
+  const double k = M_PI * (double)m / L;
+  kodd[i] = (T)(2 * i == n ? 0.0 : k);
+  kk[i] = (T)(k * k);
+  sm[i] = (T)exp(-0.5 * sigma * sigma * k * k);
+}
+
+template <typename T>
+hipError_t launch_axis_table(C2<T>* tw, T* kodd, T* kk, T* sm, int n, double L, double sigma,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((axis_table_kernel<T>), dim3((n + kRB - 1) / kRB), dim3(kRB), 0, s, tw, kodd, kk, sm,
+                     n, L, sigma);
+  return hipGetLastError();
+}
+
 #define SCFFT_INST(T)                                                                          \
   template hipError_t launch_fill_uniform<T>(T*, size_t, const double[3], hipStream_t);        \
   template hipError_t launch_combo<T>(T*, const T*, const T*, double, const T*, double,        \
@@ -460,7 +488,8 @@ hipError_t launch_count_nonpositive(const T* v, size_t n, double* partials, int 
   template hipError_t launch_masked_copy<T>(T*, const T*, const uint8_t*, size_t, hipStream_t); \
   template hipError_t launch_ratio_max<T>(const T*, const T*, double, size_t, double*, int,     \
                                           hipStream_t);                                         \
-  template hipError_t launch_count_nonpositive<T>(const T*, size_t, double*, int, hipStream_t);
+  template hipError_t launch_count_nonpositive<T>(const T*, size_t, double*, int, hipStream_t); \
+  template hipError_t launch_axis_table<T>(C2<T>*, T*, T*, T*, int, double, double, hipStream_t);
 SCFFT_INST(double)
 SCFFT_INST(float)
 #undef SCFFT_INST

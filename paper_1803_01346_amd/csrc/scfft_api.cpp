@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -188,21 +189,23 @@ void layout(scfft_ctx* c) {
 template <typename T>
 T* wsp(scfft_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
 
+// Plan over a spectrum at `main` and axis tables at `tab` (per axis: N
+// twiddles, then kodd, kk, sm, each N values; axes 256-byte aligned).
 template <typename T>
-Plan<T> make_plan(scfft_ctx* c) {
+Plan<T> plan_on(const scfft_ctx* c, char* main, char* tab) {
   Plan<T> p;
   p.nx = c->n[0];
   p.ny = c->n[1];
   p.nz = c->n[2];
-  p.main = wsp<C2<T>>(c, c->off_main);
-  size_t o = c->off_tab;
+  p.main = reinterpret_cast<C2<T>*>(main);
+  size_t o = 0;
   AxisTab<T>* tabs[3] = {&p.ax, &p.ay, &p.az};
   for (int a = 0; a < 3; ++a) {
     const size_t N = c->n[a];
-    tabs[a]->tw = wsp<C2<T>>(c, o);
-    tabs[a]->kodd = wsp<T>(c, o + N * 2 * sizeof(T));
-    tabs[a]->kk = wsp<T>(c, o + N * 3 * sizeof(T));
-    tabs[a]->sm = wsp<T>(c, o + N * 4 * sizeof(T));
+    tabs[a]->tw = reinterpret_cast<const C2<T>*>(tab + o);
+    tabs[a]->kodd = reinterpret_cast<const T*>(tab + o + N * 2 * sizeof(T));
+    tabs[a]->kk = reinterpret_cast<const T*>(tab + o + N * 3 * sizeof(T));
+    tabs[a]->sm = reinterpret_cast<const T*>(tab + o + N * 4 * sizeof(T));
     o = align_up(o + N * 5 * sizeof(T));
   }
   p.full_ranges();
@@ -210,6 +213,9 @@ Plan<T> make_plan(scfft_ctx* c) {
   p.xalt = c->opts.x_alt;
   return p;
 }
+
+template <typename T>
+Plan<T> make_plan(scfft_ctx* c) { return plan_on<T>(c, c->ws + c->off_main, c->ws + c->off_tab); }
 
 // Plans restricted to the bounding box of Omega (identical results: skipped
 // inputs are exact zeros, skipped outputs are never read).
@@ -785,13 +791,11 @@ scfft_status rhs_vjp_impl(scfft_ctx* c, const T* h, const T* in2, double in2_coe
   return SCFFT_OK;
 }
 
+// One operator application v -> out: forward transform, the symbol in the Z
+// pass, inverse transform (the X/XY passes read in and write out only).
 template <typename T>
-scfft_status apply_operator(scfft_ctx* c, const T* v, T* out, int sym, double sign) {
-  const Plan<T> p = make_plan<T>(c);
+scfft_status apply_on(scfft_ctx* c, const Plan<T>& p, const XArgs<T>& a, int sym, double sign) {
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
-  XArgs<T> a = base_args<T>(c);
-  a.in = v;
-  a.out = out;
   if (use_xy<T>(c, p)) {
     HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));
     HIPCHK(c, run_z<T>(c, p, sym, sign * norm));
@@ -802,6 +806,71 @@ scfft_status apply_operator(scfft_ctx* c, const T* v, T* out, int sym, double si
   HIPCHK(c, spectral_middle<T>(c, p, sym, sign * norm));
   HIPCHK(c, run_x<T>(c, p, X_STORE, a));
   return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status apply_operator(scfft_ctx* c, const T* v, T* out, int sym, double sign) {
+  XArgs<T> a = base_args<T>(c);
+  a.in = v;
+  a.out = out;
+  return apply_on<T>(c, make_plan<T>(c), a, sym, sign);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free curl (scfft_curl_noalloc)
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate device memory, the half spectrum and the
+// axis tables of one curl live in this file-scope device array instead of the
+// context's workspace: one copy per GPU, held until the process ends, shared
+// by every call on that GPU.  In host code the array's name is not a device
+// address: host code uses the address hipGetSymbolAddress returns for the
+// current device (scratch_on), looked up once per device.
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on(int dev, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// bytes of the scratch array one curl needs: half spectrum, then the tables
+size_t noalloc_spec_bytes(const scfft_ctx* c) {
+  return align_up(3 * (size_t)c->n[2] * c->n[1] * (c->n[0] / 2) * 2 * c->wsize);
+}
+size_t noalloc_bytes(const scfft_ctx* c) {
+  size_t o = noalloc_spec_bytes(c);
+  for (int a = 0; a < 3; ++a) o = align_up(o + (size_t)c->n[a] * 5 * c->wsize);
+  return o;
+}
+
+template <typename T>
+scfft_status curl_noalloc_impl(scfft_ctx* c, char* base, const T* v, T* out) {
+  char* tab = base + noalloc_spec_bytes(c);
+  size_t o = 0;
+  for (int a = 0; a < 3; ++a) {  // every call writes the tables it reads
+    const size_t N = c->n[a];
+    HIPCHK(c, launch_axis_table<T>(reinterpret_cast<C2<T>*>(tab + o), reinterpret_cast<T*>(tab + o + N * 2 * sizeof(T)),
+                                   reinterpret_cast<T*>(tab + o + N * 3 * sizeof(T)),
+                                   reinterpret_cast<T*>(tab + o + N * 4 * sizeof(T)), (int)N, c->L[a], c->sigma,
+                                   c->stream));
+    o = align_up(o + N * 5 * sizeof(T));
+  }
+  XArgs<T> a;
+  std::memset(&a, 0, sizeof a);  // the forward and store passes read in and write out only
+  a.in = v;
+  a.out = out;
+  return apply_on<T>(c, plan_on<T>(c, base, tab), a, Z_CURL, 1.0);
 }
 
 template <typename T>
@@ -1792,6 +1861,8 @@ scfft_status scfft_create(scfft_ctx** out, const scfft_grid* g, const scfft_mate
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return SCFFT_ERR_DEVICE;
+  char* scratch_dev = nullptr;  // device address of the allocation-free curl's array
+  if (scratch_on(dev, &scratch_dev) != hipSuccess) return SCFFT_ERR_DEVICE;
   scfft_ctx* c = new scfft_ctx();
   c->grid = *g;
   c->mat = *m;
@@ -2215,6 +2286,28 @@ scfft_status scfft_phi(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
   return ctx->prec == SCFFT_F64
              ? apply_operator<double>(ctx, (const double*)v_dev, (double*)out_dev, sym, 1.0)
              : apply_operator<float>(ctx, (const float*)v_dev, (float*)out_dev, sym, 1.0);
+}
+
+scfft_status scfft_curl_noalloc(scfft_ctx* ctx, const void* v_dev, void* out_dev) {
+  if (!ctx) return SCFFT_ERR_ARG;
+  if (ctx->graph_busy) return fail(ctx, SCFFT_ERR_STATE, "a graph integration is enqueued");
+  if (!v_dev || !out_dev) return fail(ctx, SCFFT_ERR_ARG, "NULL field pointer");
+  CHECK_FIELD(ctx, v_dev);
+  CHECK_FIELD(ctx, out_dev);
+  const size_t need = noalloc_bytes(ctx);
+  if (need > kScratchBytes)
+    return fail(ctx, SCFFT_ERR_WORKSPACE,
+                "the allocation-free curl has %zu bytes of device scratch; this grid needs %zu",
+                kScratchBytes, need);
+  int dev = -1;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  if (dev != ctx->device)
+    return fail(ctx, SCFFT_ERR_DEVICE, "current device %d is not the context's (%d)", dev, ctx->device);
+  char* base = nullptr;
+  HIPCHK(ctx, scratch_on(dev, &base));
+  return ctx->prec == SCFFT_F64
+             ? curl_noalloc_impl<double>(ctx, base, (const double*)v_dev, (double*)out_dev)
+             : curl_noalloc_impl<float>(ctx, base, (const float*)v_dev, (float*)out_dev);
 }
 
 scfft_status scfft_current(scfft_ctx* ctx, const void* h_dev, void* j_dev) {

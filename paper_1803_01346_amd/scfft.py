@@ -117,6 +117,7 @@ _SIGS = {
     "scfft_integrate": (C.c_int, [_P, C.c_double, C.c_double, _P, C.POINTER(OdeOpts), OBSERVER,
                                   _P, C.POINTER(OdeStats)]),
     "scfft_curl": (C.c_int, [_P, _P, _P]),
+    "scfft_curl_noalloc": (C.c_int, [_P, _P, _P]),
     "scfft_phi": (C.c_int, [_P, _P, _P]),
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
@@ -381,6 +382,10 @@ def scfft_integrate(ctx, t0_s, t1_s, h, opts, observer=None, stats=None):
 
 def scfft_curl(ctx, v, out):
     return _check(load().scfft_curl(ctx, _ptr(v), _ptr(out)), ctx)
+
+
+def scfft_curl_noalloc(ctx, v, out):
+    return _check(load().scfft_curl_noalloc(ctx, _ptr(v), _ptr(out)), ctx)
 
 
 def scfft_phi(ctx, v, out):
