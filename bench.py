@@ -273,69 +273,148 @@ def adjoint_leg(cfg, steps=2000, every=50):
 
 
 def graph_leg(count=64, steps=4):
-    """Launch-bound and batched regimes: the 32^3 cube alone, and a batch of
-    independent instances of mixed size (boxes of 48 to 192 nodes per edge,
-    radix-3 lengths included), integrated with fixed steps (3 exterior
-    iterations) either one after another with per-kernel launches or with
-    graph-replayed steps, one stream per instance, all in flight at once;
-    each instance's pass schedule is picked by the autotuner first.
-    Aggregate right-hand-side evaluations per second."""
+    """Launch-bound and batched regimes, fixed steps (3 exterior iterations)
+    replayed from captured graphs:
+      cube32          one 32^3 cube: per-kernel launches vs graph replay;
+      batch           the 64 mixed instances of workloads.batch_instances
+                      (seed 4; box edges 48 to 192, cube / cylinder / cup,
+                      n, jc and field directions drawn): each instance its
+                      own context on its own stream (schedule autotuned),
+                      against one batch per box edge whose members share
+                      every launch (scfft_batch), the batches on their own
+                      streams.  Aggregate right-hand sides per second
+                      (1 + 3 steps per instance), also per box edge, and the
+                      batched right-hand side's bytes against the HBM peak."""
+    import gc
+
     import torch
     from paper_1803_01346_amd import scfft, workloads
+    opts = lambda: scfft.default_rhs_opts(fixed_iter=FIXED_ITER)
 
-    def setup(cfgs):
-        streams = [torch.cuda.Stream() for _ in cfgs]
-        sims = [scfft.Simulation(c, precision=scfft.F64, stream=st.cuda_stream,
-                                 rhs_opts=scfft.default_rhs_opts(fixed_iter=FIXED_ITER))
-                for c, st in zip(cfgs, streams)]
-        hs = [workloads.synthetic_state_torch(c, seed=i) for i, c in enumerate(cfgs)]
+    def per_instance(cl):
+        sts = [torch.cuda.Stream() for _ in cl]
+        sims = [scfft.Simulation(c, precision=scfft.F64, stream=st.cuda_stream, rhs_opts=opts())
+                for c, st in zip(cl, sts)]
+        hs = [workloads.synthetic_state_torch(c, seed=i) for i, c in enumerate(cl)]
         wss = [scfft.device_buffer(scfft.scfft_graph_workspace_size(s_.ctx, steps)) for s_ in sims]
         torch.cuda.synchronize()
-        # the schedule autotuner picks row/column or fused plane passes per instance
         picks = [scfft.scfft_autotune(s_.ctx, h, calls=3)[0] for s_, h in zip(sims, hs)]
-        return streams, sims, hs, wss, picks
 
-    def plain(sims, hs):
-        o = scfft.default_ode_opts(fixed_steps=steps)
-
-        def run(hh):
-            for s_, h in zip(sims, hh):
-                scfft.scfft_integrate(s_.ctx, 0.0, 1e-3, h, o)
+        def run():
+            hh = [h.clone() for h in hs]
             torch.cuda.synchronize()
-        run([h.clone() for h in hs])
-        t = time.perf_counter()
-        run([h.clone() for h in hs])
-        return len(sims) * (1 + 3 * steps) / (time.perf_counter() - t)
-
-    def graphs(sims, hs, wss):
-        def run(hh):
+            t = time.perf_counter()
             for s_, h, ws in zip(sims, hh, wss):
                 scfft.scfft_integrate_graph(s_.ctx, 0.0, 1e-3, steps, ws, h)
             for s_ in sims:
                 scfft.scfft_integrate_wait(s_.ctx)
             torch.cuda.synchronize()
-        run([h.clone() for h in hs])
-        hh = [h.clone() for h in hs]
+            return time.perf_counter() - t
+
+        run()
+        el = run()
+        for s_ in sims:
+            s_.close()
+        return len(cl) * (1 + 3 * steps) / el, picks
+
+    def batched(groups):
+        bs = []
+        for cl in groups:
+            st = torch.cuda.Stream()
+            b = scfft.Batch(cl, precision=scfft.F64, stream=st.cuda_stream, rhs_opts=opts())
+            h = torch.stack([workloads.synthetic_state_torch(c, seed=i) for i, c in enumerate(cl)]).contiguous()
+            bs.append((b, h, b.graph_workspace(steps)))
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        run(hh)
-        return len(sims) * (1 + 3 * steps) / (time.perf_counter() - t)
+
+        def run():
+            hh = [h.clone() for _, h, _ in bs]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for (b, _, ws), h in zip(bs, hh):
+                b.integrate_graph(0.0, 1e-3, steps, h, ws)
+            for b, _, _ in bs:
+                b.wait()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t
+
+        run()
+        el = run()
+        # bytes of one batched right-hand side (library count) and its rate, batch by batch
+        nbytes, secs = 0.0, 0.0
+        for b, h, _ in bs:
+            pk = kernel_profile(b.sims[0], lambda: b.rhs_eval(0.2, h))
+            nbytes += sum(v["bytes_per_launch"] * v["launches"] for v in pk.values())
+            hd = b.empty_field()
+            for _ in range(2):
+                b.rhs_eval(0.2, h, hd)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                b.rhs_eval(0.2, h, hd)
+            torch.cuda.synchronize()
+            secs += (time.perf_counter() - t) / 5
+        n = sum(len(cl) for cl in groups)
+        for b, _, _ in bs:
+            b.close()
+        return n * (1 + 3 * steps) / el, dict(bytes_per_batched_rhs_all=int(nbytes),
+                                               rhs_per_s=round(n / secs, 1),
+                                               achieved_GBs=round(nbytes / secs / 1e9, 1),
+                                               frac=round(nbytes / secs / (HBM_PEAK_GBS * 1e9), 4))
 
     out = dict(steps=steps, exterior_iters=FIXED_ITER, dtype="f64", unit="RHS evals/s")
-    _, sims, hs, wss, picks = setup([workloads.config("cube32")])
-    out["cube32"] = dict(plain=round(plain(sims, hs), 1), graph=round(graphs(sims, hs, wss), 1),
-                         fuse_xy=picks[0])
-    batch = workloads.batch_instances(count)
+    sims = [scfft.Simulation(workloads.config("cube32"), precision=scfft.F64, rhs_opts=opts())]
+    h = workloads.synthetic_state_torch(workloads.config("cube32"), seed=0)
+    ws = scfft.device_buffer(scfft.scfft_graph_workspace_size(sims[0].ctx, steps))
+    pick = scfft.scfft_autotune(sims[0].ctx, h, calls=3)[0]
+
+    def cube(graph):
+        hh = h.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if graph:
+            scfft.scfft_integrate_graph(sims[0].ctx, 0.0, 1e-3, steps, ws, hh)
+            scfft.scfft_integrate_wait(sims[0].ctx)
+        else:
+            scfft.scfft_integrate(sims[0].ctx, 0.0, 1e-3, hh, scfft.default_ode_opts(fixed_steps=steps))
+        torch.cuda.synchronize()
+        return (1 + 3 * steps) / (time.perf_counter() - t)
+
+    cube(False), cube(True)
+    out["cube32"] = dict(plain=round(cube(False), 1), graph=round(cube(True), 1), fuse_xy=pick)
+    sims[0].close()
+
+    cfgs = workloads.batch_instances(count)
+    groups = {}
+    for c in cfgs:
+        groups.setdefault(c["n"][0], []).append(c)
+    edges = sorted(groups)
+    res = dict(instances=count, edges=edges, per_edge={str(e): len(groups[e]) for e in edges})
     t = time.perf_counter()
-    _, sims, hs, wss, picks = setup(batch)
-    t_setup = time.perf_counter() - t
-    edges = sorted({c["n"][0] for c in batch})
-    out["batch"] = dict(instances=count, edges=edges,
-                        per_edge={str(e): sum(c["n"][0] == e for c in batch) for e in edges},
-                        setup_s=round(t_setup, 1), fused_plane_picks=int(sum(x == 2 for x in picks)),
-                        plain=round(plain(sims, hs), 1), graph_streams=round(graphs(sims, hs, wss), 1))
-    for s_ in sims:
-        s_.close()
+    rate, picks = per_instance(cfgs)
+    res["per_instance_streams"] = round(rate, 1)
+    res["fused_plane_picks"] = int(sum(x == 2 for x in picks))
+    gc.collect()
+    torch.cuda.empty_cache()
+    rate, hbm = batched([groups[e] for e in edges])
+    res["batched"] = round(rate, 1)
+    res["batched_rhs_hbm"] = hbm
+    gc.collect()
+    torch.cuda.empty_cache()
+    small = {}
+    for e in edges:
+        if e > 64:
+            continue
+        r_inst, _ = per_instance(groups[e])
+        gc.collect()
+        torch.cuda.empty_cache()
+        r_b, _ = batched([groups[e]])
+        gc.collect()
+        torch.cuda.empty_cache()
+        small[str(e)] = dict(instances=len(groups[e]), per_instance_streams=round(r_inst, 1),
+                             batched=round(r_b, 1), gain=round(r_b / r_inst, 3))
+    res["small_boxes"] = small
+    res["wall_s"] = round(time.perf_counter() - t, 1)
+    out["batch"] = res
     return out
 
 

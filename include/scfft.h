@@ -143,7 +143,13 @@ typedef struct {
  *                start, masks, exterior update with fixed_iter, store) hold
  *                the alternate number of elements per thread (4 instead of 8,
  *                or 8 instead of 4: other radices and rows per block).
- *                Results agree to rounding; scfft_autotune picks it. */
+ *                Results agree to rounding; scfft_autotune picks it.
+ *   y_alt, z_alt 0 (default) or 1: the y passes, and the z passes with the
+ *                operator symbols, hold the alternate number of elements per
+ *                thread (y: 4 instead of 8; z: 8 instead of 4 in FP64, 4
+ *                instead of 8 in FP32), i.e. other radix sequences, column
+ *                widths per block and register budgets.  Results agree to
+ *                rounding; scfft_autotune picks them. */
 typedef struct {
   double delta_it;
   int32_t min_iter;
@@ -154,6 +160,8 @@ typedef struct {
   int32_t fuse_xy;
   int32_t prune_box;
   int32_t x_alt;
+  int32_t y_alt;
+  int32_t z_alt;
 } scfft_rhs_opts;
 
 typedef struct {
@@ -331,13 +339,15 @@ scfft_status scfft_integrate(scfft_ctx* ctx, double t0_s, double t1_s, void* h_d
                              scfft_ode_stats* stats);
 
 /* Autotuner: times one right-hand-side call (fixed_iter > 0) under each pass
- * schedule this grid supports (row/column passes with either element count
- * of the per-component x passes, rhs option x_alt 0 or 1; fused xy-plane
- * passes where a z plane fits in LDS) on the caller's state h, calls times
- * each after a warm-up call, and keeps the fastest as the rhs options fuse_xy
- * (0 or 2) and x_alt.  The warm start is restored afterwards.  fuse_xy and
- * ms_per_call (may be NULL) receive the schedule and its mean time per call;
- * scfft_get_rhs_opts returns all options.  Synchronous. */
+ * schedule this grid supports on the caller's state h, calls times each after
+ * a warm-up call, and keeps the fastest.  The schedules: row/column passes or
+ * fused xy-plane passes where a z plane fits in LDS (rhs option fuse_xy 0 or
+ * 2), crossed with the instantiated variants of the passes (x_alt for the
+ * per-component x passes of the row/column schedule, y_alt, z_alt: other
+ * elements per thread, radices and column widths).  The warm start is
+ * restored afterwards.  fuse_xy and ms_per_call (may be NULL) receive the
+ * schedule and its mean time per call; scfft_get_rhs_opts returns all
+ * options.  Synchronous. */
 scfft_status scfft_autotune(scfft_ctx* ctx, const void* h_dev, int32_t calls, int32_t* fuse_xy,
                             double* ms_per_call);
 
@@ -374,6 +384,49 @@ scfft_status scfft_integrate_wait(scfft_ctx* ctx, scfft_ode_stats* stats);
  * and the accepted count to *n_steps. */
 scfft_status scfft_graph_moments(scfft_ctx* ctx, int32_t omega_only, int32_t max_steps, double* m_Am2,
                                  int32_t* n_steps);
+
+/* ---- batches of same-size instances ----
+ *
+ * Many instances of the method (Sec. 2: each its own body, material and
+ * applied field) on grids of one size, advanced together: every transform
+ * pass is a single launch over all of them, so boxes too small to fill the
+ * GPU alone do so as a batch.  The members are ordinary contexts, each set
+ * up as usual (mask, drive, material n / jc / rho_out, optional jc map,
+ * options), with
+ *   - equal node counts, dimensionless half widths (box / l) and precision,
+ *     one stream, equal right-hand-side options with fixed_iter > 0;
+ *   - no field-dependent or anisotropic law; jc maps on all or on none;
+ *   - workspaces that follow each other at one constant stride (member b's
+ *     workspace = member 0's + b * stride bytes, stride >= the workspace
+ *     size, a multiple of 256): one allocation carved in equal slices.
+ * A batch holds no device memory of its own beyond those workspaces; the
+ * members stay usable alone between batch calls.  Batched fields are
+ * caller-owned device arrays with member b's field at base + b *
+ * field_stride elements (field_stride >= 3 Nx Ny Nz, even).  Up to 512
+ * members; every call runs on member 0's stream.  Errors of batch calls are
+ * reported through member 0 (scfft_batch_last_error). */
+typedef struct scfft_batch scfft_batch;
+scfft_status scfft_batch_create(scfft_batch** out, scfft_ctx* const* members, int32_t count);
+void scfft_batch_destroy(scfft_batch* batch);
+/* One right-hand side of every member at time t_s (each in its own Eq. 8
+ * units), as scfft_rhs_eval gives it, with batched launches; updates every
+ * member's warm start (members must agree on having one). */
+scfft_status scfft_batch_rhs_eval(scfft_batch* batch, double t_s, const void* h_dev, void* hdot_dev,
+                                  int64_t field_stride);
+/* The graph-replayed fixed-step integration of scfft_integrate_graph for
+ * the whole batch: `steps` equal Bogacki-Shampine steps from t0_s to t1_s of
+ * every member, one captured step of batched launches replayed `steps`
+ * times; each member's step size, stage coefficients and applied-field rates
+ * (tabulated on the host) follow its own time unit.  A non-finite error norm
+ * of any member stops all.  scfft_batch_integrate_wait synchronises, writes
+ * the last accepted states back to h (batched) and fills stats[count].
+ * graph_ws: scfft_batch_graph_workspace_size bytes, 256-byte aligned. */
+scfft_status scfft_batch_graph_workspace_size(const scfft_batch* batch, int32_t steps, size_t* bytes);
+scfft_status scfft_batch_integrate_graph(scfft_batch* batch, double t0_s, double t1_s, int32_t steps,
+                                         void* graph_ws, size_t graph_bytes, void* h_dev,
+                                         int64_t field_stride);
+scfft_status scfft_batch_integrate_wait(scfft_batch* batch, scfft_ode_stats* stats);
+const char* scfft_batch_last_error(const scfft_batch* batch);
 
 /* ---- reverse mode (gradients) ----
  *

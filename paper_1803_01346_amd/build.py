@@ -40,18 +40,16 @@ def _compile(src, extra=(), build_dir=None):
     return obj
 
 
-def build(verbose=False, defines=(), out=None, build_dir=None):
-    """Compile and link.  defines: extra -D options (tuning variants);
-    out / build_dir: alternative library path and object folder."""
-    bdir = build_dir or BUILD
-    lib = out or LIB
+def build(verbose=False):
+    """Compile and link."""
+    bdir = BUILD
+    lib = LIB
     if os.path.isdir(bdir):
         shutil.rmtree(bdir)
     os.makedirs(bdir, exist_ok=True)
-    extra = ["-D" + d for d in defines]
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra, bdir), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, (), bdir), SOURCES))
     tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -264,24 +264,17 @@ __device__ __forceinline__ void wave_sync() {
 // share a lane group (N/E < 16) the row index joins the high bits.  When the
 // N/E threads of a row lie in one wavefront (N/E <= 64, rows aligned to
 // waves) the exchange needs only a wavefront barrier.
-#ifndef SCFFT_ROWS_PAD
-#define SCFFT_ROWS_PAD 0
-#endif
 template <typename T, int N, int E>
 struct LdsRows {
-  static constexpr int STRIDE = SCFFT_ROWS_PAD ? N + N / 16 + 1 : ((N + 1 + 15) / 16) * 16;
+  static constexpr int STRIDE = ((N + 1 + 15) / 16) * 16;
   static constexpr bool ROWMIX = (N / E) < 16;
   static constexpr bool IN_WAVE = (N / E) <= 64;
   C2<T>* base;
   int row;
   __device__ __forceinline__ static int parity(int v) { return __builtin_popcount(v) & 1; }
   __device__ __forceinline__ int swz(int idx) const {
-#if SCFFT_ROWS_PAD
-    return idx + (idx >> 4);
-#else
     const int h = ((idx >> 3) + (ROWMIX ? 2 * row : 0)) & 15;
     return idx ^ (parity(h & 3) | (parity(h & 5) << 1) | (parity(h & 3) << 2));
-#endif
   }
   __device__ __forceinline__ void store(int idx, C2<T> v) { base[row * STRIDE + swz(idx)] = v; }
   __device__ __forceinline__ C2<T> load(int idx) const { return base[row * STRIDE + swz(idx)]; }

@@ -46,6 +46,13 @@ struct Plan {
   Ranges r;
   const int* stop = nullptr;  // device flag: once nonzero, the passes of this plan return at once
   int xalt = 0;  // per-component X passes with the alternate element count per thread
+  int yalt = 0;  // Y passes with the alternate element count per thread
+  int zalt = 0;  // Z passes with the alternate element count per thread
+  // batched launches: `batch` instances of the same grid, instance blockIdx.z;
+  // instance b's spectrum starts zs_main elements after instance b-1's (the
+  // axis tables are shared: equal grids and dimensionless boxes)
+  int batch = 1;
+  int64_t zs_main = 0;
   void full_ranges() {
     r = Ranges{0, nz, 0, ny, 0, ny, 0, nz, 0, ny, 0, nz, 0, ny, 0, nz};
   }
@@ -123,7 +130,54 @@ struct XArgs {
   int warm_used;         // X_ADJ_LAST: the forward call started from a warm start
   double pos0[3];        // coordinate of node 0 along each axis (moment)
   double step[3];        // node spacing (moment)
+  // Batched launches (instance b = blockIdx.z): byte offsets of instance b's
+  // pointers from instance 0's, b times the stride of their class:
+  //   zs_ws   buffers inside the instances' workspaces (chi, kappa, warm,
+  //           warm_out, partials, clamps, mom_partials, zpar)
+  //   zs_in   in, in2;   zs_out   out, j_out;   zs_tab   hedot_tab
+  // zpar (if set): per-instance scalars, [0] n, [1] rho_out, [2 + in2_sel]
+  // the stage coefficient in2_coef (in2_sel >= 0)
+  int64_t zs_ws, zs_in, zs_out, zs_tab;
+  const double* zpar;
+  int in2_sel;
 };
+
+// Instance b's pointer: p shifted by b * stride bytes (null stays null).
+template <typename P>
+__host__ __device__ __forceinline__ P* zshift(P* p, size_t bytes) {
+  return p ? reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(p) + bytes) : p;
+}
+
+// The arguments of instance blockIdx.z of a batched launch (unchanged for a
+// single instance, where blockIdx.z = 0 and zpar is null).
+template <typename T>
+__device__ __forceinline__ XArgs<T> instance_args(const XArgs<T>& A0) {
+  XArgs<T> A = A0;
+  const size_t z = blockIdx.z;
+  if (z) {
+    const size_t w = z * (size_t)A.zs_ws, i = z * (size_t)A.zs_in, o = z * (size_t)A.zs_out;
+    A.chi = zshift(A.chi, w);
+    A.kappa = zshift(A.kappa, w);
+    A.warm = zshift(A.warm, w);
+    A.warm_out = zshift(A.warm_out, w);
+    A.partials = zshift(A.partials, w);
+    A.clamps = zshift(A.clamps, w);
+    A.mom_partials = zshift(A.mom_partials, w);
+    A.kappa_bar = zshift(A.kappa_bar, w);
+    A.in = zshift(A.in, i);
+    A.in2 = zshift(A.in2, i);
+    A.out = zshift(A.out, o);
+    A.j_out = zshift(A.j_out, o);
+    A.hedot_tab = zshift(A.hedot_tab, z * (size_t)A.zs_tab);
+  }
+  if (A.zpar) {
+    const double* q = zshift(A.zpar, z * (size_t)A.zs_ws);
+    A.npow = (T)q[0];
+    A.rho_out = (T)q[1];
+    if (A.in2_sel >= 0) A.in2_coef = (T)q[2 + A.in2_sel];
+  }
+  return A;
+}
 
 // Optional start/stop events attached to a kernel's own dispatch (timing of
 // the kernel body, as a kernel trace reports it); both null = plain launch.
@@ -211,6 +265,24 @@ hipError_t launch_probe(const T* h, int nx, int ny, int nz, const double* pts, i
 template <typename T>
 hipError_t launch_masked_copy(T* dst, const T* src, const uint8_t* chi, size_t nodes,
                               hipStream_t s);
+// Batched integrator kernels (instance b = grid y): buffers of instance b lie
+// b * zs bytes after instance 0's; par_b = par + b * zs bytes holds the
+// instance's step coefficients (par_b[4..6]: stage weights times dt, [7]: dt)
+template <typename T>
+hipError_t launch_combo_batch(T* out, const T* y, const T* k1, const T* k2, const T* k3, const double* par,
+                              size_t n, int count, int64_t zs, hipStream_t s, const int* stop);
+template <typename T>
+hipError_t launch_errnorm_batch(const T* y, const T* y1, const T* k1, const T* k2, const T* k3, const T* k4,
+                                const double* par, double thr, size_t n, double* partials, int nblocks,
+                                int count, int64_t zs, hipStream_t s, const int* stop);
+hipError_t launch_max_partials_batch(const double* partials, int n, double* out, int count, int64_t zs,
+                                     hipStream_t s, const int* stop);
+// instance b (b < count) copies n values from src + b szs bytes to dst + b dzs bytes
+template <typename T>
+hipError_t launch_strided_copy(T* dst, int64_t dzs, const T* src, int64_t szs, size_t n, int count,
+                               hipStream_t s);
+hipError_t launch_batch_step_end(const double* err, int64_t zs, int count, int steps, GraphState* g,
+                                 double* hist, hipStream_t s);
 // the tables of one axis (AxisTab layout) computed on the device, in FP64
 template <typename T>
 hipError_t launch_axis_table(C2<T>* tw, T* kodd, T* kk, T* sm, int n, double L, double sigma,

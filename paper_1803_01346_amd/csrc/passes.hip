@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "tuning.h"
 
 namespace scfft {
 
@@ -34,74 +35,23 @@ static void launch(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime t, Args
     hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
 
-// Elements per thread of each pass kind (register footprint vs. number of
-// LDS exchanges); the FP64 X and Z passes hold three components at once.
-#ifndef SCFFT_EX_F64
-#define SCFFT_EX_F64 4
-#endif
-#ifndef SCFFT_EX_F32
-#define SCFFT_EX_F32 4
-#endif
-#ifndef SCFFT_EY_F64
-#define SCFFT_EY_F64 8
-#endif
-#ifndef SCFFT_EY_F32
-#define SCFFT_EY_F32 8
-#endif
-#ifndef SCFFT_EZ_F64
-#define SCFFT_EZ_F64 4
-#endif
-#ifndef SCFFT_EZ_F32
-#define SCFFT_EZ_F32 8
-#endif
-#ifndef SCFFT_EX1_F64
-#define SCFFT_EX1_F64 8
-#endif
-#ifndef SCFFT_EX1_F32
-#define SCFFT_EX1_F32 8
-#endif
-// X passes: NC = 3 components per thread, or 1 (fewer registers: longer lines).
-// In FP64 the per-component masks and exterior updates run shorter lines
-// (more rows per block) than the other per-component steps: measured faster.
-#ifndef SCFFT_EX1U_F64
-#define SCFFT_EX1U_F64 4
-#endif
+// Elements per thread of each pass kind (tuning.h); the FP64 per-component
+// masks and updates run shorter lines than the other per-component steps.
 template <typename T, int NC = 3, int OP = -1>
 constexpr int ex_max() {
   if (NC == 1 && sizeof(T) == 8 && (OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MASK))
-    return SCFFT_EX1U_F64;
-  return NC == 1 ? (sizeof(T) == 8 ? SCFFT_EX1_F64 : SCFFT_EX1_F32)
-                 : (sizeof(T) == 8 ? SCFFT_EX_F64 : SCFFT_EX_F32);
+    return tune::kEx1UpdF64;
+  return NC == 1 ? (sizeof(T) == 8 ? tune::kEx1F64 : tune::kEx1F32)
+                 : (sizeof(T) == 8 ? tune::kEx3F64 : tune::kEx3F32);
 }
 template <typename T>
-constexpr int ey_max() { return sizeof(T) == 8 ? SCFFT_EY_F64 : SCFFT_EY_F32; }
+constexpr int ey_max() { return sizeof(T) == 8 ? tune::kEyF64 : tune::kEyF32; }
 template <typename T>
-constexpr int ez_max() { return sizeof(T) == 8 ? SCFFT_EZ_F64 : SCFFT_EZ_F32; }
+constexpr int ez_max() { return sizeof(T) == 8 ? tune::kEzF64 : tune::kEzF32; }
 
-// Column passes exchange through two alternating LDS buffers (one barrier
-// per exchange) where that does not cost occupancy: the Z pass (three
-// transforms per column, 4 elements per thread in FP64); the Y pass keeps a
-// single buffer (its 8-element FP64 tile would double to 64 KB).
-#ifndef SCFFT_PP_Y
-#define SCFFT_PP_Y 0
-#endif
-#ifndef SCFFT_PP_Z
-#define SCFFT_PP_Z 1
-#endif
 // Threads per block of a column pass: 256, doubled while the columns of one
-// block span fewer than 128 contiguous bytes of a row (FP32 at N = 256).
-#ifndef SCFFT_COL_BYTES
-#define SCFFT_COL_BYTES 128
-#endif
-// The Z pass widens only in FP64: its FP32 block of 512 threads would hold
-// 143 VGPRs per lane and leave one block per CU (measured slower at 256^3).
-#ifndef SCFFT_COL_BYTES_Z_F32
-#define SCFFT_COL_BYTES_Z_F32 64
-#endif
-#ifndef SCFFT_COL_BYTES_Z_F64
-#define SCFFT_COL_BYTES_Z_F64 SCFFT_COL_BYTES
-#endif
-template <typename T, int N, int EMAX, int BYTES = SCFFT_COL_BYTES>
+// block span fewer than BYTES contiguous bytes of a row.
+template <typename T, int N, int EMAX, int BYTES = tune::kColBytes>
 constexpr int col_block() {
   const int tpt = N / elems_per_thread(N, EMAX);
   int b = kBlock;
@@ -144,15 +94,18 @@ __device__ __forceinline__ C2<T> dc_join(C2<T> S, C2<T> R, bool low) {
 // ---------------------------------------------------------------------------
 // Y pass
 // ---------------------------------------------------------------------------
-template <typename T, int NY, bool INV>
-__global__ __launch_bounds__((col_block<T, NY, ey_max<T>()>())) void ypass_kernel(C2<T>* __restrict__ main, int M, int nz,
-                                                       Ranges R, const C2<T>* __restrict__ tw,
-                                                       const int* __restrict__ stop) {
+// EV: elements-per-thread bound (0: ey_max; the alternate is a rhs option)
+template <typename T, int NY, bool INV, int EV = 0>
+__global__ __launch_bounds__((col_block<T, NY, EV ? EV : ey_max<T>()>())) void ypass_kernel(
+    C2<T>* __restrict__ main, int M, int nz, Ranges R, const C2<T>* __restrict__ tw,
+    const int* __restrict__ stop, int64_t zs) {
   if (stop && *stop) return;  // uniform: the iteration has stopped
-  constexpr int E = elems_per_thread(NY, ey_max<T>());
+  main += blockIdx.z * zs;    // instance of a batched launch
+  constexpr int EM = EV ? EV : ey_max<T>();
+  constexpr int E = elems_per_thread(NY, EM);
   constexpr int TPT = NY / E;
-  constexpr int COLS = col_block<T, NY, ey_max<T>()>() / TPT;
-  __shared__ C2<T> smem[(SCFFT_PP_Y ? 2 : 1) * NY * COLS];
+  constexpr int COLS = col_block<T, NY, EM>() / TPT;
+  __shared__ C2<T> smem[(tune::kPingPongY ? 2 : 1) * NY * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -173,7 +126,7 @@ __global__ __launch_bounds__((col_block<T, NY, ey_max<T>()>())) void ypass_kerne
     const int y = j + m * TPT;
     v[m] = (valid && y >= R.ylo_in && y < R.yhi_in) ? p[(size_t)y * es] : C2<T>{T(0), T(0)};
   }
-  ColLds<SCFFT_PP_Y, T, NY, COLS> lds{smem, col};
+  ColLds<tune::kPingPongY, T, NY, COLS> lds{smem, col};
   if constexpr (INV) {
     if (dc_block) {  // rebuild P(ky) of the kx = 0 column from its half-complex layout
 #pragma unroll
@@ -243,17 +196,24 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
   d = {-cz.y * f, cz.x * f};
 }
 
-// FP64: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per CU, so
-// the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on 256 CUs
-template <typename T, int NZ, int SYM>
-__global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>()), sizeof(T) == 8 ? 4 : 1) void zpass_kernel(
+// FP64 default: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per
+// CU, so the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on
+// 256 CUs.  EV: elements-per-thread bound (0: ez_max; the alternate, a rhs
+// option, takes the registers it needs).
+template <typename T, int NZ, int EV>
+constexpr int z_block() {
+  return col_block<T, NZ, EV ? EV : ez_max<T>(), (sizeof(T) == 8 ? tune::kColBytesZF64 : tune::kColBytesZF32)>();
+}
+template <typename T, int NZ, int SYM, int EV = 0>
+__global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0) ? 4 : 1) void zpass_kernel(
     C2<T>* __restrict__ main, int ny, int M, AxisTab<T> tx, AxisTab<T> ty, AxisTab<T> tz, T coef,
-    Ranges R, const int* __restrict__ stop) {
+    Ranges R, const int* __restrict__ stop, int64_t zs) {
   if (stop && *stop) return;  // uniform: the iteration has stopped
-  constexpr int E = elems_per_thread(NZ, ez_max<T>());
+  main += blockIdx.z * zs;    // instance of a batched launch
+  constexpr int E = elems_per_thread(NZ, EV ? EV : ez_max<T>());
   constexpr int TPT = NZ / E;
-  constexpr int COLS = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>() / TPT;
-  __shared__ C2<T> smem[(SCFFT_PP_Z ? 2 : 1) * NZ * COLS];
+  constexpr int COLS = z_block<T, NZ, EV>() / TPT;
+  __shared__ C2<T> smem[(tune::kPingPongZ ? 2 : 1) * NZ * COLS];
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -283,7 +243,7 @@ __global__ __launch_bounds__((col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SC
       v[c][m] = (valid && z >= R.zlo && z < R.zhi) ? p[c * cs + (size_t)z * es]
                                                    : C2<T>{T(0), T(0)};
     }
-  ColLds<SCFFT_PP_Z, T, NZ, COLS> lds{smem, col};
+  ColLds<tune::kPingPongZ, T, NZ, COLS> lds{smem, col};
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
 
@@ -429,8 +389,11 @@ __device__ __forceinline__ void power_law_aniso(T& a, T& b, T& c, T wx, T wy, T 
 // EV: elements-per-thread bound of the row transform (0: the default of the
 // op, ex_max); the schedule autotuner may pick the alternate one.
 template <typename T, int NX, int OP, int NC, int EV = 0>
-__global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
-  if (P.stop && *P.stop) return;  // uniform: the iteration has stopped
+__global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P0, XArgs<T> A0) {
+  if (P0.stop && *P0.stop) return;  // uniform: the iteration has stopped
+  Plan<T> P = P0;
+  P.main += blockIdx.z * P0.zs_main;        // instance of a batched launch
+  const XArgs<T> A = instance_args(A0);
   static_assert(NC == 3 || NC == 1, "components per block");
   static_assert(NC == 3 || (OP != X_LAW && OP != X_MOMENT && OP != X_ADJ_LAST && OP != X_ADJ_LAW),
                 "needs all components");
@@ -471,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P, XArgs<T> A) {
   unsigned clamps = 0;
   T hdv[NC];  // applied-field rate of the exterior update
 #pragma unroll
-  for (int cc = 0; cc < NC; ++cc) hdv[cc] = A.hedot[c0 + cc];
+  for (int cc = 0; cc < NC; ++cc) hdv[cc] = A0.hedot[c0 + cc];  // kernel argument: indexed in place
   if constexpr (OP == X_UPDATE || OP == X_UPDATE_LAST) {
     if (A.hedot_tab) {
       const double* q = A.hedot_tab + 9 * (size_t)(*A.hedot_step) + 3 * A.hedot_stage;
@@ -926,7 +889,7 @@ template <typename T, int NX, int OP, int NC, int EV = 0>
 static void xlaunch_ev(const Plan<T>& p, const XArgs<T>& a, hipStream_t s, KTime t) {
   const int nb = xblocks_n<T, NX, NC, OP, EV>(p);
   if (nb <= 0) return;  // empty row range
-  launch(xpass_kernel<T, NX, OP, NC, EV>, dim3(nb, NC == 3 ? 1 : 3), dim3(kBlock), s, t, p, a);
+  launch(xpass_kernel<T, NX, OP, NC, EV>, dim3(nb, NC == 3 ? 1 : 3, p.batch), dim3(kBlock), s, t, p, a);
 }
 
 template <typename T, int NX, int OP, int NC>
@@ -1003,20 +966,29 @@ hipError_t launch_xpass(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t
   return hipErrorInvalidValue;
 }
 
-template <typename T, int NY>
-static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
-  constexpr int BLOCK = col_block<T, NY, ey_max<T>()>();
-  constexpr int COLS = BLOCK / tpt_of<NY, ey_max<T>()>();
+template <typename T>
+constexpr int ey_alt() { return ey_max<T>() >= 8 ? 4 : 8; }
+
+template <typename T, int NY, int EV>
+static hipError_t ylaunch_ev(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
+  constexpr int EM = EV ? EV : ey_max<T>();
+  constexpr int BLOCK = col_block<T, NY, EM>();
+  constexpr int COLS = BLOCK / tpt_of<NY, EM>();
   const int M = p.nx / 2;
   const int nzr = p.r.zhi - p.r.zlo;
   if (nzr <= 0) return hipSuccess;  // nothing to transform
   const int ncm = 3 * nzr * M;
-  const dim3 grid((ncm + COLS - 1) / COLS), block(BLOCK);
+  const dim3 grid((ncm + COLS - 1) / COLS, 1, p.batch), block(BLOCK);
   if (inv)
-    launch(ypass_kernel<T, NY, true>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop);
+    launch(ypass_kernel<T, NY, true, EV>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop, p.zs_main);
   else
-    launch(ypass_kernel<T, NY, false>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop);
+    launch(ypass_kernel<T, NY, false, EV>, grid, block, s, t, p.main, M, p.nz, p.r, p.ay.tw, p.stop, p.zs_main);
   return hipGetLastError();
+}
+
+template <typename T, int NY>
+static hipError_t ylaunch_n(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
+  return p.yalt ? ylaunch_ev<T, NY, ey_alt<T>()>(p, inv, s, t) : ylaunch_ev<T, NY, 0>(p, inv, s, t);
 }
 
 template <typename T>
@@ -1037,28 +1009,36 @@ hipError_t launch_ypass(const Plan<T>& p, bool inv, hipStream_t s, KTime t) {
   return hipErrorInvalidValue;
 }
 
-template <typename T, int NZ>
-static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
-  constexpr int BLOCK = col_block<T, NZ, ez_max<T>(), (sizeof(T) == 8 ? SCFFT_COL_BYTES_Z_F64 : SCFFT_COL_BYTES_Z_F32)>();
-  constexpr int COLS = BLOCK / tpt_of<NZ, ez_max<T>()>();
+template <typename T>
+constexpr int ez_alt() { return ez_max<T>() >= 8 ? 4 : 8; }
+
+template <typename T, int NZ, int EV>
+static hipError_t zlaunch_ev(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
+  constexpr int BLOCK = z_block<T, NZ, EV>();
+  constexpr int COLS = BLOCK / tpt_of<NZ, EV ? EV : ez_max<T>()>();
   const int M = p.nx / 2;
-  const dim3 grid((p.ny * M + COLS - 1) / COLS), block(BLOCK);
+  const dim3 grid((p.ny * M + COLS - 1) / COLS, 1, p.batch), block(BLOCK);
   switch (sym) {
     case Z_CURL:
-      launch(zpass_kernel<T, NZ, Z_CURL>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
-             p.r, p.stop);
+      launch(zpass_kernel<T, NZ, Z_CURL, EV>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
+             p.r, p.stop, p.zs_main);
       break;
     case Z_PHI:
-      launch(zpass_kernel<T, NZ, Z_PHI>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
-             p.r, p.stop);
+      launch(zpass_kernel<T, NZ, Z_PHI, EV>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay, p.az, coef,
+             p.r, p.stop, p.zs_main);
       break;
     case Z_PHI_SMOOTH:
-      launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay,
-             p.az, coef, p.r, p.stop);
+      launch(zpass_kernel<T, NZ, Z_PHI_SMOOTH, EV>, grid, block, s, t, p.main, p.ny, M, p.ax, p.ay,
+             p.az, coef, p.r, p.stop, p.zs_main);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int NZ>
+static hipError_t zlaunch_n(const Plan<T>& p, int sym, T coef, hipStream_t s, KTime t) {
+  return p.zalt ? zlaunch_ev<T, NZ, ez_alt<T>()>(p, sym, coef, s, t) : zlaunch_ev<T, NZ, 0>(p, sym, coef, s, t);
 }
 
 template <typename T>

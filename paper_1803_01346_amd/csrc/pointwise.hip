@@ -182,9 +182,11 @@ hipError_t launch_iter_decide(const double* partials, int n, double n_out, doubl
 
 __global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restrict__ p, int n,
                                                            double* __restrict__ out,
-                                                           const int* __restrict__ stop) {
+                                                           const int* __restrict__ stop, int64_t zs) {
   __shared__ double sh[kRB];
   if (stop && *stop) return;  // uniform
+  p = zshift(p, blockIdx.y * (size_t)zs);      // instance of a batched launch
+  out = zshift(out, blockIdx.y * (size_t)zs);
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += kRB) acc = fmax(acc, p[i]);
   const double r = block_max(acc, sh);
@@ -193,7 +195,39 @@ __global__ __launch_bounds__(kRB) void max_partials_kernel(const double* __restr
 
 hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t s,
                                const int* stop) {
-  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, out, stop);
+  hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(kRB), 0, s, partials, n, out, stop, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_partials_batch(const double* partials, int n, double* out, int count, int64_t zs,
+                                     hipStream_t s, const int* stop) {
+  hipLaunchKernelGGL(max_partials_kernel, dim3(1, count), dim3(kRB), 0, s, partials, n, out, stop, zs);
+  return hipGetLastError();
+}
+
+// Batched graph replay: instance b's error norm (err + b zs bytes) into
+// hist[b * steps + step]; a non-finite one stops every instance; else the
+// shared step counter advances.
+__global__ void batch_step_end_kernel(const double* __restrict__ err, int64_t zs, int count, int steps,
+                                      GraphState* g, double* __restrict__ hist) {
+  if (threadIdx.x != 0 || g->stop) return;
+  bool bad = false;
+  for (int b = 0; b < count; ++b) {
+    const double e = *zshift(err, b * (size_t)zs);
+    hist[(size_t)b * steps + g->step] = e;
+    if (!isfinite(e)) bad = true;
+  }
+  if (bad) {
+    g->stop = 1;
+    g->bad = g->step;
+  } else {
+    g->step += 1;
+  }
+}
+
+hipError_t launch_batch_step_end(const double* err, int64_t zs, int count, int steps, GraphState* g,
+                                 double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(batch_step_end_kernel, dim3(1), dim3(64), 0, s, err, zs, count, steps, g, hist);
   return hipGetLastError();
 }
 
@@ -217,13 +251,31 @@ hipError_t launch_fill_uniform(T* h, size_t nodes, const double he[3], hipStream
 
 // out = y + c1 k1 + c2 k2 + c3 k3; coefficients in T (FP32 path: the stage
 // combination is bulk arithmetic), terms with a null pointer are skipped.
+// Batched (instance b = blockIdx.y): every buffer of instance b lies zs
+// bytes after instance b-1's, and if par is set the coefficients are
+// par_b[4], par_b[5], par_b[6] (par_b = par + b zs bytes).
 template <typename T>
 __global__ __launch_bounds__(kRB) void combo_kernel(T* __restrict__ out, const T* __restrict__ y,
                                                     const T* __restrict__ k1, T c1,
                                                     const T* __restrict__ k2, T c2,
                                                     const T* __restrict__ k3, T c3, size_t n,
-                                                    const int* __restrict__ stop) {
+                                                    const int* __restrict__ stop, int64_t zs,
+                                                    const double* __restrict__ par) {
   if (stop && *stop) return;  // uniform
+  if (blockIdx.y) {
+    const size_t o = blockIdx.y * (size_t)zs;
+    out = zshift(out, o);
+    y = zshift(y, o);
+    k1 = zshift(k1, o);
+    k2 = zshift(k2, o);
+    k3 = zshift(k3, o);
+  }
+  if (par) {
+    const double* q = zshift(par, blockIdx.y * (size_t)zs);
+    c1 = (T)q[4];
+    c2 = (T)q[5];
+    c3 = (T)q[6];
+  }
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
     T v = y ? y[i] : T(0);
     if (k1) v += c1 * k1[i];
@@ -239,7 +291,17 @@ hipError_t launch_combo(T* out, const T* y, const T* k1, double c1, const T* k2,
   const size_t want = (n + kRB - 1) / kRB;
   const int nb = (int)(want < 8192 ? want : 8192);
   hipLaunchKernelGGL((combo_kernel<T>), dim3(nb), dim3(kRB), 0, s, out, y, k1, (T)c1, k2, (T)c2,
-                     k3, (T)c3, n, stop);
+                     k3, (T)c3, n, stop, (int64_t)0, (const double*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_combo_batch(T* out, const T* y, const T* k1, const T* k2, const T* k3, const double* par,
+                              size_t n, int count, int64_t zs, hipStream_t s, const int* stop) {
+  const size_t want = (n + kRB - 1) / kRB;
+  const int nb = (int)(want < 2048 ? want : 2048);
+  hipLaunchKernelGGL((combo_kernel<T>), dim3(nb, count), dim3(kRB), 0, s, out, y, k1, T(0), k2, T(0),
+                     k3, T(0), n, stop, zs, par);
   return hipGetLastError();
 }
 
@@ -253,9 +315,21 @@ __global__ __launch_bounds__(kRB) void errnorm_kernel(const T* __restrict__ y,
                                                       const T* __restrict__ k4, double dt,
                                                       double thr, size_t n,
                                                       double* __restrict__ partials,
-                                                      const int* __restrict__ stop) {
+                                                      const int* __restrict__ stop, int64_t zs,
+                                                      const double* __restrict__ par) {
   __shared__ double sh[kRB];
   if (stop && *stop) return;  // uniform
+  if (blockIdx.y) {  // instance of a batched launch (see combo_kernel)
+    const size_t o = blockIdx.y * (size_t)zs;
+    y = zshift(y, o);
+    y1 = zshift(y1, o);
+    k1 = zshift(k1, o);
+    k2 = zshift(k2, o);
+    k3 = zshift(k3, o);
+    k4 = zshift(k4, o);
+    partials = zshift(partials, o);
+  }
+  if (par) dt = zshift(par, blockIdx.y * (size_t)zs)[7];
   const double e1 = -5.0 / 72.0, e2 = 1.0 / 12.0, e3 = 1.0 / 9.0, e4 = -1.0 / 8.0;
   double acc = 0.0;
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
@@ -275,7 +349,16 @@ hipError_t launch_errnorm(const T* y, const T* y1, const T* k1, const T* k2, con
                           const T* k4, double dt, double thr, size_t n, double* partials,
                           int nblocks, hipStream_t s, const int* stop) {
   hipLaunchKernelGGL((errnorm_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, y, y1, k1, k2, k3, k4,
-                     dt, thr, n, partials, stop);
+                     dt, thr, n, partials, stop, (int64_t)0, (const double*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_errnorm_batch(const T* y, const T* y1, const T* k1, const T* k2, const T* k3, const T* k4,
+                                const double* par, double thr, size_t n, double* partials, int nblocks,
+                                int count, int64_t zs, hipStream_t s, const int* stop) {
+  hipLaunchKernelGGL((errnorm_kernel<T>), dim3(nblocks, count), dim3(kRB), 0, s, y, y1, k1, k2, k3, k4,
+                     0.0, thr, n, partials, stop, zs, par);
   return hipGetLastError();
 }
 
@@ -430,7 +513,7 @@ __global__ __launch_bounds__(kRB) void count_nonpositive_kernel(const T* __restr
   double bad = 0.0;
   for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) {
     const T x = v[i];
-    if (!(x > T(0) && x <= HUGE_VAL)) bad += 1.0;  // NaN fails both tests
+    if (!(x > T(0)) || !__builtin_isfinite(x)) bad += 1.0;  // NaN fails the first test
   }
   const double b = block_sum(bad, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = b;
@@ -442,6 +525,30 @@ hipError_t launch_count_nonpositive(const T* v, size_t n, double* partials, int 
   hipLaunchKernelGGL((count_nonpositive_kernel<T>), dim3(nblocks), dim3(kRB), 0, s, v, n, partials);
   return hipGetLastError();
 }
+
+// Batched set-up copies: instance b's n values of T go from src + b szs
+// bytes to dst + b dzs bytes (instance b = blockIdx.y).
+template <typename T>
+__global__ __launch_bounds__(kRB) void strided_copy_kernel(T* __restrict__ dst, int64_t dzs,
+                                                           const T* __restrict__ src, int64_t szs,
+                                                           size_t n) {
+  dst = zshift(dst, blockIdx.y * (size_t)dzs);
+  src = zshift(src, blockIdx.y * (size_t)szs);
+  for (size_t i = blockIdx.x * (size_t)kRB + threadIdx.x; i < n; i += (size_t)gridDim.x * kRB) dst[i] = src[i];
+}
+
+template <typename T>
+hipError_t launch_strided_copy(T* dst, int64_t dzs, const T* src, int64_t szs, size_t n, int count,
+                               hipStream_t s) {
+  const size_t want = (n + kRB - 1) / kRB;
+  const int nb = (int)(want < 2048 ? want : 2048);
+  hipLaunchKernelGGL((strided_copy_kernel<T>), dim3(nb, count), dim3(kRB), 0, s, dst, dzs, src, szs, n);
+  return hipGetLastError();
+}
+template hipError_t launch_strided_copy<double>(double*, int64_t, const double*, int64_t, size_t, int,
+                                                hipStream_t);
+template hipError_t launch_strided_copy<float>(float*, int64_t, const float*, int64_t, size_t, int,
+                                               hipStream_t);
 
 // The axis tables of one axis on the device (the layout of AxisTab):
 // tw[i] = exp(-2 pi i / n), kodd[i] = pi m / L (0 at the Nyquist index),
@@ -489,7 +596,12 @@ hipError_t launch_axis_table(C2<T>* tw, T* kodd, T* kk, T* sm, int n, double L, 
   template hipError_t launch_ratio_max<T>(const T*, const T*, double, size_t, double*, int,     \
                                           hipStream_t);                                         \
   template hipError_t launch_count_nonpositive<T>(const T*, size_t, double*, int, hipStream_t); \
-  template hipError_t launch_axis_table<T>(C2<T>*, T*, T*, T*, int, double, double, hipStream_t);
+  template hipError_t launch_axis_table<T>(C2<T>*, T*, T*, T*, int, double, double, hipStream_t); \
+  template hipError_t launch_combo_batch<T>(T*, const T*, const T*, const T*, const T*, const double*, \
+                                            size_t, int, int64_t, hipStream_t, const int*);     \
+  template hipError_t launch_errnorm_batch<T>(const T*, const T*, const T*, const T*, const T*,  \
+                                              const T*, const double*, double, size_t, double*,  \
+                                              int, int, int64_t, hipStream_t, const int*);
 SCFFT_INST(double)
 SCFFT_INST(float)
 #undef SCFFT_INST

@@ -24,6 +24,17 @@ constexpr size_t kAlign = 256;
 constexpr int kMaxDeltaSlots = 256;
 constexpr int kIterChunk = 4;  // adaptive iteration: launches between reads of the stop flag
 constexpr int kProbeChunk = 4096;
+// Per-instance scalars of a batched launch, in each member's workspace (the
+// passes read slot [0..3], the batched integrator [4..7], the applied-field
+// rates of a plain batched call [8..16], a zero step index [17] and the
+// error norm [18]):
+enum BPar : int {
+  BP_N = 0, BP_RHO, BP_C2, BP_C3,      // n, rho_out, stage coefficients dt/2, 3dt/4
+  BP_B1, BP_B2, BP_B3, BP_DT,          // 2dt/9, dt/3, 4dt/9, dt (dimensionless)
+  BP_HEDOT = 8,                        // 3 stages x 3 components
+  BP_ZERO = 17, BP_ERR = 18,
+  kBParDoubles = 32
+};
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -56,7 +67,7 @@ struct scfft_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_main, off_warm, off_chi, off_kappa, off_tab, off_part, off_scal, off_delta,
-      off_clamp, off_mom, off_adj, off_adjs, off_ode, off_probe, total;
+      off_clamp, off_mom, off_adj, off_adjs, off_ode, off_probe, off_bpar, total;
   size_t wsize;  // element size
   bool has_mask = false, has_kappa = false, has_warm = false;
   int64_t n_in = 0, n_out = 0;
@@ -183,6 +194,8 @@ void layout(scfft_ctx* c) {
   c->off_adjs = o;  o = align_up(o + 16 * sizeof(double));
   c->off_ode = o;   o = align_up(o + 7 * 3 * nodes * w);  // 6 BS23 fields + a third state
   c->off_probe = o; o = align_up(o + (size_t)kProbeChunk * 6 * sizeof(double));
+  // per-instance scalars of a batched launch (scfft_batch): see BPar
+  c->off_bpar = o;  o = align_up(o + kBParDoubles * sizeof(double));
   c->total = o;
 }
 
@@ -211,6 +224,8 @@ Plan<T> plan_on(const scfft_ctx* c, char* main, char* tab) {
   p.full_ranges();
   p.stop = c->graph_stop;
   p.xalt = c->opts.x_alt;
+  p.yalt = c->opts.y_alt;
+  p.zalt = c->opts.z_alt;
   return p;
 }
 
@@ -233,10 +248,10 @@ struct BoxPlans {
 };
 
 template <typename T>
-BoxPlans<T> box_plans(const scfft_ctx* c, const Plan<T>& p, bool prune) {
+BoxPlans<T> box_plans_for(const int lo[3], const int hi[3], const Plan<T>& p, bool prune) {
   BoxPlans<T> b{p, p, p, p, p, p, p, p, p};
   if (!prune) return b;
-  const int y0 = c->box_lo[1], y1 = c->box_hi[1], z0 = c->box_lo[2], z1 = c->box_hi[2];
+  const int y0 = lo[1], y1 = hi[1], z0 = lo[2], z1 = hi[2];
   b.z_store.r.zlo_out = z0;
   b.z_store.r.zhi_out = z1;
   b.y_inv.r.zlo = z0;
@@ -264,6 +279,11 @@ BoxPlans<T> box_plans(const scfft_ctx* c, const Plan<T>& p, bool prune) {
   b.xy_hin.r.izlo = z0;
   b.xy_hin.r.izhi = z1;
   return b;
+}
+
+template <typename T>
+BoxPlans<T> box_plans(const scfft_ctx* c, const Plan<T>& p, bool prune) {
+  return box_plans_for<T>(c->box_lo, c->box_hi, p, prune);
 }
 
 // Axis tables in FP64 on the host (Sec. 2: wavenumbers on the box, Gaussian
@@ -380,12 +400,12 @@ template <typename T>
 double bytes_y(const scfft_ctx* c, const Plan<T>& p) {
   const double cw = 2.0 * sizeof(T), kx = p.nx / 2;
   const double planes = 3.0 * (p.r.zhi - p.r.zlo);
-  return planes * kx * cw * ((p.r.yhi_in - p.r.ylo_in) + (p.r.yhi_out - p.r.ylo_out));
+  return p.batch * planes * kx * cw * ((p.r.yhi_in - p.r.ylo_in) + (p.r.yhi_out - p.r.ylo_out));
 }
 template <typename T>
 double bytes_z(const scfft_ctx* c, const Plan<T>& p) {
   const double cw = 2.0 * sizeof(T), col = 3.0 * p.ny * (p.nx / 2);
-  return col * cw * ((p.r.zhi - p.r.zlo) + (p.r.zhi_out - p.r.zlo_out));
+  return p.batch * col * cw * ((p.r.zhi - p.r.zlo) + (p.r.zhi_out - p.r.zlo_out));
 }
 template <typename T>
 double bytes_x(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
@@ -448,7 +468,7 @@ template <typename T>
 hipError_t run_x(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   KTime t;
   const int kind = op < X_ADJ_START ? SCFFT_KERNEL_X_FWD + op : SCFFT_KERNEL_X_ADJ_START + (op - X_ADJ_START);
-  hipError_t e = prof_slot(c, kind, &t, c->prof ? bytes_x<T>(c, p, op, a) : 0.0);
+  hipError_t e = prof_slot(c, kind, &t, c->prof ? p.batch * bytes_x<T>(c, p, op, a) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_xpass<T>(p, op, a, c->stream, t), t);
 }
@@ -474,7 +494,7 @@ hipError_t run_z(scfft_ctx* c, const Plan<T>& p, int sym, double coef) {
 template <typename T>
 hipError_t run_xy(scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a) {
   KTime t;
-  hipError_t e = prof_slot(c, SCFFT_KERNEL_XY_FWD + op, &t, c->prof ? bytes_xy<T>(c, p, op, a) : 0.0);
+  hipError_t e = prof_slot(c, SCFFT_KERNEL_XY_FWD + op, &t, c->prof ? p.batch * bytes_xy<T>(c, p, op, a) : 0.0);
   if (e != hipSuccess) return e;
   return prof_done(c, launch_xypass<T>(p, op, a, c->stream, t), t);
 }
@@ -498,55 +518,71 @@ bool use_xy(const scfft_ctx* c, const Plan<T>& p) {
   return c->opts.fuse_xy >= 2 || (c->opts.fuse_xy == 1 && p.nx <= 64);
 }
 
-// Fixed iteration count with fused xy-plane passes: the per-component steps
-// (warm start, masks, exterior update) each take one pass over the spectrum
-// instead of three; only the power law, which needs |j| over the three
-// components, keeps the Y inverse / X / Y forward sequence.
+// The passes of one right-hand side with a fixed iteration count (Sec. 2:
+// Eqs. 4, 1, 3, then iteration (5) fixed_iter times), for one context or a
+// batch of same-size instances (plan and arguments batched; lo/hi: the box
+// that holds Omega of every instance).  With fused xy-plane passes the
+// per-component steps (warm start, masks, exterior update) each take one pass
+// over the spectrum instead of three; the power law, which needs |j| over the
+// three components, keeps the Y inverse / X / Y forward sequence.
 template <typename T>
-scfft_status rhs_fused(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, const T* h, T* hdot,
-                       scfft_rhs_stats* stats) {
+scfft_status rhs_fixed_passes(scfft_ctx* c, const Plan<T>& p, XArgs<T> a, bool warm_start, T* warm,
+                              const int lo[3], const int hi[3], const T* h, T* hdot) {
   const double norm = 1.0 / ((double)c->n[0] * c->n[1] * c->n[2]);
   const int phi_sym = c->opts.smooth_phi ? Z_PHI_SMOOTH : Z_PHI;
   const int fixed = c->opts.fixed_iter;
-  T* warm = wsp<T>(c, c->off_warm);
-  const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
-  const bool warm_start = c->has_warm;
+  const BoxPlans<T> b = box_plans_for<T>(lo, hi, p, c->opts.prune_box != 0);
   a.in = h;
   a.out = hdot;
   a.track = 0;
-  HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));                     // F(h) in x, y
-  HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));                   // j = C_s h (Eq. 4)
-  HIPCHK(c, run_y<T>(c, p, true));
-  HIPCHK(c, run_x<T>(c, p, X_LAW, a));                       // e (Eq. 1)
+  if (use_xy<T>(c, p)) {
+    HIPCHK(c, run_xy<T>(c, p, XY_FWD, a));                     // F(h) in x, y
+    HIPCHK(c, run_z<T>(c, p, Z_CURL, norm));                   // j = C_s h (Eq. 4)
+    HIPCHK(c, run_y<T>(c, p, true));
+    HIPCHK(c, run_x<T>(c, p, X_LAW, a));                       // e (Eq. 1)
+    HIPCHK(c, run_y<T>(c, p, false));
+    // -C_s e (Eq. 3); with a warm start it is needed on Omega only
+    HIPCHK(c, run_z<T>(c, warm_start ? b.z_store : p, Z_CURL, -norm));
+    a.warm = warm_start ? warm : nullptr;
+    HIPCHK(c, run_xy<T>(c, warm_start ? b.xy_hin : p, XY_HIN, a));  // hdot^0
+    for (int it = 0; it < fixed; ++it) {                       // iteration (5)
+      HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));         // jdot^i (needed on Omega)
+      HIPCHK(c, run_xy<T>(c, b.xy_box, XY_MASK, a));           // jdot_in^i
+      HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));         // Phi[jdot_in^i] (Eq. 7)
+      const bool last = it + 1 == fixed;
+      a.warm_out = last ? warm : nullptr;
+      HIPCHK(c, run_xy<T>(c, p, last ? XY_UPDATE_LAST : XY_UPDATE, a));
+    }
+    return SCFFT_OK;
+  }
+  // j = C_s h  (Eq. 4)
+  HIPCHK(c, run_x<T>(c, p, X_FWD, a));
+  HIPCHK(c, spectral_middle<T>(c, p, Z_CURL, norm));
+  // e (Eq. 1; rho_out j outside), then -C_s e (Eq. 3); with a warm start it
+  // is needed on Omega only
+  HIPCHK(c, run_x<T>(c, p, X_LAW, a));
   HIPCHK(c, run_y<T>(c, p, false));
-  // -C_s e (Eq. 3); with a warm start it is needed on Omega only
   HIPCHK(c, run_z<T>(c, warm_start ? b.z_store : p, Z_CURL, -norm));
+  HIPCHK(c, run_y<T>(c, warm_start ? b.y_inv : p, true));
+  // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out
   a.warm = warm_start ? warm : nullptr;
-  HIPCHK(c, run_xy<T>(c, warm_start ? b.xy_hin : p, XY_HIN, a));  // hdot^0
-  for (int it = 0; it < fixed; ++it) {                       // iteration (5)
-    HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));         // jdot^i (needed on Omega)
-    HIPCHK(c, run_xy<T>(c, b.xy_box, XY_MASK, a));           // jdot_in^i
-    HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));         // Phi[jdot_in^i] (Eq. 7)
+  HIPCHK(c, run_x<T>(c, warm_start ? b.x_hin : p, X_HIN, a));
+  for (int it = 0; it < fixed; ++it) {  // iteration (5)
     const bool last = it + 1 == fixed;
+    // jdot^i = C_s hdot^i (needed on Omega only), jdot_in^i, then Phi[jdot_in^i]
+    // (Eq. 7) of a field that vanishes outside the box, update (Eq. 5); the
+    // last update also stores the next warm start
     a.warm_out = last ? warm : nullptr;
-    HIPCHK(c, run_xy<T>(c, p, last ? XY_UPDATE_LAST : XY_UPDATE, a));
+    HIPCHK(c, run_y<T>(c, p, false));
+    HIPCHK(c, run_z<T>(c, b.z_store, Z_CURL, norm));
+    HIPCHK(c, run_y<T>(c, b.y_inv, true));
+    HIPCHK(c, run_x<T>(c, b.x_box, X_MASK, a));
+    HIPCHK(c, run_y<T>(c, b.y_fwd, false));
+    HIPCHK(c, run_z<T>(c, b.z_load, phi_sym, norm));
+    HIPCHK(c, run_y<T>(c, p, true));
+    HIPCHK(c, run_x<T>(c, p, last ? X_UPDATE_LAST : X_UPDATE, a));
   }
-  c->has_warm = true;
-  scfft_status st = SCFFT_OK;
-  if (stats) {
-    unsigned long long cl = 0;
-    HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
-                             hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
-    c->clamp_seen = (int64_t)cl;
-    stats->iters = fixed;
-    stats->converged = 1;
-    stats->last_delta = -1.0;
-    stats->clamps = new_clamps;
-    if (new_clamps > 0) st = SCFFT_WARN_CLAMPED;
-  }
-  return st;
+  return SCFFT_OK;
 }
 
 template <typename T>
@@ -573,7 +609,28 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   a.mom_partials = mom;
   a.j_out = j_out;
 
-  if (c->opts.fixed_iter > 0 && use_xy<T>(c, p)) return rhs_fused<T>(c, p, a, h, hdot, stats);
+  const int fixed = c->opts.fixed_iter;
+  if (fixed > 0) {
+    const scfft_status fs = rhs_fixed_passes<T>(c, p, a, c->has_warm, wsp<T>(c, c->off_warm), c->box_lo,
+                                                c->box_hi, h, hdot);
+    if (fs < 0) return fs;
+    c->has_warm = true;
+    scfft_status st = SCFFT_OK;
+    if (stats) {
+      unsigned long long cl = 0;
+      HIPCHK(c, hipMemcpyAsync(&cl, wsp<unsigned long long>(c, c->off_clamp), sizeof cl,
+                               hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      const int64_t new_clamps = (int64_t)cl - c->clamp_seen;
+      c->clamp_seen = (int64_t)cl;
+      stats->iters = fixed;
+      stats->converged = 1;
+      stats->last_delta = -1.0;
+      stats->clamps = new_clamps;
+      if (new_clamps > 0) st = SCFFT_WARN_CLAMPED;
+    }
+    return st;
+  }
   const BoxPlans<T> b = box_plans<T>(c, p, c->opts.prune_box != 0);
   const bool warm_start = c->has_warm;
 
@@ -587,14 +644,14 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   HIPCHK(c, run_y<T>(c, p, false));
   HIPCHK(c, run_z<T>(c, warm_start ? b.z_store : p, Z_CURL, -norm));
   HIPCHK(c, run_y<T>(c, warm_start ? b.y_inv : p, true));
-  // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out
-  const int fixed = c->opts.fixed_iter;
+  // hdot^0: -curl e on Omega, warm start (or Ohm's law) on Omega_out; every
+  // iterate is kept in hdot (the stopping rule compares consecutive ones)
   a.out = hdot;
   a.warm = c->has_warm ? wsp<T>(c, c->off_warm) : nullptr;
-  a.track = fixed > 0 ? 0 : 1;
+  a.track = 1;
   HIPCHK(c, run_x<T>(c, warm_start ? b.x_hin : p, X_HIN, a));
 
-  // iteration (5)
+  // iteration (5) with the stopping rule
   unsigned long long clamps_now = 0;
   int it = 0;
   bool converged = false;
@@ -612,15 +669,7 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
     if ((e = run_y<T>(c, pp, true)) != hipSuccess) return e;
     return run_x<T>(c, pp, op, a);
   };
-  if (fixed > 0) {
-    for (it = 0; it < fixed; ++it) {
-      const bool lastit = it + 1 == fixed;
-      // the last update also stores the next warm start
-      a.warm_out = lastit ? wsp<T>(c, c->off_warm) : nullptr;
-      HIPCHK(c, iteration(p, b, lastit ? X_UPDATE_LAST : X_UPDATE));
-    }
-    converged = true;
-  } else {
+  {
     // Stopping rule on the device: after each update a one-block kernel sums
     // |delta| and sets a stop flag that makes every later pass of the loop
     // return at once.  The host first launches as many iterations as the
@@ -686,23 +735,16 @@ scfft_status rhs_impl(scfft_ctx* c, double t, const T* h, T* hdot, scfft_rhs_sta
   c->has_warm = true;
 
   scfft_status st = converged ? SCFFT_OK : SCFFT_WARN_NOT_CONVERGED;
-  if (stats || fixed <= 0) {
-    if (fixed > 0) {  // the adaptive loop read the clamp counter with its last flag
-      HIPCHK(c, hipMemcpyAsync(&clamps_now, wsp<unsigned long long>(c, c->off_clamp), sizeof clamps_now,
-                               hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      last = -1.0;  // not tracked with a fixed iteration count
-    }
-    const int64_t new_clamps = (int64_t)clamps_now - c->clamp_seen;
-    c->clamp_seen = (int64_t)clamps_now;
-    if (stats) {
-      stats->iters = it;
-      stats->converged = converged ? 1 : 0;
-      stats->last_delta = last;
-      stats->clamps = new_clamps;
-    }
-    if (st == SCFFT_OK && new_clamps > 0) st = SCFFT_WARN_CLAMPED;
+  // the adaptive loop read the clamp counter with its last flag
+  const int64_t new_clamps = (int64_t)clamps_now - c->clamp_seen;
+  c->clamp_seen = (int64_t)clamps_now;
+  if (stats) {
+    stats->iters = it;
+    stats->converged = converged ? 1 : 0;
+    stats->last_delta = last;
+    stats->clamps = new_clamps;
   }
+  if (st == SCFFT_OK && new_clamps > 0) st = SCFFT_WARN_CLAMPED;
   return st;
 }
 
@@ -1596,11 +1638,20 @@ scfft_status graph_wait_impl(scfft_ctx* c, scfft_ode_stats* stats) {
 template <typename T>
 scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, double* ms_best) {
   const Plan<T> p = make_plan<T>(c);
-  // (fuse_xy, x_alt): row/column passes with either element count of the
-  // per-component x passes, and the fused plane pass where it fits (which
-  // has no per-component x pass to vary)
-  std::vector<std::pair<int, int>> cand = {{0, 0}, {0, 1}};
-  if (xypass_supported<T>(p)) cand.push_back({2, 0});
+  // (fuse_xy, x_alt, y_alt, z_alt): row/column passes with either element
+  // count of the per-component x passes, and the fused plane pass where it
+  // fits (which has no per-component x pass to vary), each with either
+  // element count of the y and z passes
+  struct Cand {
+    int fuse, x, y, z;
+  };
+  std::vector<Cand> cand;
+  for (int y = 0; y < 2; ++y)
+    for (int z = 0; z < 2; ++z) {
+      cand.push_back({0, 0, y, z});
+      cand.push_back({0, 1, y, z});
+      if (xypass_supported<T>(p)) cand.push_back({2, 0, y, z});
+    }
   const size_t fb = 3 * c->nodes * sizeof(T);
   T* out = wsp<T>(c, c->off_ode + 4 * fb);
   T* saved = wsp<T>(c, c->off_ode + 5 * fb);
@@ -1618,13 +1669,15 @@ scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, dou
     (void)hipEventDestroy(e0);
     return fail(c, SCFFT_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(he));
   }
-  const int keep = c->opts.fuse_xy, keep_alt = c->opts.x_alt;
+  const scfft_rhs_opts keep = c->opts;
   scfft_status st = SCFFT_OK;
   double best = INFINITY;
-  int pick = keep, pick_alt = keep_alt;
+  Cand pick{keep.fuse_xy, keep.x_alt, keep.y_alt, keep.z_alt};
   for (const auto& fa : cand) {
-    c->opts.fuse_xy = fa.first;
-    c->opts.x_alt = fa.second;
+    c->opts.fuse_xy = fa.fuse;
+    c->opts.x_alt = fa.x;
+    c->opts.y_alt = fa.y;
+    c->opts.z_alt = fa.z;
     if ((he = restore()) != hipSuccess) break;
     if ((st = rhs_impl<T>(c, 0.0, h, out, nullptr)) < 0) break;          // warm-up
     if ((he = hipEventRecord(e0, c->stream)) != hipSuccess) break;
@@ -1636,22 +1689,22 @@ scfft_status autotune_impl(scfft_ctx* c, const T* h, int calls, int* choice, dou
     if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
     if (ms / calls < best) {
       best = ms / calls;
-      pick = fa.first;
-      pick_alt = fa.second;
+      pick = fa;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->opts.fuse_xy = keep;
-  c->opts.x_alt = keep_alt;
+  c->opts = keep;
   if (st < 0) return st;
   if (he != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "autotune: %s", hipGetErrorString(he));
   HIPCHK(c, restore());
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->opts.fuse_xy = pick;
-  c->opts.x_alt = pick_alt;
+  c->opts.fuse_xy = pick.fuse;
+  c->opts.x_alt = pick.x;
+  c->opts.y_alt = pick.y;
+  c->opts.z_alt = pick.z;
   ++c->epoch;
-  if (choice) *choice = pick;
+  if (choice) *choice = pick.fuse;
   if (ms_best) *ms_best = best;
   return SCFFT_OK;
 }
@@ -1766,6 +1819,332 @@ const uint64_t kStateMagic = 0x5343464654535431ull;  // "SCFFTST1"
 }  // namespace
 
 // ===========================================================================
+// batches of same-size instances
+// ===========================================================================
+// A batch advances several contexts of one grid together: every pass is one
+// launch over all of them (instance = blockIdx.z), so small boxes fill the
+// chip.  The members' workspaces lie at a constant stride in one allocation,
+// so instance b's buffers are instance 0's shifted by b strides; the
+// per-instance scalars (n, rho_out, stage coefficients, applied-field rates)
+// sit in each member's BPar slot, uploaded from pinned host rows.
+constexpr int kBatchRing = 4;       // pinned row sets in flight (plain batched calls)
+constexpr int kMaxBatch = 512;      // members per batch (their BPar rows fit the probe area)
+
+struct scfft_batch {
+  std::vector<scfft_ctx*> m;
+  size_t stride = 0;                          // bytes from one member's workspace to the next
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // box holding Omega of every member
+  double* pin = nullptr;                      // kBatchRing sets of BPar rows, one row per member
+  hipEvent_t ev[kBatchRing] = {};
+  bool ev_live[kBatchRing] = {};
+  int ring = 0;
+  // graph-replayed fixed steps
+  bool busy = false;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  char* gws = nullptr;
+  int steps = 0;
+  double t0_s = 0.0, t1_s = 0.0;
+  void* h = nullptr;
+  int64_t fstride = 0;
+  std::vector<double> tab;                    // host rate tables (alive until the wait)
+};
+
+namespace {
+
+struct BatchGraphLayout {
+  size_t off_state = 0, off_hist = 0, off_tab = 0, total = 0;
+};
+
+// graph workspace of a batch: replay state, error norms [member][step], rate
+// tables [member][step][stage][component]
+BatchGraphLayout batch_graph_layout(int count, int steps) {
+  BatchGraphLayout L;
+  size_t o = 0;
+  L.off_state = o;  o = align_up(o + sizeof(GraphState));
+  L.off_hist = o;   o = align_up(o + (size_t)count * steps * sizeof(double));
+  L.off_tab = o;    o = align_up(o + (size_t)count * steps * 9 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+// The next set of pinned rows (waits until its last upload has been read),
+// filled with each member's n and rho_out.
+scfft_status batch_rows(scfft_batch* B, double** rows) {
+  scfft_ctx* c = B->m[0];
+  const int k = B->ring;
+  if (B->ev_live[k]) HIPCHK(c, hipEventSynchronize(B->ev[k]));
+  double* r = B->pin + (size_t)k * B->m.size() * kBParDoubles;
+  std::memset(r, 0, B->m.size() * kBParDoubles * sizeof(double));
+  for (size_t b = 0; b < B->m.size(); ++b) {
+    r[b * kBParDoubles + BP_N] = B->m[b]->mat.n_power;
+    r[b * kBParDoubles + BP_RHO] = B->m[b]->mat.rho_out;
+  }
+  *rows = r;
+  return SCFFT_OK;
+}
+
+// upload the rows of batch_rows (one copy into member 0's probe area) and
+// scatter them into every member's BPar slot
+scfft_status batch_upload(scfft_batch* B, const double* rows) {
+  scfft_ctx* c = B->m[0];
+  double* stage = wsp<double>(c, c->off_probe);
+  HIPCHK(c, hipMemcpyAsync(stage, rows, B->m.size() * kBParDoubles * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipEventRecord(B->ev[B->ring], c->stream));
+  HIPCHK(c, launch_strided_copy<double>(wsp<double>(c, c->off_bpar), (int64_t)B->stride, stage,
+                                        kBParDoubles * (int64_t)sizeof(double), kBParDoubles, (int)B->m.size(),
+                                        c->stream));
+  B->ev_live[B->ring] = true;
+  B->ring = (B->ring + 1) % kBatchRing;
+  return SCFFT_OK;
+}
+
+bool batch_warm(const scfft_batch* B, scfft_status* st) {
+  for (auto* m : B->m)
+    if (m->has_warm != B->m[0]->has_warm) {
+      *st = fail(B->m[0], SCFFT_ERR_STATE, "batch members differ in having a warm start");
+      return false;
+    }
+  return true;
+}
+
+// One right-hand side (fixed iteration count) of every member as batched
+// launches.  Instance b reads h + b zs_in bytes (plus in2_coef in2 of its
+// own, in2_sel: BPar stage coefficient) and writes hdot + b zs_out bytes; its
+// applied-field rate is tab[b zs_tab bytes + 9 *step + 3 stage + c].
+template <typename T>
+scfft_status batch_rhs_passes(scfft_batch* B, const T* h, T* hdot, int64_t zs_in, int64_t zs_out,
+                              const T* in2, int in2_sel, const double* tab, int64_t zs_tab,
+                              const int* step, int stage) {
+  scfft_ctx* c = B->m[0];
+  Plan<T> p = make_plan<T>(c);
+  p.batch = (int)B->m.size();
+  p.zs_main = (int64_t)(B->stride / sizeof(C2<T>));
+  XArgs<T> a = base_args<T>(c);
+  a.zs_ws = (int64_t)B->stride;
+  a.zs_in = zs_in;
+  a.zs_out = zs_out;
+  a.zpar = wsp<double>(c, c->off_bpar);
+  a.in2 = in2;
+  a.in2_sel = in2 ? in2_sel : -1;
+  a.hedot_tab = tab;
+  a.zs_tab = zs_tab;
+  a.hedot_step = step;
+  a.hedot_stage = stage;
+  const scfft_status st =
+      rhs_fixed_passes<T>(c, p, a, c->has_warm, wsp<T>(c, c->off_warm), B->lo, B->hi, h, hdot);
+  if (st < 0) return st;
+  for (auto* m : B->m) {
+    m->has_warm = true;
+    drop_cont(m);
+  }
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status batch_rhs_impl(scfft_batch* B, double t_s, const T* h, T* hdot, int64_t fstride) {
+  scfft_ctx* c = B->m[0];
+  scfft_status st;
+  if (!batch_warm(B, &st)) return st;
+  double* rows = nullptr;
+  if ((st = batch_rows(B, &rows)) < 0) return st;
+  for (size_t b = 0; b < B->m.size(); ++b) {
+    double he[3], hd[3];
+    B->m[b]->drive.eval(t_s / B->m[b]->u.t0, he, hd);
+    for (int d = 0; d < 3; ++d) rows[b * kBParDoubles + BP_HEDOT + d] = hd[d];
+  }
+  if ((st = batch_upload(B, rows)) < 0) return st;
+  double* par = wsp<double>(c, c->off_bpar);
+  const int64_t fs = fstride * (int64_t)sizeof(T);
+  return batch_rhs_passes<T>(B, h, hdot, fs, fs, nullptr, -1, par + BP_HEDOT, (int64_t)B->stride,
+                             reinterpret_cast<const int*>(par + BP_ZERO), 0);
+}
+
+// One Bogacki-Shampine step of every member as batched launches, as captured
+// in a graph (the steps of graph_step, with per-member step sizes, stage
+// coefficients and rate tables).
+template <typename T>
+scfft_status batch_graph_step(scfft_batch* B, T* const r[6], GraphState* gs, const double* tab, int steps,
+                              double* hist) {
+  scfft_ctx* c = B->m[0];
+  const int count = (int)B->m.size();
+  const int64_t zs = (int64_t)B->stride;
+  const int64_t zt = (int64_t)steps * 9 * (int64_t)sizeof(double);
+  double* par = wsp<double>(c, c->off_bpar);
+  const double thr = 1e-6 / 2e-4;  // atol / rtol of the default controller
+  scfft_status st;
+  if ((st = batch_rhs_passes<T>(B, r[B_Y], r[B_K2], zs, zs, r[B_K1], BP_C2 - 2, tab, zt, &gs->step, 0)) < 0)
+    return st;
+  if ((st = batch_rhs_passes<T>(B, r[B_Y], r[B_K3], zs, zs, r[B_K2], BP_C3 - 2, tab, zt, &gs->step, 1)) < 0)
+    return st;
+  HIPCHK(c, launch_combo_batch<T>(r[B_Y1], r[B_Y], r[B_K1], r[B_K2], r[B_K3], par, 3 * c->nodes, count, zs,
+                                  c->stream, &gs->stop));
+  if ((st = batch_rhs_passes<T>(B, r[B_Y1], r[B_K4], zs, zs, nullptr, -1, tab, zt, &gs->step, 2)) < 0)
+    return st;
+  double* part = wsp<double>(c, c->off_part);
+  HIPCHK(c, launch_errnorm_batch<T>(r[B_Y], r[B_Y1], r[B_K1], r[B_K2], r[B_K3], r[B_K4], par, thr, 3 * c->nodes,
+                                    part, kReduceBlocks, count, zs, c->stream, &gs->stop));
+  HIPCHK(c, launch_max_partials_batch(part, kReduceBlocks, par + BP_ERR, count, zs, c->stream, &gs->stop));
+  HIPCHK(c, launch_batch_step_end(par + BP_ERR, zs, count, steps, gs, hist, c->stream));
+  return SCFFT_OK;
+}
+
+void batch_drop_graphs(scfft_batch* B) {
+  for (auto& x : B->exec)
+    if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+}
+
+template <typename T>
+scfft_status batch_graph_begin_impl(scfft_batch* B, double t0_s, double t1_s, int steps, char* gws, T* h,
+                                    int64_t fstride) {
+  scfft_ctx* c = B->m[0];
+  const int count = (int)B->m.size();
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  const int64_t zs = (int64_t)B->stride;
+  const BatchGraphLayout L = batch_graph_layout(count, steps);
+  GraphState* gs = reinterpret_cast<GraphState*>(gws + L.off_state);
+  double* hist = reinterpret_cast<double*>(gws + L.off_hist);
+  double* tab = reinterpret_cast<double*>(gws + L.off_tab);
+  T* buf[6];
+  for (int k = 0; k < 6; ++k) buf[k] = wsp<T>(c, c->off_ode + (size_t)k * fb);
+  scfft_status st;
+  double* rows = nullptr;
+  if ((st = batch_rows(B, &rows)) < 0) return st;
+  // per member: dimensionless step (t' = t / t0 of its own jc), stage
+  // coefficients, the rate at t0 (first evaluation) and at every stage time
+  B->tab.assign((size_t)count * steps * 9, 0.0);
+  const double frac[3] = {0.5, 0.75, 1.0};
+  for (int b = 0; b < count; ++b) {
+    const scfft_ctx* m = B->m[b];
+    // the step as graph_begin_impl forms it, so a member replays bit for bit
+    // what its own context would
+    const double t0 = t0_s / m->u.t0, t1 = t1_s / m->u.t0, dt = (t1 - t0) / steps;
+    double* r = rows + (size_t)b * kBParDoubles;
+    r[BP_C2] = 0.5 * dt;
+    r[BP_C3] = 0.75 * dt;
+    r[BP_B1] = dt * (2.0 / 9.0);
+    r[BP_B2] = dt * (1.0 / 3.0);
+    r[BP_B3] = dt * (4.0 / 9.0);
+    r[BP_DT] = dt;
+    double he[3], hd[3];
+    m->drive.eval(t0, he, hd);
+    for (int d = 0; d < 3; ++d) r[BP_HEDOT + d] = hd[d];
+    for (int s = 0; s < steps; ++s)
+      for (int q = 0; q < 3; ++q) {
+        m->drive.eval(t0 + s * dt + frac[q] * dt, he, hd);
+        for (int d = 0; d < 3; ++d) B->tab[((size_t)b * steps + s) * 9 + q * 3 + d] = hd[d];
+      }
+  }
+  if ((st = batch_upload(B, rows)) < 0) return st;
+  HIPCHK(c, hipMemcpyAsync(tab, B->tab.data(), B->tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, launch_graph_reset(gs, c->stream));
+  // the members' states into their Y buffers, then their first rates (plain launches)
+  HIPCHK(c, launch_strided_copy<T>(buf[B_Y], zs, h, fstride * (int64_t)sizeof(T), 3 * c->nodes, count,
+                                   c->stream));
+  double* par = wsp<double>(c, c->off_bpar);
+  if ((st = batch_rhs_passes<T>(B, buf[B_Y], buf[B_K1], zs, zs, nullptr, -1, par + BP_HEDOT, zs,
+                                reinterpret_cast<const int*>(par + BP_ZERO), 0)) < 0)
+    return st;
+  // one step captured for each parity of the buffer roles, then replayed
+  batch_drop_graphs(B);
+  hipStream_t cs = nullptr;
+  HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const hipStream_t saved = c->stream;
+  const bool saved_prof = c->prof;
+  c->stream = cs;
+  c->prof = false;
+  c->graph_stop = &gs->stop;
+  T* r[6];
+  for (int k = 0; k < 6; ++k) r[k] = buf[k];
+  st = SCFFT_OK;
+  for (int parity = 0; parity < 2 && st == SCFFT_OK; ++parity) {
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+      break;
+    }
+    const scfft_status sst = batch_graph_step<T>(B, r, gs, tab, steps, hist);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (sst < 0) {
+      st = sst;
+    } else if (e != hipSuccess) {
+      st = fail(c, SCFFT_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    } else {
+      e = hipGraphInstantiate(&B->exec[parity], g, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(c, SCFFT_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (g) (void)hipGraphDestroy(g);
+    std::swap(r[B_Y], r[B_Y1]);
+    std::swap(r[B_K1], r[B_K4]);
+  }
+  c->stream = saved;
+  c->prof = saved_prof;
+  c->graph_stop = nullptr;
+  (void)hipStreamDestroy(cs);
+  for (int s = 0; s < steps && st == SCFFT_OK; ++s) {
+    const hipError_t e = hipGraphLaunch(B->exec[s & 1], c->stream);
+    if (e != hipSuccess) st = fail(c, SCFFT_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+  }
+  if (st != SCFFT_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    batch_drop_graphs(B);
+    return st;
+  }
+  B->busy = true;
+  for (auto* m : B->m) m->graph_busy = true;
+  B->gws = gws;
+  B->steps = steps;
+  B->t0_s = t0_s;
+  B->t1_s = t1_s;
+  B->h = h;
+  B->fstride = fstride;
+  return SCFFT_OK;
+}
+
+template <typename T>
+scfft_status batch_graph_wait_impl(scfft_batch* B, scfft_ode_stats* stats) {
+  scfft_ctx* c = B->m[0];
+  const int count = (int)B->m.size();
+  const BatchGraphLayout L = batch_graph_layout(count, B->steps);
+  GraphState hs{0, 0, -1, 0};
+  hipError_t e = hipMemcpyAsync(&hs, B->gws + L.off_state, sizeof hs, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  B->busy = false;
+  for (auto* m : B->m) m->graph_busy = false;
+  if (e != hipSuccess) return fail(c, SCFFT_ERR_DEVICE, "batch graph integration: %s", hipGetErrorString(e));
+  // the last accepted states sit in the Y buffers of the parity of the next (or failed) step
+  const size_t fb = 3 * c->nodes * sizeof(T);
+  const int next = hs.bad >= 0 ? hs.bad : hs.step;
+  const int slot = (next & 1) ? B_Y1 : B_Y;
+  HIPCHK(c, launch_strided_copy<T>(static_cast<T*>(B->h), B->fstride * (int64_t)sizeof(T),
+                                   wsp<T>(c, c->off_ode + (size_t)slot * fb), (int64_t)B->stride, 3 * c->nodes,
+                                   count, c->stream));
+  std::vector<double> hist((size_t)count * B->steps, 0.0);
+  HIPCHK(c, hipMemcpyAsync(hist.data(), B->gws + L.off_hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int last = hs.bad >= 0 ? hs.bad : hs.step - 1;
+  const double dts = (B->t1_s - B->t0_s) / B->steps;
+  if (stats) {
+    for (int b = 0; b < count; ++b) {
+      scfft_ode_stats& st = stats[b];
+      std::memset(&st, 0, sizeof st);
+      st.accepted = hs.step;
+      st.rhs_calls = 1 + 3 * (int64_t)(hs.step + (hs.bad >= 0 ? 1 : 0));
+      st.iters_total = st.rhs_calls * B->m[b]->opts.fixed_iter;
+      st.t_s = hs.step == B->steps ? B->t1_s : B->t0_s + hs.step * dts;
+      st.dt_last_s = dts;
+      st.err_last = last >= 0 ? hist[(size_t)b * B->steps + last] : 0.0;
+    }
+  }
+  return hs.bad >= 0 ? fail(c, SCFFT_ERR_NAN, "non-finite error norm at step %d", hs.bad) : SCFFT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -1781,6 +2160,8 @@ void scfft_default_rhs_opts(scfft_rhs_opts* o) {
   o->fuse_xy = 1;
   o->prune_box = 1;
   o->x_alt = 0;
+  o->y_alt = 0;
+  o->z_alt = 0;
 }
 
 void scfft_default_ode_opts(scfft_ode_opts* o) {
@@ -2026,7 +2407,7 @@ scfft_status scfft_set_rhs_opts(scfft_ctx* ctx, const scfft_rhs_opts* o) {
   drop_cont(ctx);
   if (!(o->delta_it > 0.0) || o->min_iter < 0 || o->max_iter < 1 || o->fixed_iter < 0 ||
       !(o->sigma_scale > 0.0) || o->min_iter > o->max_iter || o->fuse_xy < 0 || o->fuse_xy > 2 ||
-      o->x_alt < 0 || o->x_alt > 1)
+      o->x_alt < 0 || o->x_alt > 1 || o->y_alt < 0 || o->y_alt > 1 || o->z_alt < 0 || o->z_alt > 1)
     return fail(ctx, SCFFT_ERR_ARG, "invalid rhs options");
   const bool resigma = o->sigma_scale != ctx->opts.sigma_scale;
   ctx->opts = *o;
@@ -2522,5 +2903,136 @@ const char* scfft_status_string(scfft_status s) {
 }
 
 const char* scfft_last_error(const scfft_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+scfft_status scfft_batch_create(scfft_batch** out, scfft_ctx* const* members, int32_t count) {
+  if (!out || !members || count < 1 || count > kMaxBatch) return SCFFT_ERR_ARG;
+  *out = nullptr;
+  scfft_ctx* c = members[0];
+  if (!c) return SCFFT_ERR_ARG;
+  for (int32_t b = 0; b < count; ++b) {
+    scfft_ctx* m = members[b];
+    if (!m) return fail(c, SCFFT_ERR_ARG, "member %d is NULL", b);
+    for (int32_t q = 0; q < b; ++q)
+      if (members[q] == m) return fail(c, SCFFT_ERR_ARG, "member %d appears twice", b);
+    scfft_status st;
+    if (!ready(m, true, &st)) return fail(c, st, "member %d: %s", b, m->err.c_str());
+    if (!m->has_drive) return fail(c, SCFFT_ERR_ARG, "member %d has no drive", b);
+    bool same = m->prec == c->prec && m->stream == c->stream && m->device == c->device;
+    for (int a = 0; a < 3; ++a)
+      same = same && m->n[a] == c->n[a] && std::fabs(m->L[a] - c->L[a]) <= 1e-12 * c->L[a];
+    if (!same)
+      return fail(c, SCFFT_ERR_SHAPE, "member %d differs in grid, dimensionless box, precision or stream", b);
+    const scfft_rhs_opts &o = m->opts, &o0 = c->opts;
+    if (o.fixed_iter <= 0 || o.fixed_iter != o0.fixed_iter || o.smooth_phi != o0.smooth_phi ||
+        o.sigma_scale != o0.sigma_scale || o.fuse_xy != o0.fuse_xy || o.prune_box != o0.prune_box ||
+        o.x_alt != o0.x_alt || o.y_alt != o0.y_alt || o.z_alt != o0.z_alt)
+      return fail(c, SCFFT_ERR_ARG, "member %d: batches need equal options with fixed_iter > 0", b);
+    if (m->field_hk_inv > 0.0 || m->has_aniso || m->has_kappa != c->has_kappa)
+      return fail(c, SCFFT_ERR_ARG, "member %d: no field law or anisotropy, and jc maps on all or none", b);
+  }
+  // workspaces at a constant stride: instance b's buffers are instance 0's plus b strides
+  size_t stride = 0;
+  if (count > 1) {
+    const uintptr_t w0 = (uintptr_t)c->ws, w1 = (uintptr_t)members[1]->ws;
+    stride = w1 > w0 ? (size_t)(w1 - w0) : 0;
+    if (stride < c->total || stride % kAlign)
+      return fail(c, SCFFT_ERR_WORKSPACE, "member workspaces must follow each other at a constant stride");
+    for (int32_t b = 2; b < count; ++b)
+      if ((uintptr_t)members[b]->ws != w0 + (uintptr_t)b * stride)
+        return fail(c, SCFFT_ERR_WORKSPACE, "member workspaces must follow each other at a constant stride");
+  }
+  scfft_batch* B = new scfft_batch();
+  B->m.assign(members, members + count);
+  B->stride = stride;
+  // the box that holds Omega of every member (pruning stays exact)
+  bool any = false;
+  for (int a = 0; a < 3; ++a) {
+    B->lo[a] = c->n[a];
+    B->hi[a] = 0;
+  }
+  for (auto* m : B->m) {
+    if (m->n_in == 0) continue;
+    any = true;
+    for (int a = 0; a < 3; ++a) {
+      B->lo[a] = std::min(B->lo[a], m->box_lo[a]);
+      B->hi[a] = std::max(B->hi[a], m->box_hi[a]);
+    }
+  }
+  if (!any)
+    for (int a = 0; a < 3; ++a) B->lo[a] = B->hi[a] = 0;
+  hipError_t e = hipHostMalloc((void**)&B->pin, (size_t)kBatchRing * count * kBParDoubles * sizeof(double),
+                               hipHostMallocDefault);
+  for (int k = 0; k < kBatchRing && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&B->ev[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    scfft_batch_destroy(B);
+    return fail(c, SCFFT_ERR_DEVICE, "batch: %s", hipGetErrorString(e));
+  }
+  *out = B;
+  return SCFFT_OK;
+}
+
+void scfft_batch_destroy(scfft_batch* B) {
+  if (!B) return;
+  if (!B->m.empty()) (void)hipStreamSynchronize(B->m[0]->stream);
+  if (B->busy)
+    for (auto* m : B->m) m->graph_busy = false;
+  batch_drop_graphs(B);
+  for (auto& ev : B->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (B->pin) (void)hipHostFree(B->pin);
+  delete B;
+}
+
+scfft_status scfft_batch_rhs_eval(scfft_batch* B, double t_s, const void* h_dev, void* hdot_dev,
+                                  int64_t field_stride) {
+  if (!B) return SCFFT_ERR_ARG;
+  scfft_ctx* c = B->m[0];
+  if (B->busy) return fail(c, SCFFT_ERR_STATE, "a batch graph integration is enqueued");
+  if (!h_dev || !hdot_dev || h_dev == hdot_dev) return fail(c, SCFFT_ERR_ARG, "invalid field pointers");
+  CHECK_FIELD(c, h_dev);
+  CHECK_FIELD(c, hdot_dev);
+  if (field_stride < (int64_t)(3 * c->nodes) || field_stride % 2)
+    return fail(c, SCFFT_ERR_ARG, "field stride must be even and at least one field (3 Nx Ny Nz)");
+  return c->prec == SCFFT_F64
+             ? batch_rhs_impl<double>(B, t_s, (const double*)h_dev, (double*)hdot_dev, field_stride)
+             : batch_rhs_impl<float>(B, t_s, (const float*)h_dev, (float*)hdot_dev, field_stride);
+}
+
+scfft_status scfft_batch_graph_workspace_size(const scfft_batch* B, int32_t steps, size_t* bytes) {
+  if (!B || !bytes || steps <= 0) return SCFFT_ERR_ARG;
+  *bytes = batch_graph_layout((int)B->m.size(), steps).total;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_batch_integrate_graph(scfft_batch* B, double t0_s, double t1_s, int32_t steps, void* graph_ws,
+                                         size_t graph_bytes, void* h_dev, int64_t field_stride) {
+  if (!B) return SCFFT_ERR_ARG;
+  scfft_ctx* c = B->m[0];
+  if (B->busy) return fail(c, SCFFT_ERR_STATE, "a batch graph integration is enqueued");
+  scfft_status st;
+  for (auto* m : B->m)
+    if (!ready(m, true, &st)) return fail(c, st, "batch member: %s", m->err.c_str());
+  if (!batch_warm(B, &st)) return st;
+  if (!h_dev || steps <= 0 || !(t1_s > t0_s)) return fail(c, SCFFT_ERR_ARG, "invalid integrate arguments");
+  CHECK_FIELD(c, h_dev);
+  if (field_stride < (int64_t)(3 * c->nodes) || field_stride % 2)
+    return fail(c, SCFFT_ERR_ARG, "field stride must be even and at least one field (3 Nx Ny Nz)");
+  const size_t need = batch_graph_layout((int)B->m.size(), steps).total;
+  if (!graph_ws || graph_bytes < need || (reinterpret_cast<uintptr_t>(graph_ws) & 255))
+    return fail(c, SCFFT_ERR_WORKSPACE, "batch graph workspace: %zu bytes at a 256-byte boundary needed", need);
+  for (auto* m : B->m) drop_cont(m);
+  return c->prec == SCFFT_F64
+             ? batch_graph_begin_impl<double>(B, t0_s, t1_s, steps, (char*)graph_ws, (double*)h_dev, field_stride)
+             : batch_graph_begin_impl<float>(B, t0_s, t1_s, steps, (char*)graph_ws, (float*)h_dev, field_stride);
+}
+
+scfft_status scfft_batch_integrate_wait(scfft_batch* B, scfft_ode_stats* stats) {
+  if (!B) return SCFFT_ERR_ARG;
+  if (!B->busy) return fail(B->m[0], SCFFT_ERR_STATE, "no batch graph integration is enqueued");
+  return B->m[0]->prec == SCFFT_F64 ? batch_graph_wait_impl<double>(B, stats)
+                                    : batch_graph_wait_impl<float>(B, stats);
+}
+
+const char* scfft_batch_last_error(const scfft_batch* B) { return B ? B->m[0]->err.c_str() : ""; }
 
 }  // extern "C"

@@ -1,0 +1,43 @@
+// Launch shapes of the transform passes: one table of compile-time constants,
+// each chosen by measurement on MI355X (gfx950).  The run-time alternates of
+// the per-component X, the Y and the Z passes (rhs options x_alt, y_alt,
+// z_alt) are other instantiations of the same kernels, picked per grid by
+// scfft_autotune.
+#pragma once
+
+namespace scfft {
+namespace tune {
+
+// Elements per thread (an upper bound; also the largest radix) of one line.
+constexpr int kEx3F64 = 4;     // X passes holding all three components (power law, moment,
+constexpr int kEx3F32 = 4;     //   adaptive update, reverse mode)
+constexpr int kEx1F64 = 8;     // per-component X passes (input, warm start, store, reverse mode)
+constexpr int kEx1F32 = 8;
+constexpr int kEx1UpdF64 = 4;  // FP64 per-component masks and exterior updates: shorter lines,
+                               //   more rows per block (measured faster)
+constexpr int kEyF64 = 8;      // Y passes (one component per column)
+constexpr int kEyF32 = 8;
+constexpr int kEzF64 = 4;      // Z passes (three components of a column in registers)
+constexpr int kEzF32 = 8;
+
+// Column passes exchange through two alternating LDS buffers (one barrier per
+// exchange) where that does not cost occupancy: the Z pass; the Y pass keeps
+// one buffer (its 8-element FP64 tile would double to 64 KB).
+constexpr bool kPingPongY = false;
+constexpr bool kPingPongZ = true;
+
+// Threads per block of a column pass: 256, doubled while the columns of one
+// block span fewer than this many contiguous bytes of a row.  The FP32 Z
+// pass stops at 64 bytes: a 512-thread block would hold 143 VGPRs per lane
+// and leave one block per CU (measured slower at 256^3).
+constexpr int kColBytes = 128;
+constexpr int kColBytesZF64 = 128;
+constexpr int kColBytesZF32 = 64;
+
+// Threads per block of the fused xy-plane pass (one block per plane): FP64
+// lines need more registers, so FP64 uses fewer, fuller threads.
+constexpr int kXYBlockF64 = 512;
+constexpr int kXYBlockF32 = 1024;
+
+}  // namespace tune
+}  // namespace scfft

@@ -22,19 +22,13 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "tuning.h"
 
 namespace scfft {
 
-// Threads per block (one block per plane): FP64 lines need more registers,
-// so FP64 uses fewer, fuller threads.
-#ifndef SCFFT_XY_BLOCK_F64
-#define SCFFT_XY_BLOCK_F64 512
-#endif
-#ifndef SCFFT_XY_BLOCK_F32
-#define SCFFT_XY_BLOCK_F32 1024
-#endif
+// Threads per block (one block per plane), tuning.h.
 template <typename T>
-constexpr int xy_block() { return sizeof(T) == 8 ? SCFFT_XY_BLOCK_F64 : SCFFT_XY_BLOCK_F32; }
+constexpr int xy_block() { return sizeof(T) == 8 ? tune::kXYBlockF64 : tune::kXYBlockF32; }
 
 template <typename T, int STRIDE>
 struct LdsLine {  // one row (STRIDE = 1) or one column (STRIDE = row stride) of the plane
@@ -140,7 +134,7 @@ __device__ __forceinline__ void row_r2c(C2<T>* row, int j, const C2<T>* __restri
 }
 
 template <typename T, int NX, int NY, int OP>
-__global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs<T> A) {
+__global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArgs<T> A0) {
   using G = XYGeom<T, NX, NY>;
   constexpr int M = G::M, RS = G::RS, E = G::EX, TPT = G::TPTX;
   constexpr bool HAS_INV = OP != XY_FWD;
@@ -148,7 +142,10 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   constexpr bool NEED_CHI = OP == XY_HIN || OP == XY_MASK || OP == XY_UPDATE || OP == XY_UPDATE_LAST;
   constexpr bool NEED_AUX = OP == XY_FWD || OP == XY_HIN || OP == XY_UPDATE;
   __shared__ C2<T> plane[NY * RS];
-  if (P.stop && *P.stop) return;  // uniform: a graph replay has stopped
+  if (P0.stop && *P0.stop) return;  // uniform: a graph replay has stopped
+  Plan<T> P = P0;
+  P.main += blockIdx.z * P0.zs_main;  // instance of a batched launch
+  const XArgs<T> A = instance_args(A0);
 
   const int nz = P.nz;
   const int nzr = P.r.zhi - P.r.zlo;                  // planes of this launch
@@ -160,7 +157,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P, XArgs
   const size_t rbase = (size_t)c * csr + (size_t)z * NY * NX;  // this plane, real field
   const size_t sbase = ((size_t)c * nz + z) * NY * M;          // this plane, spectrum
   const C2<T>* __restrict__ twx = P.ax.tw;
-  T hdc = A.hedot[c];  // applied-field rate of this component (exterior update)
+  T hdc = A0.hedot[c];  // applied-field rate of this component (kernel argument: indexed in place)
   if constexpr (OP == XY_UPDATE || OP == XY_UPDATE_LAST) {
     if (A.hedot_tab) hdc = (T)A.hedot_tab[9 * (size_t)(*A.hedot_step) + 3 * A.hedot_stage + c];
   }
@@ -326,7 +323,7 @@ template <typename T, int N>
 static hipError_t xylaunch_n(const Plan<T>& p, int op, const XArgs<T>& a, hipStream_t s, KTime t) {
   const int nzr = p.r.zhi - p.r.zlo;
   if (nzr <= 0) return hipSuccess;
-  const dim3 grid(3 * nzr), block(xy_block<T>());
+  const dim3 grid(3 * nzr, 1, p.batch), block(xy_block<T>());
 #define SCFFT_XY_CASE(OPV)                                                                   \
   case OPV:                                                                                  \
     if (t.start)                                                                             \

@@ -58,7 +58,8 @@ class Shape(C.Structure):
 class RhsOpts(C.Structure):
     _fields_ = [("delta_it", C.c_double), ("min_iter", C.c_int32), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("smooth_phi", C.c_int32), ("sigma_scale", C.c_double),
-                ("fuse_xy", C.c_int32), ("prune_box", C.c_int32), ("x_alt", C.c_int32)]
+                ("fuse_xy", C.c_int32), ("prune_box", C.c_int32), ("x_alt", C.c_int32),
+                ("y_alt", C.c_int32), ("z_alt", C.c_int32)]
 
 
 class RhsStats(C.Structure):
@@ -118,6 +119,14 @@ _SIGS = {
                                   _P, C.POINTER(OdeStats)]),
     "scfft_curl": (C.c_int, [_P, _P, _P]),
     "scfft_curl_noalloc": (C.c_int, [_P, _P, _P]),
+    "scfft_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(_P), C.c_int32]),
+    "scfft_batch_destroy": (None, [_P]),
+    "scfft_batch_rhs_eval": (C.c_int, [_P, C.c_double, _P, _P, C.c_int64]),
+    "scfft_batch_graph_workspace_size": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scfft_batch_integrate_graph": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, C.c_size_t, _P,
+                                              C.c_int64]),
+    "scfft_batch_integrate_wait": (C.c_int, [_P, C.POINTER(OdeStats)]),
+    "scfft_batch_last_error": (C.c_char_p, [_P]),
     "scfft_phi": (C.c_int, [_P, _P, _P]),
     "scfft_current": (C.c_int, [_P, _P, _P]),
     "scfft_moment": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
@@ -448,6 +457,47 @@ def scfft_integrate_wait(ctx, stats=None):
     return _check(load().scfft_integrate_wait(ctx, C.byref(stats) if stats is not None else None), ctx)
 
 
+def _bcheck(st, batch):
+    if st < 0:
+        msg = load().scfft_batch_last_error(batch).decode()
+        raise ScfftError(st, "%s: %s" % (scfft_status_string(st), msg))
+    return st
+
+
+def scfft_batch_create(ctxs):
+    arr = (_P * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    b = _P()
+    st = load().scfft_batch_create(C.byref(b), arr, len(ctxs))
+    if st < 0:
+        raise ScfftError(st, "%s: %s" % (scfft_status_string(st), scfft_last_error(ctxs[0])))
+    return b
+
+
+def scfft_batch_destroy(batch):
+    load().scfft_batch_destroy(batch)
+
+
+def scfft_batch_rhs_eval(batch, t_s, h, hdot, field_stride):
+    return _bcheck(load().scfft_batch_rhs_eval(batch, float(t_s), _ptr(h), _ptr(hdot), int(field_stride)), batch)
+
+
+def scfft_batch_graph_workspace_size(batch, steps):
+    n = C.c_size_t()
+    _bcheck(load().scfft_batch_graph_workspace_size(batch, int(steps), C.byref(n)), batch)
+    return n.value
+
+
+def scfft_batch_integrate_graph(batch, t0_s, t1_s, steps, ws, h, field_stride):
+    return _bcheck(load().scfft_batch_integrate_graph(batch, float(t0_s), float(t1_s), int(steps), _ptr(ws),
+                                                      int(ws.numel()), _ptr(h), int(field_stride)), batch)
+
+
+def scfft_batch_integrate_wait(batch, count):
+    stats = (OdeStats * count)()
+    _bcheck(load().scfft_batch_integrate_wait(batch, stats), batch)
+    return list(stats)
+
+
 def device_buffer(nbytes):
     """A 256-byte aligned uint8 device tensor of nbytes (workspaces)."""
     import torch
@@ -553,7 +603,9 @@ class Simulation:
     n_power, jc, e0, rho_out and drive (see workloads.CONFIGS).
     """
 
-    def __init__(self, cfg, precision=F64, stream=None, rhs_opts=None):
+    def __init__(self, cfg, precision=F64, stream=None, rhs_opts=None, workspace=None):
+        """workspace: (device address, bytes) of caller memory to use instead
+        of a tensor of its own (the slices of a Batch)."""
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -568,9 +620,15 @@ class Simulation:
         self.stream = stream
         self.ctx = scfft_create(self.grid, self.material, precision, stream)
         nbytes = scfft_workspace_size(self.ctx)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
+        if workspace is None:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+        else:
+            self.workspace = None
+            aligned, have = workspace
+            if have < nbytes:
+                raise ValueError("workspace slice of %d bytes, %d needed" % (have, nbytes))
         scfft_set_workspace(self.ctx, aligned, nbytes)
         self.shapes, self.n_shapes = make_shapes(cfg["shapes"], l)
         if scfft_voxelize(self.ctx, self.shapes, self.n_shapes) == WARN_TOPOLOGY:
@@ -611,6 +669,76 @@ class Simulation:
         if self.ctx:
             scfft_destroy(self.ctx)
             self.ctx = None
+
+
+class Batch:
+    """Same-size instances advanced with batched launches (scfft_batch_*):
+    one Simulation per configuration, their workspaces carved in equal
+    slices from one allocation.  Fields are tensors of shape
+    (count, 3, Nz, Ny, Nx)."""
+
+    def __init__(self, cfgs, precision=F64, stream=None, rhs_opts=None):
+        import torch
+        self.torch = torch
+        l0 = cfgs[0]["l_m"]
+        g = make_grid(cfgs[0]["n"], [v * l0 for v in cfgs[0]["half_width"]])
+        m = make_material(cfgs[0]["n_power"], cfgs[0]["jc"], cfgs[0].get("e0", 1e-4), cfgs[0]["rho_out"], l0)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        ctx = scfft_create(g, m, precision, stream)
+        stride = (scfft_workspace_size(ctx) + 255) // 256 * 256
+        scfft_destroy(ctx)
+        self.count = len(cfgs)
+        self.stride = stride
+        self.workspace = torch.empty(self.count * stride + 256, dtype=torch.uint8, device="cuda")
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.sims = [Simulation(c, precision=precision, stream=stream, rhs_opts=rhs_opts,
+                                workspace=(base + b * stride, stride)) for b, c in enumerate(cfgs)]
+        self.dtype = self.sims[0].dtype
+        self.field_shape = (self.count,) + self.sims[0].field_shape
+        self.field_stride = int(np.prod(self.sims[0].field_shape))
+        self.batch = scfft_batch_create([s.ctx for s in self.sims])
+
+    def empty_field(self):
+        return self.torch.empty(self.field_shape, dtype=self.dtype, device="cuda")
+
+    def _check_field(self, f):
+        if tuple(f.shape) != self.field_shape or f.dtype != self.dtype or not f.is_contiguous():
+            raise ValueError("field must be a contiguous %s tensor of shape %s" % (self.dtype, self.field_shape))
+
+    def rhs_eval(self, t_s, h, hdot=None):
+        if hdot is None:
+            hdot = self.empty_field()
+        self._check_field(h)
+        self._check_field(hdot)
+        scfft_batch_rhs_eval(self.batch, t_s, h, hdot, self.field_stride)
+        return hdot
+
+    def graph_workspace(self, steps):
+        return device_buffer(scfft_batch_graph_workspace_size(self.batch, steps))
+
+    def integrate_graph(self, t0_s, t1_s, steps, h, ws=None):
+        """Enqueue `steps` fixed Bogacki-Shampine steps of every member; wait()
+        returns the per-member stats and leaves the states in h."""
+        self._check_field(h)
+        self._ws = ws if ws is not None else self.graph_workspace(steps)
+        scfft_batch_integrate_graph(self.batch, t0_s, t1_s, steps, self._ws, h, self.field_stride)
+
+    def wait(self):
+        return scfft_batch_integrate_wait(self.batch, self.count)
+
+    def close(self):
+        if self.batch:
+            scfft_batch_destroy(self.batch)
+            self.batch = None
+        for s in self.sims:
+            s.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __del__(self):
         try:

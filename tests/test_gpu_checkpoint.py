@@ -71,7 +71,9 @@ def test_adaptive_resume_repeats_the_uninterrupted_steps():
     restart without the continuation recomputes k1 and a first step size and
     does not."""
     h0 = to_dev(torch, state(CUP, seed=3), torch.float64)
-    t_end = 0.002
+    probe = sim(CUP, delta_it=2e-5)
+    scfft.scfft_init_state(probe.ctx, 0.0, h0)           # virgin state: the field ramp penetrates
+    t_end = 0.2
 
     a = sim(CUP, delta_it=2e-5)
     ha = h0.clone()
@@ -79,7 +81,7 @@ def test_adaptive_resume_repeats_the_uninterrupted_steps():
     sa = scfft.OdeStats()
     scfft.scfft_integrate(a.ctx, 0.0, t_end, ha, scfft.default_ode_opts(),
                           observer=lambda _u, t, _p: ta.append(t) or 0, stats=sa)
-    assert sa.accepted >= 8 and sa.rejected + sa.accepted > 0
+    assert sa.accepted >= 6
     k = sa.accepted // 2
 
     b = sim(CUP, delta_it=2e-5)
