@@ -214,6 +214,41 @@ __device__ __forceinline__ void fft_inverse(C2<T> (&v)[E], int j, Lds& lds,
   for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
 }
 
+// Twiddle table of one axis staged in LDS.  Every pass of a transform after
+// the first reads it; from global memory (an L2 round trip per pass) that
+// latency sat between the LDS exchanges.  fetch() issues the global loads
+// (before the block's other loads, so waiting for them later waits for
+// nothing else); put() writes the LDS copy.  The copy must be visible to the
+// whole block before the first read: with column layouts every exchange is a
+// block barrier and the first pass of a transform reads no twiddle, so put()
+// before the first transform suffices; with row layouts (wavefront-local
+// exchanges) the caller adds one block barrier after put().
+template <typename T, int N, int BLOCK>
+struct LdsTwiddles {
+  // at most two entries per thread, held as plain scalars (a C2 or an array
+  // member is placed in LDS by the compiler's alloca promotion)
+  static_assert(N <= 2 * BLOCK, "twiddle table larger than two entries per thread");
+  T r0x = T(0), r0y = T(0), r1x = T(0), r1y = T(0);
+  __device__ __forceinline__ void fetch(const C2<T>* __restrict__ g) {
+    const int i = (int)threadIdx.x;
+    if (i < N) {
+      const C2<T> w = g[i];
+      r0x = w.x;
+      r0y = w.y;
+    }
+    if (N > BLOCK && i + BLOCK < N) {
+      const C2<T> w = g[i + BLOCK];
+      r1x = w.x;
+      r1y = w.y;
+    }
+  }
+  __device__ __forceinline__ void put(C2<T>* s) const {
+    const int i = (int)threadIdx.x;
+    if (i < N) s[i] = C2<T>{r0x, r0y};
+    if (N > BLOCK && i + BLOCK < N) s[i + BLOCK] = C2<T>{r1x, r1y};
+  }
+};
+
 // LDS layouts.  Column-major: COLS transforms side by side, element idx of
 // column c at idx * COLS + c (lanes of one row of columns are contiguous).
 //

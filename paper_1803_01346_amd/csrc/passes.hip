@@ -106,6 +106,9 @@ __global__ __launch_bounds__((col_block<T, NY, EV ? EV : ey_max<T>()>())) void y
   constexpr int TPT = NY / E;
   constexpr int COLS = col_block<T, NY, EM>() / TPT;
   __shared__ C2<T> smem[(tune::kPingPongY ? 2 : 1) * NY * COLS];
+  __shared__ C2<T> twl[NY];
+  LdsTwiddles<T, NY, col_block<T, NY, EM>()> twd;
+  twd.fetch(tw);
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -127,6 +130,7 @@ __global__ __launch_bounds__((col_block<T, NY, EV ? EV : ey_max<T>()>())) void y
     v[m] = (valid && y >= R.ylo_in && y < R.yhi_in) ? p[(size_t)y * es] : C2<T>{T(0), T(0)};
   }
   ColLds<tune::kPingPongY, T, NY, COLS> lds{smem, col};
+  twd.put(twl);  // read from the transform's second pass on (block barriers between passes)
   if constexpr (INV) {
     if (dc_block) {  // rebuild P(ky) of the kx = 0 column from its half-complex layout
 #pragma unroll
@@ -141,9 +145,9 @@ __global__ __launch_bounds__((col_block<T, NY, EV ? EV : ey_max<T>()>())) void y
       }
       __syncthreads();
     }
-    fft_inverse<T, NY, E>(v, j, lds, tw, 1);
+    fft_inverse<T, NY, E>(v, j, lds, twl, 1);
   } else {
-    fft_forward<T, NY, E>(v, j, lds, tw, 1);
+    fft_forward<T, NY, E>(v, j, lds, twl, 1);
     if (dc_block) {  // split the kx = 0 column into A and B (half-complex layout)
       __syncthreads();
 #pragma unroll
@@ -214,6 +218,9 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   constexpr int TPT = NZ / E;
   constexpr int COLS = z_block<T, NZ, EV>() / TPT;
   __shared__ C2<T> smem[(tune::kPingPongZ ? 2 : 1) * NZ * COLS];
+  __shared__ C2<T> twl[NZ];
+  LdsTwiddles<T, NZ, z_block<T, NZ, EV>()> twd;
+  twd.fetch(tz.tw);
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -244,8 +251,9 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
                                                    : C2<T>{T(0), T(0)};
     }
   ColLds<tune::kPingPongZ, T, NZ, COLS> lds{smem, col};
+  twd.put(twl);  // read from the transform's second pass on (block barriers between passes)
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, tz.tw, 1);
+  for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, twl, 1);
 
   // Packed columns P = A + i B: with A = (P + conj P(-k)) / 2 on the kx = 0
   // plane and B = (P - conj P(-k)) / 2i on the Nyquist plane, and both planes
@@ -304,7 +312,7 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   // overlap the inverse transforms of the next ones
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    fft_inverse<T, NZ, E>(v[c], j, lds, tz.tw, 1);
+    fft_inverse<T, NZ, E>(v[c], j, lds, twl, 1);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -426,7 +434,10 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P0, XArgs<T> A0) 
   const bool inv_row = valid && ry >= P.r.iylo && ry < P.r.iyhi && rz >= P.r.izlo && rz < P.r.izhi;
   const size_t csm = (size_t)nrows * M;        // component stride, main spectrum
   const size_t csr = (size_t)nrows * NX;       // component stride, real field
-  const C2<T>* __restrict__ tw = P.ax.tw;      // exp(-2 pi i k / NX)
+  __shared__ C2<T> twl[NX];
+  LdsTwiddles<T, NX, kBlock> twd;
+  twd.fetch(P.ax.tw);
+  const C2<T>* tw = twl;                       // exp(-2 pi i k / NX), staged in LDS below
   const int c0 = NC == 3 ? 0 : (int)blockIdx.y;  // first component of this block
   L lds{smem, rl};
 
@@ -452,17 +463,20 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P0, XArgs<T> A0) 
   constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST || OP >= X_ADJ_START;
   C2<T> Xs[HAS_INV ? NC : 1][E];
   C2<T> Xn[NC];
+  // the power law loads its third component's row after the first is transformed
+  constexpr bool LAZY = NC == 3 && OP == X_LAW;
+  auto load_row = [&](int cc) {
+    const int c = c0 + cc;
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      Xs[cc][m] = inv_row ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
+    // the kx = 0 slot holds X[0] + i X[M] (both real)
+    Xn[cc] = {Xs[cc][0].y, T(0)};
+    if (j == 0) Xs[cc][0].y = T(0);
+  };
   if constexpr (HAS_INV) {
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-      const int c = c0 + cc;
-#pragma unroll
-      for (int m = 0; m < E; ++m)
-        Xs[cc][m] = inv_row ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-      // the kx = 0 slot holds X[0] + i X[M] (both real)
-      Xn[cc] = {Xs[cc][0].y, T(0)};
-      if (j == 0) Xs[cc][0].y = T(0);
-    }
+    for (int cc = 0; cc < (LAZY ? 2 : NC); ++cc) load_row(cc);
   }
   // Nodes x = 2n, 2n+1 of one complex element n are adjacent: the mask and
   // the real fields are read (and stored) two nodes per access.  Measured
@@ -548,9 +562,15 @@ __global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P0, XArgs<T> A0) 
     }
   }
 
+  twd.put(twl);
+  __syncthreads();  // row exchanges are wavefront-local: make the table visible to the block
+
   if constexpr (HAS_INV) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      if constexpr (LAZY) {
+        if (c == 1) load_row(2);
+      }
 #pragma unroll
       for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Xs[c][m]);
       if (j == 0) lds.store(M, Xn[c]);

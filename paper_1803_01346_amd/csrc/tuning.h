@@ -15,8 +15,8 @@ constexpr int kEx1F64 = 8;     // per-component X passes (input, warm start, sto
 constexpr int kEx1F32 = 8;
 constexpr int kEx1UpdF64 = 4;  // FP64 per-component masks and exterior updates: shorter lines,
                                //   more rows per block (measured faster)
-constexpr int kEyF64 = 8;      // Y passes (one component per column)
-constexpr int kEyF32 = 8;
+constexpr int kEyF64 = 4;      // Y passes (one component per column); FP64: 8 lanes of a
+constexpr int kEyF32 = 8;      //   16 KB tile hold 8 blocks per CU (4 with 8 elements)
 constexpr int kEzF64 = 4;      // Z passes (three components of a column in registers)
 constexpr int kEzF32 = 8;
 

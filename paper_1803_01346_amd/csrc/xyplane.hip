@@ -156,8 +156,17 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
   const size_t csr = (size_t)nz * NY * NX;                    // component stride, real field
   const size_t rbase = (size_t)c * csr + (size_t)z * NY * NX;  // this plane, real field
   const size_t sbase = ((size_t)c * nz + z) * NY * M;          // this plane, spectrum
-  const C2<T>* __restrict__ twx = P.ax.tw;
-  T hdc = A0.hedot[c];  // applied-field rate of this component (kernel argument: indexed in place)
+  // twiddle tables of both axes staged in LDS (fetched before the other loads)
+  __shared__ C2<T> twl_x[NX];
+  __shared__ C2<T> twl_y[NY];
+  LdsTwiddles<T, NX, G::BLOCK> twdx;
+  LdsTwiddles<T, NY, G::BLOCK> twdy;
+  twdx.fetch(P.ax.tw);
+  twdy.fetch(P.ay.tw);
+  const C2<T>* twx = twl_x;
+  // applied-field rate of this component, selected (a dynamic index into the
+  // argument struct would copy it to scratch)
+  T hdc = c == 0 ? A0.hedot[0] : (c == 1 ? A0.hedot[1] : A0.hedot[2]);
   if constexpr (OP == XY_UPDATE || OP == XY_UPDATE_LAST) {
     if (A.hedot_tab) hdc = (T)A.hedot_tab[9 * (size_t)(*A.hedot_step) + 3 * A.hedot_stage + c];
   }
@@ -217,6 +226,10 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
     }
   }
 
+  twdx.put(twl_x);
+  twdy.put(twl_y);
+  __syncthreads();  // line exchanges are wavefront-local: make the tables visible to the block
+
   // planes outside [izlo, izhi) need no inverse transform (their input counts as 0)
   const bool inv_plane = z >= P.r.izlo && z < P.r.izhi;
   if constexpr (HAS_INV) {
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
         plane[(NY - y) * RS] = C2<T>{a.x + b.y, b.x - a.y};
       }
       __syncthreads();
-      plane_columns<T, NX, NY, true>(plane, P.ay.tw);
+      plane_columns<T, NX, NY, true>(plane, twl_y);
       __syncthreads();
       // X[0] + i X[M] of each row to the two real slots
       for (int y = t; y < NY; y += G::BLOCK) {
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
 
   if constexpr (HAS_FWD) {
     __syncthreads();
-    plane_columns<T, NX, NY, false>(plane, P.ay.tw);
+    plane_columns<T, NX, NY, false>(plane, twl_y);
     __syncthreads();
     // kx = 0 column to the half-complex layout: A(ky) and B(ky)
     for (int y = 1 + t; 2 * y < NY; y += G::BLOCK) {
