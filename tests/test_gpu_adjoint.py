@@ -285,9 +285,11 @@ def test_config5_gradients_against_central_differences():
     """The adjoint configuration at full size: the 128^3 shield with a jc map
     kappa = 1 + 0.1 N(0,1) (seed 5), a critical-state start, 2000 fixed
     steps of 2e-5 s (checkpoints every 50), loss = mean over the bore of
-    |h(t_end)|^2.  The gradients in n and in a global jc (a uniform scaling
-    of kappa) from one adjoint run agree with central differences of the
-    forward path (relative step 1e-6) within 1e-4."""
+    |h(t_end)|^2.  The gradients in n, in a global jc (a uniform scaling of
+    kappa), in the field angle (the applied field turned in the x-z plane)
+    and in the kappa voxel of largest sensitivity, all from one adjoint run,
+    agree with central differences of the forward path (relative step 1e-6)
+    within 1e-4."""
     import math
     from paper_1803_01346_amd import autograd as sag
     cfg = workloads.config("cup128")
@@ -306,24 +308,45 @@ def test_config5_gradients_against_central_differences():
     he, _ = scfft.scfft_drive_eval(s.drive, s.material, 0.005)
     h0 = to_dev(torch, state(cfg, seed=0, bg=tuple(he)), torch.float64)
     p0 = sag.drive_vector(s)
+    amp = float(torch.linalg.norm(p0))
+    d = cfg["drive"]["direction"]
+    theta = math.atan2(d[0], d[2])                         # angle from the z axis in the x-z plane
+    assert abs(d[1]) < 1e-15
 
-    def loss(sim_, kap):
+    def p_of(th):
+        return torch.tensor([amp * math.sin(th), 0.0, amp * math.cos(th)], dtype=torch.float64)
+
+    def loss(sim_, kap, p=p0):
         nt = torch.tensor(float(sim_.cfg["n_power"]), dtype=torch.float64)
-        hT = sag.IntegrateParams.apply(h0, kap, nt, p0, sim_, 0.0, t1_s, steps, every)
+        hT = sag.IntegrateParams.apply(h0, kap, nt, p, sim_, 0.0, t1_s, steps, every)
         return (hT * hT).sum(dim=0).mul(bore).sum() / nb
 
     kap = kap0.clone().requires_grad_(True)
     nt = torch.tensor(float(cfg["n_power"]), dtype=torch.float64, requires_grad=True)
-    hT = sag.IntegrateParams.apply(h0, kap, nt, p0, s, 0.0, t1_s, steps, every)
+    pt = p0.clone().requires_grad_(True)
+    hT = sag.IntegrateParams.apply(h0, kap, nt, pt, s, 0.0, t1_s, steps, every)
     L = (hT * hT).sum(dim=0).mul(bore).sum() / nb
     L.backward()
-    g_jc, g_n = float((kap.grad * kap0).sum()), float(nt.grad)
+    kbar = kap.grad
+    g_jc, g_n = float((kbar * kap0).sum()), float(nt.grad)
+    g_th = float(torch.dot(pt.grad.double().cpu(), torch.tensor(
+        [amp * math.cos(theta), 0.0, -amp * math.sin(theta)], dtype=torch.float64)))
+    iz, iy, ix = np.unravel_index(int(torch.argmax(kbar.abs())), kbar.shape)
+    g_vox = float(kbar[iz, iy, ix])
     eps = 1e-6
     with torch.no_grad():
         fd_jc = (float(loss(s, kap0 * (1 + eps))) - float(loss(s, kap0 * (1 - eps)))) / (2 * eps)
         n0 = cfg["n_power"]
         fd_n = (float(loss(make(n0 * (1 + eps)), kap0)) - float(loss(make(n0 * (1 - eps)), kap0))) / (2 * n0 * eps)
+        fd_th = (float(loss(s, kap0, p_of(theta + eps))) - float(loss(s, kap0, p_of(theta - eps)))) / (2 * eps)
+        dk = torch.zeros_like(kap0)
+        dk[iz, iy, ix] = eps * float(kap0[iz, iy, ix])
+        fd_vox = (float(loss(s, kap0 + dk)) - float(loss(s, kap0 - dk))) / (2 * float(dk[iz, iy, ix]))
     print("dL/dln(jc) adjoint %.9e fd %.9e; dL/dn adjoint %.9e fd %.9e" % (g_jc, fd_jc, g_n, fd_n))
+    print("dL/dtheta adjoint %.9e fd %.9e; dL/dkappa[%d,%d,%d] adjoint %.9e fd %.9e"
+          % (g_th, fd_th, iz, iy, ix, g_vox, fd_vox))
     assert abs(g_jc - fd_jc) <= 1e-4 * abs(fd_jc)
     assert abs(g_n - fd_n) <= 1e-4 * abs(fd_n)
+    assert abs(g_th - fd_th) <= 1e-4 * abs(fd_th)
+    assert abs(g_vox - fd_vox) <= 1e-4 * abs(fd_vox)
     assert math.isfinite(float(L.detach()))
