@@ -721,7 +721,7 @@ def copy_calibration(nbytes=256 << 20, reps=5):
         e1.record()
     torch.cuda.synchronize()
     ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)[reps // 2]
-    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 2 * reps,
+    print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 2 * reps, "timed_launches": reps,
                       "median_ms": round(ms, 4), "read_plus_write_GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}))
 
 
@@ -744,7 +744,12 @@ def profile_leg(leg, cfg, calls=6):
     for _ in range(calls):
         sim.rhs_eval(t, h, hd)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_leg": leg, "rhs_calls": calls}))
+    # one more call with the library's per-dispatch events: its byte model per
+    # launch of each kind, which the counter summaries divide the HBM bytes by
+    pk = kernel_profile(sim, lambda: sim.rhs_eval(t, h, hd))
+    print(json.dumps({"profile_leg": leg, "rhs_calls": calls + 1,
+                      "bytes_per_launch": {k: v["bytes_per_launch"] for k, v in pk.items()},
+                      "launches_per_call": {k: v["launches"] for k, v in pk.items()}}))
 
 
 def timed_steps(sim, h, steps, warmup):
