@@ -224,7 +224,11 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
-  const int q0 = (int)blockIdx.x * COLS;
+  // blocks go to the 8 XCDs in turn; a column group of 64 bytes shares its
+  // 128-byte lines with the next group: run the two on the same XCD
+  int bx = (int)blockIdx.x;
+  if (COLS * (int)sizeof(C2<T>) < 128 && gridDim.x % 8 == 0) bx = (bx % 8) * (int)(gridDim.x / 8) + bx / 8;
+  const int q0 = bx * COLS;
   const int q = q0 + col;
   const bool valid = q < ny * M;
   C2<T>* p = main + q;
