@@ -32,7 +32,8 @@ DT_STEP = 1e-8            # s: fixed step of the timed integration
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rhs_passes_cup128_f64_hbm_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1803_01346_amd", "csrc", f) for f in ("fft_core.h", "passes.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1803_01346_amd", "csrc", f)
+                  for f in ("fft_core.h", "internal.h", "tuning.h", "passes.hip")]
 
 
 def measured_traffic(kind):
