@@ -400,8 +400,13 @@ __device__ __forceinline__ void power_law_aniso(T& a, T& b, T& c, T wx, T wy, T 
 // (blockIdx.y), for the steps that act on each component alone.
 // EV: elements-per-thread bound of the row transform (0: the default of the
 // op, ex_max); the schedule autotuner may pick the alternate one.
+// The FP64 power-law pass on rows up to 128 is held to 4 waves per SIMD (128
+// VGPRs): its 4096 waves at 128^3 then fit one round of the chip instead of
+// 1.33 (at 146 VGPRs, 3 waves per SIMD); it spills 28 bytes per lane and is
+// still faster (23.9 vs 25.8 us).  The same bound on X_HIN measured slower.
 template <typename T, int NX, int OP, int NC, int EV = 0>
-__global__ __launch_bounds__(kBlock) void xpass_kernel(Plan<T> P0, XArgs<T> A0) {
+__global__ __launch_bounds__(kBlock, (sizeof(T) == 8 && OP == X_LAW && NC == 3 && NX <= 128) ? 4 : 1) void xpass_kernel(
+    Plan<T> P0, XArgs<T> A0) {
   if (P0.stop && *P0.stop) return;  // uniform: the iteration has stopped
   Plan<T> P = P0;
   P.main += blockIdx.z * P0.zs_main;        // instance of a batched launch
