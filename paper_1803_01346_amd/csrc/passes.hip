@@ -35,12 +35,9 @@ static void launch(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime t, Args
     hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
 
-// Elements per thread of each pass kind (tuning.h); the FP64 per-component
-// masks and updates run shorter lines than the other per-component steps.
+// Elements per thread of each pass kind (tuning.h).
 template <typename T, int NC = 3, int OP = -1>
 constexpr int ex_max() {
-  if (NC == 1 && sizeof(T) == 8 && (OP == X_UPDATE || OP == X_UPDATE_LAST || OP == X_MASK))
-    return tune::kEx1UpdF64;
   return NC == 1 ? (sizeof(T) == 8 ? tune::kEx1F64 : tune::kEx1F32)
                  : (sizeof(T) == 8 ? tune::kEx3F64 : tune::kEx3F32);
 }

@@ -276,6 +276,8 @@ BoxPlans<T> box_plans_for(const int lo[3], const int hi[3], const Plan<T>& p, bo
   b.xy_box.r.zhi = z1;
   b.xy_box.r.izlo = z0;
   b.xy_box.r.izhi = z1;
+  b.xy_box.r.xylo = y0;  // the mask step transforms only the box rows
+  b.xy_box.r.xyhi = y1;
   b.xy_hin.r.izlo = z0;
   b.xy_hin.r.izhi = z1;
   return b;
@@ -455,7 +457,7 @@ double bytes_xy(const scfft_ctx* c, const Plan<T>& p, int op, const XArgs<T>& a)
     case XY_FWD: return (a.in2 ? 2.0 : 1.0) * planes * p.ny * p.nx * node + planes * spec;
     case XY_HIN: return inv_planes * spec + planes * mask + (a.warm ? nout * frac * node : 0.0) +
                         (a.track ? all : nin) * frac * node + planes * spec;
-    case XY_MASK: return inv_planes * spec + planes * mask + planes * spec;
+    case XY_MASK: return inv_planes * spec + planes * mask * (p.r.xyhi - p.r.xylo) / p.ny + planes * spec;
     case XY_UPDATE: return inv_planes * spec + planes * mask + nin * frac * node + planes * spec;
     case XY_UPDATE_LAST: return inv_planes * spec + planes * mask +
                                 (a.warm_out ? 2.0 : 1.0) * nout * frac * node;

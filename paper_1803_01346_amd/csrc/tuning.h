@@ -11,10 +11,8 @@ namespace tune {
 // Elements per thread (an upper bound; also the largest radix) of one line.
 constexpr int kEx3F64 = 4;     // X passes holding all three components (power law, moment,
 constexpr int kEx3F32 = 4;     //   adaptive update, reverse mode)
-constexpr int kEx1F64 = 8;     // per-component X passes (input, warm start, store, reverse mode)
-constexpr int kEx1F32 = 8;
-constexpr int kEx1UpdF64 = 4;  // FP64 per-component masks and exterior updates: shorter lines,
-                               //   more rows per block (measured faster)
+constexpr int kEx1F64 = 4;     // per-component X passes (input, warm start, masks, updates,
+constexpr int kEx1F32 = 4;     //   store, reverse mode): shorter lines, more rows per block
 constexpr int kEyF64 = 4;      // Y passes (one component per column); FP64: 8 lanes of a
 constexpr int kEyF32 = 8;      //   16 KB tile hold 8 blocks per CU (4 with 8 elements)
 constexpr int kEzF64 = 4;      // Z passes (three components of a column in registers)
@@ -22,7 +20,7 @@ constexpr int kEzF32 = 8;
 
 // Column passes exchange through two alternating LDS buffers (one barrier per
 // exchange) where that does not cost occupancy: the Z pass; the Y pass keeps
-// one buffer (its 8-element FP64 tile would double to 64 KB).
+// one buffer (two would halve its blocks per CU).
 constexpr bool kPingPongY = false;
 constexpr bool kPingPongZ = true;
 

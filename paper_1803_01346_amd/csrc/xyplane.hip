@@ -183,7 +183,7 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
 #pragma unroll
   for (int r = 0; r < G::RX; ++r) {
     const int y = r * G::GX + gx;
-    const bool ok = y < NY;
+    const bool ok = y < NY && (OP != XY_MASK || (y >= P.r.xylo && y < P.r.xyhi));
     uint32_t bits = 0;
     if constexpr (NEED_CHI) {
       const uint16_t* chp =
@@ -264,6 +264,13 @@ __global__ __launch_bounds__(xy_block<T>()) void xyplane_kernel(Plan<T> P0, XArg
     const int y = r * G::GX + gx;
     if (y < NY) {
       C2<T>* row = plane + y * RS;
+      if constexpr (OP == XY_MASK) {
+        if (y < P.r.xylo || y >= P.r.xyhi) {  // chi = 0 on rows outside the box: a zero row
+#pragma unroll
+          for (int m = 0; m < E; ++m) row[j + m * TPT] = C2<T>{T(0), T(0)};
+          continue;
+        }
+      }
       T a[2 * E];
       if constexpr (HAS_INV) {
         row_c2r<T, NX, NY>(row, j, twx, a);
