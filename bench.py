@@ -664,26 +664,41 @@ def cpu_baseline(cfg, h_np, calls=3):
     """The oracle's rhs_eval (plain NumPy FP64, its own radix-2 FFT) on the
     same 128^3 state with 3 exterior iterations: median of `calls` full
     calls, BLAS and OpenMP pools held to one thread (NumPy's elementwise work
-    is single-threaded).  Beside it, as context, the multi-core scipy.fft
-    right-hand side (ScipyRhs) on all usable threads, median of 3."""
+    is single-threaded); the same protocol on the 32^3 cube and the 64^3 cup
+    beside it.  Also, as context, the multi-core scipy.fft right-hand side
+    (ScipyRhs) on all usable threads, median of 3."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import geometry, grid, rhs, units
+    from paper_1803_01346_amd import workloads
 
-    g = grid.Grid(cfg["n"], cfg["half_width"])
-    chi = geometry.voxelize(g, cfg["shapes"])
-    u = units.Units(cfg["jc"], cfg["l_m"])
-    d = dict(cfg["drive"])
-    drive = units.Drive(u, d.pop("kind"), **d)
-    prob = rhs.Problem(g, chi, cfg["n_power"], cfg["rho_out"], drive, rhs.RhsOptions(fixed_iter=FIXED_ITER))
-    ts = []
-    with threadpool_limits(1):
-        for _ in range(calls):
-            t = time.perf_counter()
-            rhs.rhs_eval(prob, T_STAR / u.t0, h_np)
-            ts.append(time.perf_counter() - t)
-            print("bench: oracle call %.1f s" % ts[-1], file=sys.stderr, flush=True)
-    med = float(np.median(ts))
+    def problem(c):
+        g = grid.Grid(c["n"], c["half_width"])
+        chi = geometry.voxelize(g, c["shapes"])
+        u = units.Units(c["jc"], c["l_m"])
+        d = dict(c["drive"])
+        drive = units.Drive(u, d.pop("kind"), **d)
+        return rhs.Problem(g, chi, c["n_power"], c["rho_out"], drive, rhs.RhsOptions(fixed_iter=FIXED_ITER)), u, g, chi, drive
+
+    def median_calls(prob, t, h):
+        ts = []
+        with threadpool_limits(1):
+            for _ in range(calls):
+                t0 = time.perf_counter()
+                rhs.rhs_eval(prob, t, h)
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts
+
+    # the smaller boxes of the same protocol: the 32^3 cube and the 64^3 cup
+    smaller = {}
+    for name in ("cube32", "cup64"):
+        c = workloads.config(name)
+        pr, uu, _, _, _ = problem(c)
+        m, _ = median_calls(pr, T_STAR / uu.t0, workloads.synthetic_state(c, seed=0))
+        smaller["%d^3" % c["n"][0]] = dict(workload=name, rhs_per_s=round(1.0 / m, 3), median_s=round(m, 3))
+    prob, u, g, chi, drive = problem(cfg)
+    med, ts = median_calls(prob, T_STAR / u.t0, h_np)
+    print("bench: oracle calls %s s" % ", ".join("%.1f" % x for x in ts), file=sys.stderr, flush=True)
     host = host_cpu()
     f = ScipyRhs(cfg["n"], cfg["half_width"], chi, cfg["n_power"], cfg["rho_out"], FIXED_ITER,
                  workers=host["nproc"])
@@ -698,7 +713,7 @@ def cpu_baseline(cfg, h_np, calls=3):
                 sample="the oracle's rhs_eval at 128^3 (cup shield, FP64, 3 exterior iterations, own "
                        "radix-2 FFT), median of %d full calls (%s s), one thread"
                        % (calls, ", ".join("%.1f" % x for x in ts)),
-                host_cpu=host["model"], host_nproc=host["nproc"],
+                host_cpu=host["model"], host_nproc=host["nproc"], smaller_boxes=smaller,
                 context_scipy_fft=dict(value=round(1.0 / float(np.median(tq)), 4), unit="RHS evals/s",
                                        workers=host["nproc"], kind="scipy.fft rfftn/irfftn, FP64",
                                        sample="median of 3 calls at 128^3 after one warm-up call"))
