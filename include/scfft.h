@@ -141,15 +141,16 @@ typedef struct {
  *                transforms.  Results are identical.
  *   x_alt        0 (default) or 1: the per-component x passes (input, warm
  *                start, masks, exterior update with fixed_iter, store) hold
- *                the alternate number of elements per thread (4 instead of 8,
- *                or 8 instead of 4: other radices and rows per block).
- *                Results agree to rounding; scfft_autotune picks it.
+ *                the alternate number of elements per thread (8 instead of 4:
+ *                other radices and rows per block).  Results agree to
+ *                rounding; scfft_autotune picks it.
  *   y_alt, z_alt 0 (default) or 1: the y passes, and the z passes with the
  *                operator symbols, hold the alternate number of elements per
- *                thread (y: 4 instead of 8; z: 8 instead of 4 in FP64, 4
- *                instead of 8 in FP32), i.e. other radix sequences, column
- *                widths per block and register budgets.  Results agree to
- *                rounding; scfft_autotune picks them. */
+ *                thread (y: 8 instead of 4 in FP64, 4 instead of 8 in FP32;
+ *                z: 8 instead of 4 in FP64, 4 instead of 8 in FP32), i.e.
+ *                other radix sequences, column widths per block and register
+ *                budgets.  Results agree to rounding; scfft_autotune picks
+ *                them. */
 typedef struct {
   double delta_it;
   int32_t min_iter;
