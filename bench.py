@@ -205,6 +205,41 @@ def converged_leg(cfg, h, calls=20):
                 delta_it=2e-5, calls=calls)
 
 
+def batch128_leg(calls=40):
+    """Same-size batches of the 128^3 shield (one launch per pass over the
+    members, instance = blockIdx.z; members differ in n and in their seeded
+    states): 4 members in FP64, 6 in FP32.  Aggregate right-hand sides per
+    second over `calls` back-to-back batched calls (3 exterior iterations)
+    and the library's bytes of one batched call against the HBM peak."""
+    import torch
+    from paper_1803_01346_amd import scfft, workloads
+    out = {}
+    base = workloads.config("cup128")
+    for prec, name, k in ((scfft.F64, "f64", 4), (scfft.F32, "f32", 6)):
+        dt = torch.float64 if prec == scfft.F64 else torch.float32
+        cfgs = [dict(base, n_power=base["n_power"] - 5 * i) for i in range(k)]
+        b = scfft.Batch(cfgs, precision=prec, rhs_opts=scfft.default_rhs_opts(fixed_iter=FIXED_ITER))
+        h = torch.stack([torch.from_numpy(workloads.synthetic_state(c, seed=i, background=(0.0, 0.0, 0.01)))
+                         .to(dtype=dt) for i, c in enumerate(cfgs)]).cuda().contiguous()
+        hd = b.empty_field()
+        pk = kernel_profile(b.sims[0], lambda: b.rhs_eval(T_STAR, h, hd))
+        nbytes = sum(v["bytes_per_launch"] * v["launches"] for v in pk.values())
+        for _ in range(5):
+            b.rhs_eval(T_STAR, h, hd)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(calls):
+            b.rhs_eval(T_STAR, h, hd)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / calls
+        out[name] = dict(instances=k, rhs_per_s=round(k / el, 1), bytes_per_batched_call=int(nbytes),
+                         achieved_GBs=round(nbytes / el / 1e9, 1), frac=round(nbytes / el / (HBM_PEAK_GBS * 1e9), 4))
+        b.close()
+        del h, hd
+        torch.cuda.empty_cache()
+    return out
+
+
 def lens256_leg(calls=30):
     """The 256^3 lens box in FP32 (working set beyond the 256 MB last-level
     cache: the HBM regime): RHS/s with 3 exterior iterations and the
@@ -875,6 +910,8 @@ def main():
     adj = None if args.no_adjoint else adjoint_leg(cfg)
     print("bench: batch leg", file=sys.stderr, flush=True)
     gleg = None if args.no_graph else graph_leg()
+    print("bench: same-size 128^3 batch leg", file=sys.stderr, flush=True)
+    b128 = None if args.no_graph else batch128_leg()
     extras = None
     if args.extras:
         extras = {"shield": shield_leg(), "lens_config": lens_config_leg(), "shield_config": shield_config_leg(),
@@ -912,6 +949,7 @@ def main():
         "lens256_f32": lens,
         "adjoint_cost": adj,
         "graphs": gleg,
+        "batch128": b128,
         "extras": extras,
         "roofline": roof,
         "kernels": per_kind,
