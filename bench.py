@@ -776,7 +776,7 @@ def copy_calibration(nbytes=256 << 20, reps=5):
                       "median_ms": round(ms, 4), "read_plus_write_GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}))
 
 
-def profile_leg(leg, cfg, calls=6):
+def profile_leg(leg, cfg, calls=20, warm_s=0.5):
     """A few right-hand sides of one leg only, for a kernel trace or counter
     run under rocprofv3 (f64 / f32: the 128^3 shield; lens: the 256^3 lens)."""
     import torch
@@ -792,13 +792,22 @@ def profile_leg(leg, cfg, calls=6):
         h, _ = initial_state(sim, cfg)
         t = T_STAR
     hd = sim.empty_field()
+    # warm_s seconds of the same calls first (clocks and caches settle; a
+    # kernel trace leaves them out), then the `calls` calls a summary keeps
+    warm = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(10):
+            sim.rhs_eval(t, h, hd)
+        torch.cuda.synchronize()
+        warm += 10
     for _ in range(calls):
         sim.rhs_eval(t, h, hd)
     torch.cuda.synchronize()
     # one more call with the library's per-dispatch events: its byte model per
     # launch of each kind, which the counter summaries divide the HBM bytes by
     pk = kernel_profile(sim, lambda: sim.rhs_eval(t, h, hd))
-    print(json.dumps({"profile_leg": leg, "rhs_calls": calls + 1,
+    print(json.dumps({"profile_leg": leg, "warm_calls": warm, "rhs_calls": calls + 1,
                       "bytes_per_launch": {k: v["bytes_per_launch"] for k, v in pk.items()},
                       "launches_per_call": {k: v["launches"] for k, v in pk.items()}}))
 
@@ -832,6 +841,8 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the paper's shield and lens runs (lens gain, shield cases, "
                          "two-period shield, 256^3 lens ramp)")
+    ap.add_argument("--profile-warm", type=float, default=0.5,
+                    help="seconds of right-hand sides before the profiled ones (0 for counter runs)")
     ap.add_argument("--profile-leg", choices=["f64", "f32", "lens"],
                     help="only run a few right-hand sides of one leg (for rocprofv3)")
     ap.add_argument("--copy-calibration", type=int, nargs="?", const=256 << 20, default=None,
@@ -852,7 +863,7 @@ def main():
     torch.cuda.set_device(0)
     cfg = workloads.config(args.config)
     if args.profile_leg:
-        profile_leg(args.profile_leg, cfg)
+        profile_leg(args.profile_leg, cfg, warm_s=args.profile_warm)
         return
 
     sim = make_sim(cfg, scfft.F64, FIXED_ITER)
