@@ -322,4 +322,189 @@ struct LdsRows {
   __device__ __forceinline__ void after_load() { sync(); }
 };
 
+// ---- column transform with lane-swapped index bits (gfx950) ----
+//
+// A column of N = 2^n points held by TPT = N / E lanes, E = 2^RB elements
+// each, in a block whose lane index is j * COLS + column (COLS = 8 or 16, so
+// the low JL = 3 or 2 bits of j sit in lane bits 3..5 or 4..5 and the rest of
+// j selects the wavefront).  The transform is a decimation-in-frequency FFT
+// taken as steps over groups of index bits, each step a radix-2^b DFT over
+// bits that a lane holds in its registers, followed by its twiddles:
+//   step 1: the top RB bits (radix E);
+//   lane swaps: the two bits on lane bits 5 and 4 trade places with register
+//     bits RB-1 and RB-2 (v_permlane32_swap / v_permlane16_swap, a 2 x 2
+//     transpose of two registers across two halves of the lane range);
+//   step 2: those two bits (radix 4);
+//   one LDS exchange: the remaining P2 low bits (held by lane bit 3 and the
+//     wavefront index) move to the top register bits and, where RB < P2,
+//     lane bits 5 and 4;
+//   step 3: radix 2^B3 over the register bits; where B4 = P2 - B3 > 0, lane
+//     swaps once more and step 4 (radix 2^B4, no twiddles).
+// A step over index bits [s, s + b) of a length-L sub-transform leaves its
+// output digit k in those bits, times w_L^(lo k) with lo the index bits below
+// s; digits come out lowest first, so the frequency of the element at final
+// position z is read off its bit fields (freq()).  The output stays in that
+// order; the inverse runs the transposed steps in reverse order (twiddles
+// before each DFT, decimation in time), conjugated on entry and exit, and
+// returns to natural order, so a pointwise product between the two needs no
+// reordering.  Against the Stockham passes (three LDS round trips per
+// 128-point transform with four elements per lane) this takes one.
+__host__ __device__ constexpr int ilog2_exact(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return (1 << r) == x ? r : -1;
+}
+
+template <typename T, int N, int E, int COLS>
+struct LaneCol {
+  static constexpr int n = ilog2_exact(N), RB = ilog2_exact(E), JL = 6 - ilog2_exact(COLS);
+  static constexpr int WB = n - RB - JL;  // j bits above the lane bits (wavefront index)
+  static constexpr int P2 = WB + JL - 2;  // index bits left for the steps after the exchange
+  static constexpr int B3 = RB < P2 ? RB : P2, B4 = P2 - B3;
+  static constexpr bool ok = n > 0 && (E == 4 || E == 8) && (COLS == 8 || COLS == 16) && WB >= 0 &&
+                             P2 >= 1 && B4 <= 2;
+
+  __device__ __forceinline__ static int jb(int j, int b) { return (j >> b) & 1; }
+  __device__ __forceinline__ static int l4(int j) { return jb(j, JL - 2); }  // j bit on lane bit 4
+  __device__ __forceinline__ static int l5(int j) { return jb(j, JL - 1); }  // j bit on lane bit 5
+  // natural index of element m of lane j (load and store order)
+  __device__ __forceinline__ static int pos_a(int j, int m) {
+    return (m << (n - RB)) + ((j & ((1 << JL) - 1)) << WB) + (j >> JL);
+  }
+  // index held by (j, m) after the first lane swaps
+  __device__ __forceinline__ static int pos_a2(int j, int m) {
+    int z = (((m >> (RB - 1)) & 1) << (P2 + 1)) | (((m >> (RB - 2)) & 1) << P2);
+    if constexpr (RB > 2) z |= (m & ((1 << (RB - 2)) - 1)) << (n - RB);
+    z |= (l5(j) << (n - 1)) | (l4(j) << (n - 2)) | (j >> JL);
+    if constexpr (JL == 3) z |= (j & 1) << WB;
+    return z;
+  }
+  // lane-bit part of the indices after the exchange (the low B4 bits)
+  __device__ __forceinline__ static int lrem(int j) {
+    return B4 == 1 ? l5(j) : (B4 == 2 ? 2 * l5(j) + l4(j) : 0);
+  }
+  // index held by (j, m) after the exchange: the finished top RB + 2 bits F
+  // come from the wavefront index, lane bit 3, the lane bits and register
+  // bits the last steps leave free
+  __device__ __forceinline__ static int pos_b(int j, int m) {
+    int f = j >> JL, w = WB;
+    if constexpr (JL == 3) { f |= (j & 1) << w; w += 1; }
+    if constexpr (B4 == 0) { f |= (l4(j) << w) | (l5(j) << (w + 1)); w += 2; }
+    if constexpr (B4 == 1) { f |= l4(j) << w; w += 1; }
+    if constexpr (RB > B3) f |= (m & ((1 << (RB - B3)) - 1)) << w;
+    return (f << P2) + ((m >> (RB - B3)) << (P2 - B3)) + lrem(j);
+  }
+  // frequency of the element (j, m) after the forward transform
+  __device__ __forceinline__ static int freq(int j, int m) {
+    int jj = j, mm = m;
+    if constexpr (B4 >= 1) {
+      jj = (jj & ~(1 << (JL - 1))) | (((m >> (RB - 1)) & 1) << (JL - 1));
+      mm = (mm & ~(1 << (RB - 1))) | (l5(j) << (RB - 1));
+    }
+    if constexpr (B4 == 2) {
+      jj = (jj & ~(1 << (JL - 2))) | (((m >> (RB - 2)) & 1) << (JL - 2));
+      mm = (mm & ~(1 << (RB - 2))) | (l4(j) << (RB - 2));
+    }
+    const int z = pos_b(jj, mm);
+    return (z >> (n - RB)) + E * ((z >> P2) & 3) + 4 * E * ((z >> (P2 - B3)) & ((1 << B3) - 1)) +
+           4 * E * (1 << B3) * (z & ((1 << B4) - 1));
+  }
+
+  // 2 x 2 transpose of registers x, y across lane bit LB (4 or 5): lanes with
+  // the bit clear keep x and take the partner's x into y; lanes with it set
+  // keep y and take the partner's y into x
+  template <int LB>
+  __device__ __forceinline__ static void swap_words(unsigned& x, unsigned& y) {
+    if constexpr (LB == 5) {
+      const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+      x = r[0];
+      y = r[1];
+    } else {
+      const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+      x = r[0];
+      y = r[1];
+    }
+  }
+  template <int LB>
+  __device__ __forceinline__ static void swap_pair(C2<T>& x, C2<T>& y) {
+    struct Words { unsigned w[sizeof(C2<T>) / 4]; };
+    Words a = __builtin_bit_cast(Words, x), b = __builtin_bit_cast(Words, y);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(C2<T>) / 4); ++i) swap_words<LB>(a.w[i], b.w[i]);
+    x = __builtin_bit_cast(C2<T>, a);
+    y = __builtin_bit_cast(C2<T>, b);
+  }
+  // lane bit LB <-> register bit RBIT
+  template <int LB, int RBIT>
+  __device__ __forceinline__ static void swap_bit(C2<T> (&v)[E]) {
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      if (((m >> RBIT) & 1) == 0) swap_pair<LB>(v[m], v[m | (1 << RBIT)]);
+  }
+
+  // DFT over register bits [SH, SH + B) with twiddles tw[lo * k] on output k
+  // (PRE: on input k, the transposed step)
+  template <int SH, int B, bool PRE, bool TW>
+  __device__ __forceinline__ static void step(C2<T> (&v)[E], const C2<T>* tw, int lo) {
+    constexpr int R = 1 << B;
+#pragma unroll
+    for (int o = 0; o < E; ++o) {
+      if (((o >> SH) & (R - 1)) != 0) continue;
+      C2<T> a[R];
+#pragma unroll
+      for (int d = 0; d < R; ++d) a[d] = v[o | (d << SH)];
+      if constexpr (TW && PRE) {
+#pragma unroll
+        for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw[lo * k]);
+      }
+      dftR<T, R>(a);
+      if constexpr (TW && !PRE) {
+#pragma unroll
+        for (int k = 1; k < R; ++k) a[k] = cmul(a[k], tw[lo * k]);
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[o | (k << SH)] = a[k];
+    }
+  }
+
+  // buf: this transform's LDS buffer (N * COLS elements); the caller
+  // alternates two buffers between transforms, so each exchange needs one
+  // block barrier.  tw: exp(-2 pi i k / N), k < N, readable by the block.
+  __device__ __forceinline__ static void exchange_ab(C2<T> (&v)[E], int j, int col, C2<T>* buf, bool to_b) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) buf[(to_b ? pos_a2(j, m) : pos_b(j, m)) * COLS + col] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = buf[(to_b ? pos_b(j, m) : pos_a2(j, m)) * COLS + col];
+  }
+  __device__ __forceinline__ static void forward(C2<T> (&v)[E], int j, int col, C2<T>* buf, const C2<T>* tw) {
+    const int lo2 = ((j & ((1 << (JL - 2)) - 1)) << WB) + (j >> JL);
+    step<0, RB, false, true>(v, tw, pos_a(j, 0));
+    swap_bit<5, RB - 1>(v);
+    swap_bit<4, RB - 2>(v);
+    step<RB - 2, 2, false, true>(v, tw, lo2 * E);
+    exchange_ab(v, j, col, buf, true);
+    step<RB - B3, B3, false, (B4 > 0)>(v, tw, lrem(j) * 4 * E);
+    if constexpr (B4 >= 1) swap_bit<5, RB - 1>(v);
+    if constexpr (B4 == 2) swap_bit<4, RB - 2>(v);
+    if constexpr (B4 >= 1) step<RB - B4, B4, false, false>(v, tw, 0);
+  }
+  __device__ __forceinline__ static void inverse(C2<T> (&v)[E], int j, int col, C2<T>* buf, const C2<T>* tw) {
+    const int lo2 = ((j & ((1 << (JL - 2)) - 1)) << WB) + (j >> JL);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+    if constexpr (B4 >= 1) step<RB - B4, B4, true, false>(v, tw, 0);
+    if constexpr (B4 == 2) swap_bit<4, RB - 2>(v);
+    if constexpr (B4 >= 1) swap_bit<5, RB - 1>(v);
+    step<RB - B3, B3, true, (B4 > 0)>(v, tw, lrem(j) * 4 * E);
+    exchange_ab(v, j, col, buf, false);
+    step<RB - 2, 2, true, true>(v, tw, lo2 * E);
+    swap_bit<4, RB - 2>(v);
+    swap_bit<5, RB - 1>(v);
+    step<0, RB, true, true>(v, tw, pos_a(j, 0));
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+  }
+};
+
 }  // namespace scfft

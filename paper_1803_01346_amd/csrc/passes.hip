@@ -197,6 +197,23 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
   d = {-cz.y * f, cz.x * f};
 }
 
+// Load through a buffer resource (base, size in bytes; gfx9 word 3): an offset
+// at or past the size reads zero without touching memory.  Masked elements
+// then need no branch, and a wave's loads stay in one straight line whose
+// completions the compiler counts one by one, so a transform starts as soon
+// as its own component has arrived.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr unsigned kBufMiss = 0x80000000u;  // past every array the Z pass reads (< 2 GiB)
+template <typename T>
+__device__ __forceinline__ C2<T> buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(C2<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(C2<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 // FP64 default: at least 4 waves per SIMD, i.e. 4 blocks of 256 threads per
 // CU, so the 1024 blocks of a 128 x 128 x 64 half spectrum run in one round on
 // 256 CUs.  EV: elements-per-thread bound (0: ez_max; the alternate, a rhs
@@ -214,10 +231,23 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   constexpr int E = elems_per_thread(NZ, EV ? EV : ez_max<T>());
   constexpr int TPT = NZ / E;
   constexpr int COLS = z_block<T, NZ, EV>() / TPT;
+  constexpr int BLOCK = z_block<T, NZ, EV>();
+  // lane-swapped column transform where its layout fits (powers of two), else
+  // Stockham passes; the former keeps its output in scrambled order
+  using LC = LaneCol<T, NZ, E, COLS>;
+  constexpr bool kLane = LC::ok && tune::kPingPongZ;
   __shared__ C2<T> smem[(tune::kPingPongZ ? 2 : 1) * NZ * COLS];
   __shared__ C2<T> twl[NZ];
-  LdsTwiddles<T, NZ, z_block<T, NZ, EV>()> twd;
-  twd.fetch(tz.tw);
+  LdsTwiddles<T, NZ, BLOCK> twd;
+  C2<T> twr[(NZ + BLOCK - 1) / BLOCK];
+  if constexpr (kLane) {
+    const __amdgpu_buffer_rsrc_t rt = buffer_of(tz.tw, NZ * sizeof(C2<T>));
+#pragma unroll
+    for (int k = 0; k < (NZ + BLOCK - 1) / BLOCK; ++k)
+      twr[k] = buffer_load<T>(rt, (unsigned)((((int)threadIdx.x + k * BLOCK) & (NZ - 1)) * sizeof(C2<T>)));
+  } else {
+    twd.fetch(tz.tw);
+  }
   const int tid = threadIdx.x;
   const int col = tid % COLS;
   const int j = tid / COLS;
@@ -242,19 +272,47 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   }
   const int qa = (ny / 2) * M;                      // the second packed column
   const bool pk_block = q0 == 0 || (q0 <= qa && qa < q0 + COLS);  // uniform per block
+  // z of element m on load and store; kz of element m after the forward transform
+  auto zpos = [&](int m) {
+    if constexpr (kLane) return LC::pos_a(j, m);
+    else return j + m * TPT;
+  };
+  auto kpos = [&](int m) {
+    if constexpr (kLane) return LC::freq(j, m);
+    else return j + m * TPT;
+  };
   C2<T> v[3][E];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int z = j + m * TPT;
-      v[c][m] = (valid && z >= R.zlo && z < R.zhi) ? p[c * cs + (size_t)z * es]
-                                                   : C2<T>{T(0), T(0)};
-    }
   ColLds<tune::kPingPongZ, T, NZ, COLS> lds{smem, col};
-  twd.put(twl);  // read from the transform's second pass on (block barriers between passes)
+  if constexpr (kLane) {
+    const size_t qc = valid ? (size_t)q : 0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, twl, 1);
+    for (int c = 0; c < 3; ++c) {
+      const __amdgpu_buffer_rsrc_t rc = buffer_of(main + c * cs, cs * sizeof(C2<T>));
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int z = zpos(m);
+        const bool ok = valid && z >= R.zlo && z < R.zhi;
+        v[c][m] = buffer_load<T>(rc, ok ? (unsigned)(((size_t)z * es + qc) * sizeof(C2<T>)) : kBufMiss);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < (NZ + BLOCK - 1) / BLOCK; ++k) twl[((int)threadIdx.x + k * BLOCK) & (NZ - 1)] = twr[k];
+    __syncthreads();  // the first step reads twiddles
+#pragma unroll
+    for (int c = 0; c < 3; ++c) LC::forward(v[c], j, col, smem + (c & 1) * NZ * COLS, twl);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int z = j + m * TPT;
+        v[c][m] = (valid && z >= R.zlo && z < R.zhi) ? p[c * cs + (size_t)z * es]
+                                                     : C2<T>{T(0), T(0)};
+      }
+    twd.put(twl);  // read from the transform's second pass on (block barriers between passes)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, twl, 1);
+  }
 
   // Packed columns P = A + i B: with A = (P + conj P(-k)) / 2 on the kx = 0
   // plane and B = (P - conj P(-k)) / 2i on the Nyquist plane, and both planes
@@ -265,7 +323,7 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
     T fa[E], fb[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kz = j + m * TPT;
+      const int kz = kpos(m);
       const T f0 = packed ? zsym_factor<T, SYM>(tx, ty, tz, 0, ky, kz, coef) : T(0);
       const T fm = packed ? zsym_factor<T, SYM>(tx, ty, tz, M, ky, kz, coef) : T(0);
       fa[m] = T(0.5) * (f0 + fm);
@@ -275,12 +333,12 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
     for (int c = 0; c < 3; ++c) {
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < E; ++m) smem[(j + m * TPT) * COLS + col] = v[c][m];
+      for (int m = 0; m < E; ++m) smem[kpos(m) * COLS + col] = v[c][m];
       __syncthreads();
       if (packed) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-          const int kz = j + m * TPT;
+          const int kz = kpos(m);
           const C2<T> w = cconj(smem[(kz == 0 ? 0 : NZ - kz) * COLS + col]);
           v[c][m] = {fa[m] * v[c][m].x + fb[m] * w.x, fa[m] * v[c][m].y + fb[m] * w.y};
         }
@@ -297,7 +355,7 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
     fxy = tx.kk[kx] + ty.kk[ky];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int kz = j + m * TPT;
+    const int kz = kpos(m);
     T f;
     if constexpr (SYM == Z_CURL) {
       f = fxy * tz.sm[kz];
@@ -313,11 +371,14 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   // overlap the inverse transforms of the next ones
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    fft_inverse<T, NZ, E>(v[c], j, lds, twl, 1);
+    if constexpr (kLane)
+      LC::inverse(v[c], j, col, smem + ((c + 1) & 1) * NZ * COLS, twl);
+    else
+      fft_inverse<T, NZ, E>(v[c], j, lds, twl, 1);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int z = j + m * TPT;
+        const int z = zpos(m);
         if (z >= R.zlo_out && z < R.zhi_out) p[c * cs + (size_t)z * es] = v[c][m];
       }
     }
