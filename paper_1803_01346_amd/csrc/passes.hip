@@ -205,7 +205,14 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-constexpr unsigned kBufMiss = 0x80000000u;  // past every array the Z pass reads (< 2 GiB)
+constexpr unsigned kBufMiss = 0x80000000u;  // past every array read through one resource (each < 2 GiB)
+template <typename T>
+__device__ __forceinline__ T buffer_load_real(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 template <typename T>
 __device__ __forceinline__ C2<T> buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
   if constexpr (sizeof(T) == 8)
@@ -502,8 +509,14 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 8 && OP == X_LAW && NC == 3 &
   const size_t csm = (size_t)nrows * M;        // component stride, main spectrum
   const size_t csr = (size_t)nrows * NX;       // component stride, real field
   __shared__ C2<T> twl[NX];
-  LdsTwiddles<T, NX, kBlock> twd;
-  twd.fetch(P.ax.tw);
+  constexpr int NTW = (NX + kBlock - 1) / kBlock;  // table entries per thread (duplicates allowed)
+  C2<T> twr[NTW];
+  {
+    const __amdgpu_buffer_rsrc_t rt = buffer_of(P.ax.tw, NX * sizeof(C2<T>));
+#pragma unroll
+    for (int k = 0; k < NTW; ++k)
+      twr[k] = buffer_load<T>(rt, (unsigned)((((int)threadIdx.x + k * kBlock) % NX) * sizeof(C2<T>)));
+  }
   const C2<T>* tw = twl;                       // exp(-2 pi i k / NX), staged in LDS below
   const int c0 = NC == 3 ? 0 : (int)blockIdx.y;  // first component of this block
   L lds{smem, rl};
@@ -525,45 +538,53 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 8 && OP == X_LAW && NC == 3 &
   const int z = rr / P.ny;
   const size_t rowbase = (size_t)rr * NX;
 
-  // ---- all global loads first, so their latencies overlap ----
+  // ---- all global loads first, so their latencies overlap.  Buffer loads
+  // (an offset past the end reads zero) keep them free of branches, so the
+  // compiler counts their completions one by one; the mask comes first, since
+  // the loads of the real fields that depend on it come last ----
   constexpr bool NEED_CHI = OP != X_FWD && OP != X_STORE;
   constexpr bool NEED_AUX = OP == X_HIN || OP == X_UPDATE || OP == X_UPDATE_LAST || OP >= X_ADJ_START;
-  C2<T> Xs[HAS_INV ? NC : 1][E];
-  C2<T> Xn[NC];
-  // the power law loads its third component's row after the first is transformed
-  constexpr bool LAZY = NC == 3 && OP == X_LAW;
-  auto load_row = [&](int cc) {
-    const int c = c0 + cc;
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-      Xs[cc][m] = inv_row ? P.main[c * csm + (size_t)rr * M + j + m * TPT] : C2<T>{T(0), T(0)};
-    // the kx = 0 slot holds X[0] + i X[M] (both real)
-    Xn[cc] = {Xs[cc][0].y, T(0)};
-    if (j == 0) Xs[cc][0].y = T(0);
-  };
-  if constexpr (HAS_INV) {
-#pragma unroll
-    for (int cc = 0; cc < (LAZY ? 2 : NC); ++cc) load_row(cc);
-  }
   // Nodes x = 2n, 2n+1 of one complex element n are adjacent: the mask and
   // the real fields are read (and stored) two nodes per access.  Measured
   // faster for every FP32 pass and for the FP64 updates; the FP64 input and
   // warm-start passes keep one node per access.
   constexpr bool PAIRED = sizeof(T) == 4 || !(OP == X_FWD || OP == X_HIN);
   uint8_t ch[2 * E];
-  if constexpr (NEED_CHI && !PAIRED) {
+  if constexpr (NEED_CHI) {
+    const __amdgpu_buffer_rsrc_t rc = buffer_of(A.chi, (size_t)nrows * NX);
+    if constexpr (!PAIRED) {
 #pragma unroll
-    for (int e = 0; e < 2 * E; ++e) ch[e] = valid ? A.chi[rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)] : 0;
-  }
-  if constexpr (NEED_CHI && PAIRED) {
-    const uint16_t* chp = reinterpret_cast<const uint16_t*>(A.chi + rowbase);
+      for (int e = 0; e < 2 * E; ++e)
+        ch[e] = __builtin_amdgcn_raw_buffer_load_b8(
+            rc, valid ? (unsigned)(rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)) : kBufMiss, 0, 0);
+    } else {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const unsigned v = valid ? chp[j + m * TPT] : 0u;
-      ch[2 * m] = (uint8_t)(v & 0xffu);
-      ch[2 * m + 1] = (uint8_t)(v >> 8);
+      for (int m = 0; m < E; ++m) {
+        const unsigned v =
+            __builtin_amdgcn_raw_buffer_load_b16(rc, valid ? (unsigned)(rowbase + 2 * (j + m * TPT)) : kBufMiss, 0, 0);
+        ch[2 * m] = (uint8_t)(v & 0xffu);
+        ch[2 * m + 1] = (uint8_t)(v >> 8);
+      }
     }
   }
+  C2<T> Xs[HAS_INV ? NC : 1][E];
+  // the power law loads its third component's row after the first is transformed
+  constexpr bool LAZY = NC == 3 && OP == X_LAW;
+  auto load_row = [&](int cc) {
+    const __amdgpu_buffer_rsrc_t rm = buffer_of(P.main + (c0 + cc) * csm, csm * sizeof(C2<T>));
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      Xs[cc][m] = buffer_load<T>(rm, inv_row ? (unsigned)(((size_t)rr * M + j + m * TPT) * sizeof(C2<T>)) : kBufMiss);
+  };
+  if constexpr (HAS_INV) {
+#pragma unroll
+    for (int cc = 0; cc < (LAZY ? 2 : NC); ++cc) load_row(cc);
+  }
+  // the twiddle table goes to LDS before the loads that wait for the mask are
+  // issued, so the transforms below do not wait for them
+#pragma unroll
+  for (int k = 0; k < NTW; ++k) twl[((int)threadIdx.x + k * kBlock) % NX] = twr[k];
+  __syncthreads();  // row exchanges are wavefront-local: make the table visible to the block
   // X_FWD: the real input (all nodes); X_HIN: the warm start (Omega_out);
   // X_UPDATE*: hdot^i (all nodes when tracking iterates, else Omega only:
   // with a fixed iteration count only hdot_in is read back); X_ADJ_START:
@@ -571,66 +592,65 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 8 && OP == X_LAW && NC == 3 &
   const T* auxp = (OP == X_FWD || OP == X_ADJ_START || OP == X_ADJ_LAW)
                       ? A.in
                       : (OP == X_HIN ? A.warm : A.out);
-  T aux[(NEED_AUX || OP == X_FWD) ? NC : 1][2 * E];
+  constexpr int NA = (NEED_AUX || OP == X_FWD) ? NC : 1;
+  T aux[NA][2 * E];
+  // one resource per component (each below 2 GiB); a null field reads zero
+  auto field_rsrc = [&](const T* f, int cc) {
+    return buffer_of(f ? f + (size_t)(c0 + cc) * csr : nullptr, f ? csr * sizeof(T) : 0);
+  };
   if constexpr ((NEED_AUX || OP == X_FWD) && !PAIRED) {
 #pragma unroll
-    for (int e = 0; e < 2 * E; ++e) {
-      bool need = valid && auxp != nullptr;
-      if constexpr (OP == X_HIN) need = need && ch[e] == 0;
+    for (int cc = 0; cc < NC; ++cc) {
+      const __amdgpu_buffer_rsrc_t ra = field_rsrc(auxp, cc);
+      const __amdgpu_buffer_rsrc_t r2 = field_rsrc(OP == X_FWD ? A.in2 : nullptr, cc);
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1);
-        aux[cc][e] = need ? auxp[ai] : T(0);
-        if constexpr (OP == X_FWD) {
-          if (need && A.in2) aux[cc][e] += A.in2_coef * A.in2[ai];  // stage argument y + c k
-        }
+      for (int e = 0; e < 2 * E; ++e) {
+        bool need = valid && auxp != nullptr;
+        if constexpr (OP == X_HIN) need = need && ch[e] == 0;
+        const unsigned off = need ? (unsigned)((rowbase + 2 * (j + (e >> 1) * TPT) + (e & 1)) * sizeof(T)) : kBufMiss;
+        aux[cc][e] = buffer_load_real<T>(ra, off);
+        if constexpr (OP == X_FWD) aux[cc][e] += A.in2_coef * buffer_load_real<T>(r2, off);  // stage argument y + c k
       }
     }
   }
   if constexpr ((NEED_AUX || OP == X_FWD) && PAIRED) {
-    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    bool need[2 * E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      bool need[2];
+    for (int e = 0; e < 2 * E; ++e) {
+      bool nd = valid && auxp != nullptr;
+      if constexpr (OP == X_HIN) nd = nd && ch[e] == 0;
+      if constexpr (OP == X_UPDATE) nd = nd && (A.track || ch[e] != 0);
+      if constexpr (OP == X_UPDATE_LAST) nd = nd && A.track;
+      if constexpr (OP == X_ADJ_LAW) nd = nd && ch[e] != 0;     // j is read in Omega only
+      need[e] = nd;
+    }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int e = 2 * m + h;
-        bool nd = valid && auxp != nullptr;
-        if constexpr (OP == X_HIN) nd = nd && ch[e] == 0;
-        if constexpr (OP == X_UPDATE) nd = nd && (A.track || ch[e] != 0);
-        if constexpr (OP == X_UPDATE_LAST) nd = nd && A.track;
-        if constexpr (OP == X_ADJ_LAW) nd = nd && ch[e] != 0;     // j is read in Omega only
-        need[h] = nd;
-      }
+    for (int cc = 0; cc < NC; ++cc) {
+      const __amdgpu_buffer_rsrc_t ra = field_rsrc(auxp, cc);
+      const __amdgpu_buffer_rsrc_t r2 =
+          field_rsrc((OP == X_FWD || OP == X_ADJ_START) ? A.in2 : nullptr, cc);
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const size_t ai = (c0 + cc) * csr + rowbase + 2 * (j + m * TPT);
-        T2 v = {T(0), T(0)};
-        if (need[0] || need[1]) {
-          v = *reinterpret_cast<const T2*>(auxp + ai);
-          if constexpr (OP == X_FWD) {
-            if (A.in2) {  // stage argument y + c k
-              const T2 w = *reinterpret_cast<const T2*>(A.in2 + ai);
-              v.x += A.in2_coef * w.x;
-              v.y += A.in2_coef * w.y;
-            }
-          }
-          if constexpr (OP == X_ADJ_START) {  // cotangent of hdot^K: lam + (1-chi) mu
-            if (A.in2) {
-              const T2 w = *reinterpret_cast<const T2*>(A.in2 + ai);
-              if (ch[2 * m] == 0) v.x += w.x;
-              if (ch[2 * m + 1] == 0) v.y += w.y;
-            }
-          }
+      for (int m = 0; m < E; ++m) {
+        const unsigned off = (need[2 * m] || need[2 * m + 1])
+                                 ? (unsigned)((rowbase + 2 * (j + m * TPT)) * sizeof(T))
+                                 : kBufMiss;
+        C2<T> v = buffer_load<T>(ra, off);
+        if constexpr (OP == X_FWD) {  // stage argument y + c k (zero without in2)
+          const C2<T> w = buffer_load<T>(r2, off);
+          v.x += A.in2_coef * w.x;
+          v.y += A.in2_coef * w.y;
         }
-        aux[cc][2 * m] = need[0] ? v.x : T(0);
-        aux[cc][2 * m + 1] = need[1] ? v.y : T(0);
+        if constexpr (OP == X_ADJ_START) {  // cotangent of hdot^K: lam + (1-chi) mu
+          const C2<T> w = buffer_load<T>(r2, off);
+          if (ch[2 * m] == 0) v.x += w.x;
+          if (ch[2 * m + 1] == 0) v.y += w.y;
+        }
+        aux[cc][2 * m] = need[2 * m] ? v.x : T(0);
+        aux[cc][2 * m + 1] = need[2 * m + 1] ? v.y : T(0);
       }
     }
   }
 
-  twd.put(twl);
-  __syncthreads();  // row exchanges are wavefront-local: make the table visible to the block
 
   if constexpr (HAS_INV) {
 #pragma unroll
@@ -638,9 +658,12 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 8 && OP == X_LAW && NC == 3 &
       if constexpr (LAZY) {
         if (c == 1) load_row(2);
       }
+      // the kx = 0 slot holds X[0] + i X[M] (both real)
+      const C2<T> xn = {Xs[c][0].y, T(0)};
+      if (j == 0) Xs[c][0].y = T(0);
 #pragma unroll
       for (int m = 0; m < E; ++m) lds.store(j + m * TPT, Xs[c][m]);
-      if (j == 0) lds.store(M, Xn[c]);
+      if (j == 0) lds.store(M, xn);
       lds.sync();
       C2<T> Z[E];
 #pragma unroll
