@@ -205,7 +205,10 @@ __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-constexpr unsigned kBufMiss = 0x80000000u;  // past every array read through one resource (each < 2 GiB)
+// An offset past every array read through one resource: each resource covers
+// one component (edges up to 512: at most 512^3 FP64 values or 512^2 x 256
+// complex FP64 values, 1 GiB), so sizes and offsets stay below 2^31.
+constexpr unsigned kBufMiss = 0x80000000u;
 template <typename T>
 __device__ __forceinline__ T buffer_load_real(__amdgpu_buffer_rsrc_t r, unsigned off) {
   if constexpr (sizeof(T) == 8)

@@ -6,9 +6,11 @@ column and the fused plane schedules (FP64 <= 1e-10 relative to the largest
 reference value, FP32 <= 1e-4 relative L2), and against the default
 variants at the full 128^3 size (the variants differ only in rounding
 order)."""
+import numpy as np
 import pytest
 
 from gpu_case import oracle_problem, rel_l2, rel_max, sim, small_cfg, state, to_dev
+from oracle import operators
 from oracle import rhs as orhs
 from paper_1803_01346_amd import scfft, workloads
 
@@ -97,3 +99,31 @@ def test_autotune_crosses_the_variants():
     out, _ = s.rhs_eval(0.003, dh)
     torch.cuda.synchronize()
     assert rel_max(_np(out), orhs.rhs_eval(prob, 0.003 / u.t0, h)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("zalt", [0, 1], ids=["default", "alt"])
+@pytest.mark.parametrize("nz", [64, 128, 256, 512])
+def test_z_operators_every_column_shape(nz, zalt, prec):
+    """Curl and Phi (Eq. 4, Eq. 7) with z columns of 64 to 512 nodes in both
+    element counts of the Z pass: every shape its column transform takes
+    (lane-swapped index bits with one, two or no swaps after the exchange, 8
+    or 16 columns per wavefront, or the Stockham passes at 512 nodes with 4
+    elements per lane), on full-band random input, against the oracle."""
+    n = (16, 16, nz)
+    cfg = small_cfg(n, tuple(0.25 * v / 16 for v in n), workloads.shape_cube(0.1))
+    s = sim(cfg, precision=prec, z_alt=zalt)
+    prob, _ = oracle_problem(cfg)
+    dt = torch.float64 if prec == scfft.F64 else torch.float32
+    dv = to_dev(torch, np.random.default_rng(7 + nz).normal(size=s.field_shape), dt)
+    vv = _np(dv)
+    out = s.empty_field()
+    for op, ref in ((scfft.scfft_curl, operators.curl_s), (scfft.scfft_phi, operators.phi)):
+        op(s.ctx, dv, out)
+        torch.cuda.synchronize()
+        want = ref(vv, prob.grid)
+        if prec == scfft.F64:
+            assert rel_max(_np(out), want) < 1e-12, (op.__name__, nz, zalt)
+        else:
+            assert rel_l2(_np(out), want) < 1e-5, (op.__name__, nz, zalt)
+    s.close()
