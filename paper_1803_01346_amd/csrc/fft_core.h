@@ -478,6 +478,7 @@ struct LaneCol {
     for (int m = 0; m < E; ++m) v[m] = buf[(to_b ? pos_b(j, m) : pos_a2(j, m)) * COLS + col];
   }
   __device__ __forceinline__ static void forward(C2<T> (&v)[E], int j, int col, C2<T>* buf, const C2<T>* tw) {
+    static_assert(ok, "shape outside the lane-swapped layout (use the Stockham passes)");
     const int lo2 = ((j & ((1 << (JL - 2)) - 1)) << WB) + (j >> JL);
     step<0, RB, false, true>(v, tw, pos_a(j, 0));
     swap_bit<5, RB - 1>(v);
@@ -490,6 +491,7 @@ struct LaneCol {
     if constexpr (B4 >= 1) step<RB - B4, B4, false, false>(v, tw, 0);
   }
   __device__ __forceinline__ static void inverse(C2<T> (&v)[E], int j, int col, C2<T>* buf, const C2<T>* tw) {
+    static_assert(ok, "shape outside the lane-swapped layout (use the Stockham passes)");
     const int lo2 = ((j & ((1 << (JL - 2)) - 1)) << WB) + (j >> JL);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m].y = -v[m].y;

@@ -21,7 +21,7 @@ long cylinder of the closed form.  The voxel surface carries less than the
 critical current (staircase, smoothing width ~0.9 cell), so the moment
 converges at first order in the cell size; two resolutions (8 and 12 cells
 per radius) give the Richardson extrapolant, compared with the closed form
-to the survey's 3 %.
+within 3 %.
 """
 import numpy as np
 import pytest
