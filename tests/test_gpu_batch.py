@@ -92,6 +92,25 @@ def test_batch_rhs_against_oracle():
         b.close()
 
 
+def test_batch_rhs_against_oracle_128():
+    """Two 128^3 members of the mixed set in one batched call against the
+    oracle (about 15 s per oracle call; the 3 * 2^k edges are compared at 96,
+    where the oracle's transform is affordable: at 192^3 it takes minutes)."""
+    edge, count = 128, 2
+    cfgs = _by_edge(per_edge=count)[edge][:count]
+    hs = _states(cfgs, seed0=30)
+    b = scfft.Batch(cfgs, precision=scfft.F64, rhs_opts=_opts())
+    h = torch.stack([to_dev(torch, x, torch.float64) for x in hs]).contiguous()
+    got = _np(b.rhs_eval(0.2, h))
+    b.close()
+    for i, c in enumerate(cfgs):
+        prob, u = oracle_problem(c, fixed_iter=FIXED)
+        want = orhs.rhs_eval(prob, 0.2 / u.t0, hs[i])
+        err = rel_max(got[i], want)
+        print("batch edge %d instance %d: rel max %.2e" % (edge, i, err))
+        assert err < 1e-10, (edge, i)
+
+
 @pytest.mark.parametrize("prec", [scfft.F64, scfft.F32], ids=["f64", "f32"])
 def test_batch_graph_equals_single_graphs(prec):
     dt = torch.float64 if prec == scfft.F64 else torch.float32
