@@ -171,20 +171,6 @@ __global__ __launch_bounds__((col_block<T, NY, EV ? EV : ey_max<T>()>())) void y
 // ---------------------------------------------------------------------------
 // Z pass: forward z transform of the three components, symbol, inverse.
 // ---------------------------------------------------------------------------
-// multiplier of the symbol at wavevector indices (ix, iy, iz)
-template <typename T, int SYM>
-__device__ __forceinline__ T zsym_factor(const AxisTab<T>& tx, const AxisTab<T>& ty,
-                                         const AxisTab<T>& tz, int ix, int iy, int iz, T coef) {
-  if constexpr (SYM == Z_CURL) {
-    return coef * tx.sm[ix] * ty.sm[iy] * tz.sm[iz];
-  } else {
-    const T k2 = tx.kk[ix] + ty.kk[iy] + tz.kk[iz];
-    T f = k2 > T(0) ? coef / k2 : T(0);
-    if constexpr (SYM == Z_PHI_SMOOTH) f = f * tx.sm[ix] * ty.sm[iy] * tz.sm[iz];
-    return f;
-  }
-}
-
 // i f (k_odd x v) for one wavevector
 template <typename T>
 __device__ __forceinline__ void zsym_apply(C2<T>& a, C2<T>& b, C2<T>& d, T kxo, T kyo, T kzo, T f) {
@@ -282,6 +268,68 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
   }
   const int qa = (ny / 2) * M;                      // the second packed column
   const bool pk_block = q0 == 0 || (q0 <= qa && qa < q0 + COLS);  // uniform per block
+
+  // The symbol's tables go to LDS with the twiddles: the z-axis arrays at
+  // every kz and the x, y values of the block's columns, loaded before the
+  // field loads, so the step between the transforms reads no global memory
+  // (read there, they cost every block a round trip, and the blocks holding
+  // the packed columns one per element).
+  constexpr bool NEED_SM = SYM != Z_PHI, NEED_KK = SYM != Z_CURL;
+  constexpr int NT1 = (NZ + BLOCK - 1) / BLOCK;
+  __shared__ T zt[3 * NZ];     // kodd, sm, kk along z
+  __shared__ T xyt[6 * COLS];  // per column: kodd x, kodd y, sm x, sm y, kk x, kk y
+  T ztr[3][NT1];
+  T xyr[6];
+  {
+    const T* za[3] = {tz.kodd, tz.sm, tz.kk};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if ((a == 1 && !NEED_SM) || (a == 2 && !NEED_KK)) continue;
+      const __amdgpu_buffer_rsrc_t r = buffer_of(za[a], NZ * sizeof(T));
+#pragma unroll
+      for (int k = 0; k < NT1; ++k)
+        ztr[a][k] = buffer_load_real<T>(r, (unsigned)((((int)threadIdx.x + k * BLOCK) % NZ) * sizeof(T)));
+    }
+    // the first COLS threads (j = 0) hold one column each
+    const bool first = (int)threadIdx.x < COLS;
+    const T* xa[6] = {tx.kodd, ty.kodd, tx.sm, ty.sm, tx.kk, ty.kk};
+    const int xi[6] = {kx, ky, kx, ky, kx, ky};
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      if ((a / 2 == 1 && !NEED_SM) || (a / 2 == 2 && !NEED_KK)) continue;
+      const __amdgpu_buffer_rsrc_t r = buffer_of(xa[a], (size_t)((a & 1) ? ny : 2 * M) * sizeof(T));
+      xyr[a] = buffer_load_real<T>(r, first ? (unsigned)(xi[a] * sizeof(T)) : kBufMiss);
+    }
+  }
+  // x values of the packed columns (kx = 0 and the Nyquist plane): uniform
+  const T sx0 = NEED_SM ? tx.sm[0] : T(0), sxm = NEED_SM ? tx.sm[M] : T(0);
+  const T qx0 = NEED_KK ? tx.kk[0] : T(0), qxm = NEED_KK ? tx.kk[M] : T(0);
+  auto put_tables = [&]() {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if ((a == 1 && !NEED_SM) || (a == 2 && !NEED_KK)) continue;
+#pragma unroll
+      for (int k = 0; k < NT1; ++k) zt[a * NZ + (((int)threadIdx.x + k * BLOCK) % NZ)] = ztr[a][k];
+    }
+    if ((int)threadIdx.x < COLS) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        if ((a / 2 == 1 && !NEED_SM) || (a / 2 == 2 && !NEED_KK)) continue;
+        xyt[a * COLS + threadIdx.x] = xyr[a];
+      }
+    }
+  };
+  // multiplier of the symbol from its axis factors (sm, kk per axis)
+  auto zfac = [&](T sxv, T qxv, T syv, T qyv, T szv, T qzv) -> T {
+    if constexpr (SYM == Z_CURL) {
+      return coef * sxv * syv * szv;
+    } else {
+      const T k2 = qxv + qyv + qzv;
+      T f = k2 > T(0) ? coef / k2 : T(0);
+      if constexpr (SYM == Z_PHI_SMOOTH) f = f * sxv * syv * szv;
+      return f;
+    }
+  };
   // z of element m on load and store; kz of element m after the forward transform
   auto zpos = [&](int m) {
     if constexpr (kLane) return LC::pos_a(j, m);
@@ -307,6 +355,7 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
     }
 #pragma unroll
     for (int k = 0; k < (NZ + BLOCK - 1) / BLOCK; ++k) twl[((int)threadIdx.x + k * BLOCK) & (NZ - 1)] = twr[k];
+    put_tables();
     __syncthreads();  // the first step reads twiddles
 #pragma unroll
     for (int c = 0; c < 3; ++c) LC::forward(v[c], j, col, smem + (c & 1) * NZ * COLS, twl);
@@ -320,6 +369,8 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
                                                      : C2<T>{T(0), T(0)};
       }
     twd.put(twl);  // read from the transform's second pass on (block barriers between passes)
+    put_tables();
+    __syncthreads();  // the tables, also where the transform has no exchange
 #pragma unroll
     for (int c = 0; c < 3; ++c) fft_forward<T, NZ, E>(v[c], j, lds, twl, 1);
   }
@@ -334,8 +385,10 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kz = kpos(m);
-      const T f0 = packed ? zsym_factor<T, SYM>(tx, ty, tz, 0, ky, kz, coef) : T(0);
-      const T fm = packed ? zsym_factor<T, SYM>(tx, ty, tz, M, ky, kz, coef) : T(0);
+      const T sy = xyt[3 * COLS + col], qy = xyt[5 * COLS + col];
+      const T sz = zt[NZ + kz], qz = zt[2 * NZ + kz];
+      const T f0 = packed ? zfac(sx0, qx0, sy, qy, sz, qz) : T(0);
+      const T fm = packed ? zfac(sxm, qxm, sy, qy, sz, qz) : T(0);
       fa[m] = T(0.5) * (f0 + fm);
       fb[m] = T(0.5) * (f0 - fm);
     }
@@ -357,25 +410,25 @@ __global__ __launch_bounds__((z_block<T, NZ, EV>()), (sizeof(T) == 8 && EV == 0)
     __syncthreads();
   }
 
-  const T kxo = tx.kodd[kx], kyo = ty.kodd[ky];
+  const T kxo = xyt[col], kyo = xyt[COLS + col];
   T fxy;  // the x, y part of the multiplier (packed columns: already applied)
   if constexpr (SYM == Z_CURL)
-    fxy = coef * tx.sm[kx] * ty.sm[ky];
+    fxy = coef * xyt[2 * COLS + col] * xyt[3 * COLS + col];
   else
-    fxy = tx.kk[kx] + ty.kk[ky];
+    fxy = xyt[4 * COLS + col] + xyt[5 * COLS + col];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = kpos(m);
     T f;
     if constexpr (SYM == Z_CURL) {
-      f = fxy * tz.sm[kz];
+      f = fxy * zt[NZ + kz];
     } else {
-      const T k2 = fxy + tz.kk[kz];
+      const T k2 = fxy + zt[2 * NZ + kz];
       f = k2 > T(0) ? coef / k2 : T(0);
-      if constexpr (SYM == Z_PHI_SMOOTH) f = f * tx.sm[kx] * ty.sm[ky] * tz.sm[kz];
+      if constexpr (SYM == Z_PHI_SMOOTH) f = f * xyt[2 * COLS + col] * xyt[3 * COLS + col] * zt[NZ + kz];
     }
     if (packed) f = T(1);
-    zsym_apply(v[0][m], v[1][m], v[2][m], kxo, kyo, tz.kodd[kz], f);
+    zsym_apply(v[0][m], v[1][m], v[2][m], kxo, kyo, zt[kz], f);
   }
   // each component is stored as soon as its inverse is done, so its stores
   // overlap the inverse transforms of the next ones
