@@ -335,9 +335,9 @@ struct LdsRows {
 //     bits RB-1 and RB-2 (v_permlane32_swap / v_permlane16_swap, a 2 x 2
 //     transpose of two registers across two halves of the lane range);
 //   step 2: those two bits (radix 4);
-//   one LDS exchange: the remaining P2 low bits (held by lane bit 3 and the
-//     wavefront index) move to the top register bits and, where RB < P2,
-//     lane bits 5 and 4;
+//   one LDS exchange: the remaining P2 low bits (held by the wavefront index
+//     and, with 8 columns, lane bit 3) move to the top register bits and,
+//     where RB < P2, lane bits 5 and 4;
 //   step 3: radix 2^B3 over the register bits; where B4 = P2 - B3 > 0, lane
 //     swaps once more and step 4 (radix 2^B4, no twiddles).
 // A step over index bits [s, s + b) of a length-L sub-transform leaves its
